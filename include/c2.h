@@ -1,0 +1,225 @@
+/*
+ * c2.h -- C ABI of libc2.so, Cluster-and-Conquer (C^2) KNN-graph construction
+ * on AMD MI355X (gfx950).
+ *
+ * The method (Giakkoupis, Kermarrec, Ruas, Taiani, "Cluster-and-Conquer: When
+ * Randomness Meets Graph Locality", arXiv 2010.11497) builds an approximate
+ * k-nearest-neighbour graph over users whose profiles are item sets, under
+ * Jaccard similarity, in three steps (Section II-C):
+ *   1. FastRandomHash clustering with t hash functions into b buckets, with
+ *      recursive splitting of clusters larger than N  -> c2_hash_items,
+ *      c2_frh_keys, c2_cluster;
+ *   2. an exact (brute-force) KNN graph inside every cluster -> c2_local_knn;
+ *   3. a merge of each user's t partial lists            -> c2_merge.
+ * c2_build runs the three steps; c2_graph_* capture the batched form of
+ * c2_build in a HIP graph; c2_brute_force computes the exact graph.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named in c2_profiles and every array argument are DEVICE
+ *    pointers unless the comment says "host".  They are owned by the caller;
+ *    the library never frees or retains them.  The library keeps no state
+ *    between calls except a per-thread error string (c2_last_error) and the
+ *    graph objects the caller creates.
+ *  - `stream` is a hipStream_t (passed as void*; NULL = the default stream).
+ *    Work is enqueued on it and the call returns without waiting, except where
+ *    a comment says "synchronous".
+ *  - Argument errors are detected on the host before anything is enqueued and
+ *    returned as a status; nothing is enqueued then.  Profile contents are only
+ *    checked by c2_validate: the other calls assume validated input (on
+ *    invalid input they return unspecified results but read and write only
+ *    inside the buffers the arguments describe).
+ *  - No C++ exception crosses this interface.
+ *
+ * Similarity order (exact; readings of the paper where it is silent)
+ * -------------------------------------------------------------------
+ *  For a user u and candidates v, w with I = |P_u & P_x| and U = |P_u | P_x|:
+ *  v ranks before w iff I_v * U_w > I_w * U_v, or the products are equal and
+ *  v < w.  u is never its own neighbour.  Zero-similarity neighbours are
+ *  kept.  A list with fewer than k candidates is padded with id C2_PAD and
+ *  I = U = 0.  A neighbour that appears in several partial lists is kept once.
+ */
+#ifndef C2_H
+#define C2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t c2_status;
+
+#define C2_OK 0
+#define C2_E_ARG (-1)          /* bad argument (null pointer, size out of range) */
+#define C2_E_PROFILE (-2)      /* profile data invalid (c2_validate only) */
+#define C2_E_WORKSPACE (-3)    /* workspace smaller than c2_workspace_bytes */
+#define C2_E_HIP (-4)          /* a HIP runtime call failed */
+#define C2_E_UNSUPPORTED (-5)  /* sizes outside what this build supports */
+#define C2_E_INCOMPLETE (-6)   /* batched clustering needed more split rounds */
+
+#define C2_PAD 0xFFFFFFFFu     /* padding id in neighbour lists */
+
+/* Limits of this build: n <= 2^31 - 1 users and t*n < 2^32, m <= 131072 items,
+ * nnz < 2^40, every profile shorter than 2^20 items, 1 <= t <= 64,
+ * 1 <= b <= 2^24, cap >= 1, 1 <= k <= 32. */
+
+/* Users and their profiles in CSR form (Section II-A: U, I and P_u).
+ * Row u is indices[indptr[u] .. indptr[u+1]): strictly increasing item ids
+ * < m, at least one item per user. */
+typedef struct c2_profiles {
+    uint32_t n;               /* users */
+    uint32_t m;               /* items */
+    uint64_t nnz;             /* indptr[n] */
+    const int64_t *indptr;    /* device, [n+1], indptr[0] = 0 */
+    const uint32_t *indices;  /* device, [nnz] */
+} c2_profiles;
+
+/* Parameters of the method (Section II-D, II-F, IV-C): t hash functions,
+ * b buckets per function, cap = N (clusters larger than N are split), k
+ * neighbours per user. */
+typedef struct c2_params {
+    uint32_t t, b, cap, k;
+} c2_params;
+
+/* Execution forms of the same arithmetic. */
+#define C2_FORM_PLAIN 0    /* host-driven: cluster tables read back, one launch per stage */
+#define C2_FORM_BATCHED 1  /* device-driven: no host sync, persistent local-KNN launch over
+                              all clusters of all configurations, largest first; capturable */
+
+/* Tile and schedule choices of c2_local_knn (written by the autotuner).  A
+ * NULL pointer or a zero field means the built-in default. */
+typedef struct c2_tuning {
+    uint32_t mfma_min_rows;   /* clusters with at least this many members use the
+                                 int8 MFMA path, smaller ones the bitmap path */
+    uint32_t persistent_wgs;  /* workgroups of the persistent launch (batched form) */
+    uint32_t split_rounds;    /* split rounds enqueued by the batched form */
+    uint32_t reserved;
+} c2_tuning;
+
+/* Workspace queries: which call the size is for. */
+#define C2_OP_VALIDATE 0
+#define C2_OP_CLUSTER 1
+#define C2_OP_LOCAL_KNN 2
+#define C2_OP_BUILD 3
+#define C2_OP_BRUTE_FORCE 4
+
+/* Message for the last non-OK status returned on this thread (host string,
+ * valid until the next call on this thread). */
+const char *c2_last_error(void);
+
+/* Bytes of device workspace the call `op` needs for these sizes (host-only,
+ * no device work).  Returns 0 and sets the error string if the sizes are
+ * unsupported. */
+size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *p, int op);
+
+/* Checks the profiles: indptr[0] = 0, indptr non-decreasing with every row
+ * non-empty, indptr[n] = nnz, items < m and strictly increasing in each row.
+ * Synchronous: returns C2_OK or C2_E_PROFILE.  ws: C2_OP_VALIDATE bytes. */
+c2_status c2_validate(const c2_profiles *P, void *ws, size_t ws_bytes, void *stream);
+
+/* Item hashes (Section II-D; Eq. 3's generative function h_j, one per
+ * configuration): bucket[j*m + i] = h_j(i) in [0, b) for j < t, i < m.
+ * h_j is simple tabulation hashing of the item id's 4 bytes with the random
+ * 64-bit tables tab[j][0..3][0..255] (device, uint64[t][4][256], drawn by the
+ * caller), x = T0[i & 255] ^ T1[(i >> 8) & 255] ^ T2[(i >> 16) & 255] ^
+ * T3[i >> 24], reduced to [0, b) as the high word of the 128-bit product x * b.
+ * (The paper names Jenkins' hash without variant or seeding; this function is
+ * this library's reading.) */
+c2_status c2_hash_items(const uint64_t *tab, uint32_t t, uint32_t b, uint32_t m,
+                        uint32_t *bucket, void *stream);
+
+/* FastRandomHash (Eq. 3): keys[j*n + u] = min_{i in P_u} bucket[j*m + i]. */
+c2_status c2_frh_keys(const c2_profiles *P, const uint32_t *bucket, uint32_t t,
+                      uint32_t *keys, void *stream);
+
+/* Step 1 (Algorithm 1 and the recursive splitting of Section II-D, Fig. 3).
+ * Input: bucket[t][m] from c2_hash_items (or any table of values < b).
+ * Users of configuration j are grouped by H_j(u); a cluster with index eta
+ * holding more than cap users is split by H\eta(u) = min{h_j(i) : i in P_u,
+ * h_j(i) > eta}: users sharing a new value form a new cluster (split again
+ * if it is still larger than cap); users with no value above eta, or alone
+ * with theirs, stay behind and form a final cluster that is never split.
+ * Outputs (device):
+ *   members[t*n]   configuration j's users occupy members[j*n .. j*n+n),
+ *                  grouped by final cluster, ascending inside each cluster;
+ *   cl_off[t*n+1]  cluster c holds members[cl_off[c] .. cl_off[c+1]); only
+ *                  the first (total clusters + 1) entries are written;
+ *   cl_cfg_off[t+1] clusters of configuration j are [cl_cfg_off[j], cl_cfg_off[j+1]).
+ * Cluster order: ascending top-level hash value; a split cluster is replaced
+ * by its sub-clusters in ascending new value (each recursively), followed by
+ * the users that stayed behind.
+ * form: C2_FORM_PLAIN reads the number of clusters still to split after every
+ * round (synchronises the stream once per round); C2_FORM_BATCHED enqueues
+ * tune->split_rounds rounds (default 8) without synchronising and records on
+ * the device whether that was enough (see c2_check_complete).
+ * ws: C2_OP_CLUSTER bytes; also holds the status read by c2_check_complete. */
+c2_status c2_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_params *p,
+                     int form, const c2_tuning *tune, uint32_t *members, uint32_t *cl_off,
+                     uint32_t *cl_cfg_off, void *ws, size_t ws_bytes, void *stream);
+
+/* Synchronous: C2_OK if the last batched c2_cluster / c2_build that used this
+ * workspace split every oversized cluster, C2_E_INCOMPLETE otherwise. */
+c2_status c2_check_complete(const void *ws, void *stream);
+
+/* Step 2 (Section II-F, Algorithm 2, brute-force branch): for every cluster
+ * of any partition given as (members, cl_off, cl_cfg_off) in c2_cluster's
+ * layout (members need not be sorted), and every member u of a
+ * configuration-j cluster C, the k best users of C \ {u}:
+ *   part_id[(u*t + j)*k + r], part_I[(u*t + j)*k + r]  (device, [n][t][k]),
+ * best first, padded with (C2_PAD, 0).  Every (u, j) slot is written exactly
+ * once, so every user must appear once per configuration.
+ * Pairwise intersections are exact integer counts: clusters are staged as
+ * bit rows over their local dictionary (items present at least twice in the
+ * cluster); the int8 MFMA path multiplies the 0/1 rows as a matrix product
+ * with int32 accumulation, the bitmap path uses AND and population count.
+ * form: C2_FORM_PLAIN reads the cluster table back (synchronises once) and
+ * launches one grid over (cluster, row block) pairs in cluster order;
+ * C2_FORM_BATCHED plans on the device and runs one persistent launch that
+ * takes (cluster, row block) pairs largest cluster first.
+ * tune: NULL or c2_tuning.  ws: C2_OP_LOCAL_KNN bytes. */
+c2_status c2_local_knn(const c2_profiles *P, const uint32_t *members, const uint32_t *cl_off,
+                       const uint32_t *cl_cfg_off, const c2_params *p, int form,
+                       const c2_tuning *tune, uint32_t *part_id, uint32_t *part_I,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Step 3 (Section II-G, Algorithm 3): knn(u) = the k best entries of the union
+ * of u's t partial lists (part_* as written by c2_local_knn), each neighbour
+ * once, best first, padded with (C2_PAD, 0, 0).  Outputs (device, [n][k]):
+ * knn_id, knn_I = |P_u & P_v|, knn_U = |P_u | P_v|. */
+c2_status c2_merge(const c2_profiles *P, const uint32_t *part_id, const uint32_t *part_I,
+                   const c2_params *p, uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U,
+                   void *stream);
+
+/* The whole method: c2_hash_items, c2_frh_keys, c2_cluster, c2_local_knn,
+ * c2_merge on the workspace.  tab as in c2_hash_items.  Outputs as c2_merge.
+ * ws: C2_OP_BUILD bytes. */
+c2_status c2_build(const c2_profiles *P, const uint64_t *tab, const c2_params *p, int form,
+                   const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* The exact KNN graph (Section IV-B, brute force): c2_local_knn on one cluster
+ * holding all users.  Outputs as c2_merge.  ws: C2_OP_BRUTE_FORCE bytes. */
+c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uint32_t *knn_I,
+                         uint32_t *knn_U, void *ws, size_t ws_bytes, void *stream);
+
+/* HIP-graph form of c2_build (C2_FORM_BATCHED) on fixed buffers.  Create
+ * runs one plain clustering synchronously to learn how many split rounds the
+ * data needs, then captures the batched build with that many rounds (plus
+ * one) on `stream`.  Launch replays it (asynchronous); after it, the result is
+ * valid if c2_check_complete(ws) is C2_OK (data changed in place may need
+ * more rounds).  Destroy releases the graph (host handle). */
+typedef struct c2_graph c2_graph;
+c2_status c2_graph_create(const c2_profiles *P, const uint64_t *tab, const c2_params *p,
+                          const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I,
+                          uint32_t *knn_U, void *ws, size_t ws_bytes, void *stream,
+                          c2_graph **out);
+c2_status c2_graph_launch(c2_graph *g, void *stream);
+c2_status c2_graph_destroy(c2_graph *g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* C2_H */

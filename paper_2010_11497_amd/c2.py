@@ -1,0 +1,276 @@
+"""Python binding of libc2.so (include/c2.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors) and the stream (torch's
+current stream).  If libc2.so is missing or fails to load, every call raises;
+there is no fallback.
+
+All array arguments are torch tensors on the GPU with the dtype and shape the
+C declarations state; outputs are allocated here unless passed in.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libc2.so")
+
+C2_OK = 0
+C2_PAD = 0xFFFFFFFF
+FORM_PLAIN = 0
+FORM_BATCHED = 1
+OP_VALIDATE, OP_CLUSTER, OP_LOCAL_KNN, OP_BUILD, OP_BRUTE_FORCE = range(5)
+
+# every entry point of include/c2.h
+SYMBOLS = ["c2_last_error", "c2_workspace_bytes", "c2_validate", "c2_hash_items", "c2_frh_keys",
+           "c2_cluster", "c2_check_complete", "c2_local_knn", "c2_merge", "c2_build",
+           "c2_brute_force", "c2_graph_create", "c2_graph_launch", "c2_graph_destroy"]
+
+
+class C2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("c2 status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Profiles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint32), ("nnz", ctypes.c_uint64),
+                ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_uint32), ("b", ctypes.c_uint32), ("cap", ctypes.c_uint32),
+                ("k", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("mfma_min_rows", ctypes.c_uint32), ("persistent_wgs", ctypes.c_uint32),
+                ("split_rounds", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libc2.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError("libc2.so is not built (%s); run python -m "
+                                "paper_2010_11497_amd.build" % path)
+    L = ctypes.CDLL(path)
+    P, u32, u64, i32, sz = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                            ctypes.c_size_t)
+    PP, PA, PT = ctypes.POINTER(Profiles), ctypes.POINTER(Params), ctypes.POINTER(Tuning)
+    L.c2_last_error.restype = ctypes.c_char_p
+    L.c2_workspace_bytes.argtypes = [u32, u32, u64, PA, i32]
+    L.c2_workspace_bytes.restype = sz
+    L.c2_validate.argtypes = [PP, P, sz, P]
+    L.c2_hash_items.argtypes = [P, u32, u32, u32, P, P]
+    L.c2_frh_keys.argtypes = [PP, P, u32, P, P]
+    L.c2_cluster.argtypes = [PP, P, PA, i32, PT, P, P, P, P, sz, P]
+    L.c2_check_complete.argtypes = [P, P]
+    L.c2_local_knn.argtypes = [PP, P, P, P, PA, i32, PT, P, P, P, sz, P]
+    L.c2_merge.argtypes = [PP, P, P, PA, P, P, P, P]
+    L.c2_build.argtypes = [PP, P, PA, i32, PT, P, P, P, P, sz, P]
+    L.c2_brute_force.argtypes = [PP, u32, P, P, P, P, sz, P]
+    L.c2_graph_create.argtypes = [PP, P, PA, PT, P, P, P, P, sz, P, ctypes.POINTER(P)]
+    L.c2_graph_launch.argtypes = [P, P]
+    L.c2_graph_destroy.argtypes = [P]
+    for name in SYMBOLS:
+        if name not in ("c2_last_error", "c2_workspace_bytes"):
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != C2_OK:
+        raise C2Error(st, load().c2_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _u32(shape, device):
+    return torch.empty(shape, dtype=torch.int32, device=device)
+
+
+class DeviceProfiles:
+    """CSR profiles resident on the GPU (indptr int64[n+1], indices int32 view of
+    uint32[nnz])."""
+
+    def __init__(self, indptr, indices, n: int, m: int, device="cuda"):
+        import numpy as np
+        self.n, self.m = int(n), int(m)
+        self.indptr = torch.as_tensor(np.asarray(indptr, dtype=np.int64)).to(device)
+        self.indices = torch.as_tensor(np.asarray(indices, dtype=np.uint32).view(np.int32)).to(device)
+        self.nnz = int(self.indices.numel())
+        self.device = self.indptr.device
+        self.c = Profiles(self.n, self.m, self.nnz, self.indptr.data_ptr(),
+                          self.indices.data_ptr() if self.nnz else 0)
+
+    @classmethod
+    def from_synth(cls, P, device="cuda"):
+        return cls(P.indptr, P.indices, P.n, P.m, device)
+
+
+def params(t, b, cap, k) -> Params:
+    return Params(int(t), int(b), int(cap), int(k))
+
+
+def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0) -> Tuning:
+    return Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), 0)
+
+
+def workspace_bytes(P: DeviceProfiles, p: Optional[Params], op: int) -> int:
+    L = load()
+    nb = L.c2_workspace_bytes(P.n, P.m, P.nnz, ctypes.byref(p) if p is not None else None, op)
+    if nb == 0:
+        raise C2Error(-1, L.c2_last_error().decode())
+    return int(nb)
+
+
+def workspace(P: DeviceProfiles, p: Optional[Params], op: int) -> torch.Tensor:
+    return torch.empty(workspace_bytes(P, p, op), dtype=torch.uint8, device=P.device)
+
+
+def validate(P: DeviceProfiles, ws: Optional[torch.Tensor] = None) -> None:
+    ws = workspace(P, None, OP_VALIDATE) if ws is None else ws
+    _check(load().c2_validate(ctypes.byref(P.c), _ptr(ws), ws.numel(), _stream()))
+
+
+def hash_items(tab: torch.Tensor, b: int, m: int, out=None) -> torch.Tensor:
+    """tab: int64 view of uint64[t][4][256] on the GPU; returns int32 view of
+    uint32[t][m]."""
+    t = tab.shape[0]
+    out = _u32((t, m), tab.device) if out is None else out
+    _check(load().c2_hash_items(_ptr(tab), t, int(b), int(m), _ptr(out), _stream()))
+    return out
+
+
+def frh_keys(P: DeviceProfiles, bucket: torch.Tensor, out=None) -> torch.Tensor:
+    t = bucket.shape[0]
+    out = _u32((t, P.n), P.device) if out is None else out
+    _check(load().c2_frh_keys(ctypes.byref(P.c), _ptr(bucket), t, _ptr(out), _stream()))
+    return out
+
+
+def cluster(P: DeviceProfiles, bucket: torch.Tensor, p: Params, form=FORM_PLAIN,
+            tune: Optional[Tuning] = None, ws=None):
+    """Returns (members int32[t*n], cl_off int32[t*n+1] (first ncl+1 valid),
+    cl_cfg_off int32[t+1])."""
+    NE = p.t * P.n
+    members, cl_off, cfg = _u32(NE, P.device), _u32(NE + 1, P.device), _u32(p.t + 1, P.device)
+    ws = workspace(P, p, OP_CLUSTER) if ws is None else ws
+    _check(load().c2_cluster(ctypes.byref(P.c), _ptr(bucket), ctypes.byref(p), form,
+                             ctypes.byref(tune) if tune else None, _ptr(members), _ptr(cl_off),
+                             _ptr(cfg), _ptr(ws), ws.numel(), _stream()))
+    return members, cl_off, cfg, ws
+
+
+def check_complete(ws: torch.Tensor) -> None:
+    _check(load().c2_check_complete(_ptr(ws), _stream()))
+
+
+def local_knn(P: DeviceProfiles, members, cl_off, cl_cfg_off, p: Params, form=FORM_PLAIN,
+              tune: Optional[Tuning] = None, ws=None, out=None):
+    """Returns (part_id, part_I), int32 views of uint32[n][t][k]."""
+    if out is None:
+        out = (_u32((P.n, p.t, p.k), P.device), _u32((P.n, p.t, p.k), P.device))
+    ws = workspace(P, p, OP_LOCAL_KNN) if ws is None else ws
+    _check(load().c2_local_knn(ctypes.byref(P.c), _ptr(members), _ptr(cl_off), _ptr(cl_cfg_off),
+                               ctypes.byref(p), form, ctypes.byref(tune) if tune else None,
+                               _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def merge(P: DeviceProfiles, part_id, part_I, p: Params, out=None):
+    """Returns (knn_id, knn_I, knn_U), int32 views of uint32[n][k]."""
+    if out is None:
+        out = tuple(_u32((P.n, p.k), P.device) for _ in range(3))
+    _check(load().c2_merge(ctypes.byref(P.c), _ptr(part_id), _ptr(part_I), ctypes.byref(p),
+                           _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream()))
+    return out
+
+
+def build(P: DeviceProfiles, tab: torch.Tensor, p: Params, form=FORM_PLAIN,
+          tune: Optional[Tuning] = None, ws=None, out=None):
+    if out is None:
+        out = tuple(_u32((P.n, p.k), P.device) for _ in range(3))
+    ws = workspace(P, p, OP_BUILD) if ws is None else ws
+    _check(load().c2_build(ctypes.byref(P.c), _ptr(tab), ctypes.byref(p), form,
+                           ctypes.byref(tune) if tune else None, _ptr(out[0]), _ptr(out[1]),
+                           _ptr(out[2]), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def brute_force(P: DeviceProfiles, k: int, ws=None, out=None):
+    if out is None:
+        out = tuple(_u32((P.n, k), P.device) for _ in range(3))
+    p = params(1, 1, 1, k)
+    ws = workspace(P, p, OP_BRUTE_FORCE) if ws is None else ws
+    _check(load().c2_brute_force(ctypes.byref(P.c), int(k), _ptr(out[0]), _ptr(out[1]),
+                                 _ptr(out[2]), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+class Graph:
+    """The batched build captured as a HIP graph on fixed buffers."""
+
+    def __init__(self, P: DeviceProfiles, tab: torch.Tensor, p: Params,
+                 tune: Optional[Tuning] = None):
+        self.P, self.tab, self.p = P, tab, p
+        self.out = tuple(_u32((P.n, p.k), P.device) for _ in range(3))
+        self.ws = workspace(P, p, OP_BUILD)
+        h = ctypes.c_void_p()
+        _check(load().c2_graph_create(ctypes.byref(P.c), _ptr(tab), ctypes.byref(p),
+                                      ctypes.byref(tune) if tune else None, _ptr(self.out[0]),
+                                      _ptr(self.out[1]), _ptr(self.out[2]), _ptr(self.ws),
+                                      self.ws.numel(), _stream(), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self):
+        _check(load().c2_graph_launch(self.h, _stream()))
+        return self.out
+
+    def check(self):
+        check_complete(self.ws)
+
+    def close(self):
+        if self.h:
+            load().c2_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_u32(t: torch.Tensor):
+    """Copy a device int32 view back as a numpy uint32 array."""
+    return t.cpu().numpy().view("uint32")
+
+
+def tables_to_device(tab, device="cuda") -> torch.Tensor:
+    import numpy as np
+    return torch.as_tensor(np.ascontiguousarray(tab, dtype=np.uint64).view(np.int64)).to(device)

@@ -1,0 +1,504 @@
+// C ABI of libc2.so: argument checks, workspace carving and the host-side
+// orchestration of the kernels.  Declarations and contracts: include/c2.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/c2.h"
+#include "c2_internal.h"
+#include "c2_kernels.h"
+
+using namespace c2;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+c2_status fail(c2_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+c2_status hip_fail(hipError_t e, const char *where) {
+    return fail(C2_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define C2_TRY(expr, where)                                    \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail(e_, where);      \
+    } while (0)
+
+constexpr size_t kHeader = 256;  // status word(s) at the start of every workspace
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+c2_status check_sizes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *p, bool need_p) {
+    if (n == 0 || n > 0x7FFFFFFFu) return fail(C2_E_ARG, "n = %u out of range [1, 2^31)", n);
+    if (m == 0) return fail(C2_E_ARG, "m must be >= 1");
+    if (m > kMaxItems) return fail(C2_E_UNSUPPORTED, "m = %u > %u items", m, kMaxItems);
+    if (nnz >= (1ull << 40)) return fail(C2_E_UNSUPPORTED, "nnz too large");
+    if (!need_p) return C2_OK;
+    if (!p) return fail(C2_E_ARG, "params is NULL");
+    if (p->t < 1 || p->t > 64) return fail(C2_E_ARG, "t = %u out of range [1, 64]", p->t);
+    if (p->b < 1 || p->b > (1u << 24)) return fail(C2_E_ARG, "b = %u out of range [1, 2^24]", p->b);
+    if (p->cap < 1) return fail(C2_E_ARG, "cap must be >= 1");
+    if (p->k < 1 || p->k > kMaxK) return fail(C2_E_ARG, "k = %u out of range [1, %u]", p->k, kMaxK);
+    if ((uint64_t)p->t * n >= 0xFFFFFFFFull) return fail(C2_E_UNSUPPORTED, "t*n >= 2^32");
+    return C2_OK;
+}
+
+c2_status check_profiles(const c2_profiles *P) {
+    if (!P) return fail(C2_E_ARG, "profiles is NULL");
+    if (!P->indptr || (!P->indices && P->nnz)) return fail(C2_E_ARG, "profile pointers are NULL");
+    return C2_OK;
+}
+
+ClusterDims cdims(uint32_t n, const c2_params *p) {
+    ClusterDims d;
+    d.NE = (size_t)p->t * n;
+    size_t np = d.NE / ((size_t)p->cap + 1);
+    d.NP = (np > p->t ? np : p->t) + 1;
+    return d;
+}
+
+struct BuildLayout {
+    size_t bucket, members, cl_off, cl_cfg, part_id, part_I, scratch, total;
+};
+
+BuildLayout build_layout(uint32_t n, uint32_t m, const c2_params *p) {
+    BuildLayout L;
+    size_t off = kHeader;
+    auto take = [&](size_t b) { size_t o = off; off += al(b); return o; };
+    const size_t NE = (size_t)p->t * n;
+    L.bucket = take(4 * (size_t)p->t * m);
+    L.members = take(4 * NE);
+    L.cl_off = take(4 * (NE + 1));
+    L.cl_cfg = take(4 * ((size_t)p->t + 1));
+    L.part_id = take(4 * NE * p->k);
+    L.part_I = take(4 * NE * p->k);
+    L.scratch = off;
+    const size_t cw = cluster_ws_elems(cdims(n, p), nullptr);
+    const size_t kw = knn_ws_bytes((uint32_t)NE, knn_wmax(m), nullptr);
+    L.total = off + (cw > kw ? cw : kw);
+    return L;
+}
+
+ClusterPtrs cluster_ptrs(char *base, const ClusterWs &w, uint32_t *members, uint32_t *status) {
+    ClusterPtrs c;
+    auto u32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
+    auto u64 = [&](size_t o) { return reinterpret_cast<uint64_t *>(base + o); };
+    c.E_uid = members;
+    c.E_seg = u32(w.E_seg);
+    c.S_state = u32(w.S_state);
+    c.S_eta1 = u32(w.S_eta1);
+    c.S_len = u32(w.S_len);
+    c.mark = u64(w.mark);
+    c.mtmp = u64(w.mtmp);
+    c.A_uid = u32(w.A_uid);
+    c.A_rank = u32(w.A_rank);
+    c.P_start = u32(w.P_start);
+    c.P_len = u32(w.P_len);
+    c.P_state = u32(w.P_state);
+    c.P_q0 = u32(w.P_q0);
+    c.key = u64(w.key);
+    c.key_alt = u64(w.key_alt);
+    c.val = u32(w.val);
+    c.val_alt = u32(w.val_alt);
+    c.hist = u32(w.hist);
+    c.htmp = u32(w.htmp);
+    c.glb = u32(w.glb);
+    c.glen = u32(w.glen);
+    c.flg = u64(w.flg);
+    c.ftmp = u64(w.ftmp);
+    c.keys0 = u32(w.keys0);
+    c.ctr = u32(w.ctr);
+    c.status = status;
+    return c;
+}
+
+KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
+    KnnPtrs k;
+    auto u32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
+    auto u64 = [&](size_t o) { return reinterpret_cast<uint64_t *>(base + o); };
+    k.rows = u32(w.rows);
+    k.rlen = u32(w.rlen);
+    k.cl_W = u32(w.cl_W);
+    k.nrb = u32(w.nrb);
+    k.item_off = u32(w.item_off);
+    k.items = u64(w.items);
+    k.csort_key = u64(w.csort_key);
+    k.csort_key_alt = u64(w.csort_key_alt);
+    k.csort_val = u32(w.csort_val);
+    k.csort_val_alt = u32(w.csort_val_alt);
+    k.hist = u32(w.hist);
+    k.htmp = u32(w.htmp);
+    k.ctr = u32(w.ctr);
+    return k;
+}
+
+uint32_t rounds_from(const c2_tuning *tune) {
+    uint32_t r = tune && tune->split_rounds ? tune->split_rounds : 8;
+    return r > kMaxRounds ? kMaxRounds : r;
+}
+
+// Clustering on an explicit scratch region (clusters of `ws` header status).
+c2_status run_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_params *p, int form,
+                      uint32_t rounds_batched, uint32_t *members, uint32_t *cl_off,
+                      uint32_t *cl_cfg_off, char *scratch, uint32_t *status, hipStream_t s,
+                      uint32_t *rounds_used) {
+    ClusterWs w;
+    const ClusterDims d = cdims(P->n, p);
+    cluster_ws_elems(d, &w);
+    const ClusterPtrs c = cluster_ptrs(scratch, w, members, status);
+    ClusterArgs a;
+    a.indptr = P->indptr;
+    a.indices = P->indices;
+    a.nnz = P->nnz;
+    a.n = P->n;
+    a.m = P->m;
+    a.t = p->t;
+    a.b = p->b;
+    a.bb = bit_width(p->b);
+    a.cap = p->cap;
+    a.bucket = bucket;
+    a.NE = (uint32_t)d.NE;
+    a.NP = (uint32_t)d.NP;
+    C2_TRY(cluster_init(a, c, s), "cluster init");
+    uint32_t r = 0;
+    if (form == C2_FORM_PLAIN) {
+        for (;; ++r) {
+            if (r >= kMaxRounds) return fail(C2_E_UNSUPPORTED, "more than %u split rounds", kMaxRounds);
+            C2_TRY(cluster_round(a, c, r, s), "cluster round");
+            uint32_t more = 0;
+            C2_TRY(hipMemcpyAsync(&more, c.ctr + 1 + r, 4, hipMemcpyDeviceToHost, s), "copy");
+            C2_TRY(hipStreamSynchronize(s), "sync");
+            if (!more) { ++r; break; }
+        }
+        C2_TRY(cluster_finish(a, c, 0, cl_off, cl_cfg_off, s), "cluster finish");
+    } else {
+        for (r = 0; r < rounds_batched; ++r) C2_TRY(cluster_round(a, c, r, s), "cluster round");
+        C2_TRY(cluster_finish(a, c, rounds_batched, cl_off, cl_cfg_off, s), "cluster finish");
+    }
+    if (rounds_used) *rounds_used = r;
+    return C2_OK;
+}
+
+c2_status run_knn(const c2_profiles *P, const uint32_t *members, const uint32_t *cl_off,
+                  const uint32_t *cl_cfg_off, uint32_t t, uint32_t k, int form,
+                  const c2_tuning *tune, uint32_t *part_id, uint32_t *part_I, char *scratch,
+                  hipStream_t s) {
+    KnnWs w;
+    const uint32_t NE = t * P->n;
+    const uint32_t wmax = knn_wmax(P->m);
+    knn_ws_bytes(NE, wmax, &w);
+    KnnArgs a;
+    a.indptr = P->indptr;
+    a.indices = P->indices;
+    a.nnz = P->nnz;
+    a.n = P->n;
+    a.m = P->m;
+    a.t = t;
+    a.k = k;
+    a.members = members;
+    a.cl_off = cl_off;
+    a.cl_cfg_off = cl_cfg_off;
+    a.NE = NE;
+    a.wmax = wmax;
+    a.part_id = part_id;
+    a.part_I = part_I;
+    const KnnPtrs kp = knn_ptrs(scratch, w);
+    if (form == C2_FORM_PLAIN) C2_TRY(knn_plain(a, kp, s), "local knn");
+    else C2_TRY(knn_batched(a, kp, tune ? tune->persistent_wgs : 0, s), "local knn");
+    return C2_OK;
+}
+
+c2_status check_ws(void *ws, size_t have, size_t need) {
+    if (!ws) return fail(C2_E_ARG, "workspace is NULL");
+    if (have < need) return fail(C2_E_WORKSPACE, "workspace %zu bytes < %zu needed", have, need);
+    return C2_OK;
+}
+
+c2_status check_form(int form) {
+    if (form != C2_FORM_PLAIN && form != C2_FORM_BATCHED) return fail(C2_E_ARG, "bad form %d", form);
+    return C2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *c2_last_error(void) { return g_err; }
+
+size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *p, int op) {
+    c2_params one = {1, 1, 1, 1};
+    switch (op) {
+    case C2_OP_VALIDATE:
+        if (check_sizes(n, m, nnz, nullptr, false) != C2_OK) return 0;
+        return kHeader;
+    case C2_OP_CLUSTER:
+        if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
+        return kHeader + cluster_ws_elems(cdims(n, p), nullptr);
+    case C2_OP_LOCAL_KNN:
+        if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
+        return kHeader + knn_ws_bytes(p->t * n, knn_wmax(m), nullptr);
+    case C2_OP_BUILD:
+        if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
+        return build_layout(n, m, p).total;
+    case C2_OP_BRUTE_FORCE: {
+        one.k = p ? p->k : 1;
+        if (check_sizes(n, m, nnz, &one, true) != C2_OK) return 0;
+        const size_t head = kHeader + al(4 * (size_t)n) + al(4 * ((size_t)n + 1)) + al(8) +
+                            2 * al(4 * (size_t)n * one.k);
+        return head + knn_ws_bytes(n, knn_wmax(m), nullptr);
+    }
+    default:
+        fail(C2_E_ARG, "unknown op %d", op);
+        return 0;
+    }
+}
+
+c2_status c2_validate(const c2_profiles *P, void *ws, size_t ws_bytes, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, nullptr, false)) != C2_OK) return st;
+    if ((st = check_ws(ws, ws_bytes, kHeader)) != C2_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *err = reinterpret_cast<uint32_t *>(ws);
+    C2_TRY(launch_fill_u32(err, 0, 1, s), "validate");
+    C2_TRY(launch_validate(P->indptr, P->indices, P->nnz, P->n, P->m, err, s), "validate");
+    uint32_t h = 0;
+    C2_TRY(hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, s), "validate copy");
+    C2_TRY(hipStreamSynchronize(s), "validate sync");
+    if (h) {
+        return fail(C2_E_PROFILE, "invalid profiles:%s%s%s%s", (h & 1) ? " indptr ends" : "",
+                    (h & 2) ? " empty row" : "", (h & 4) ? " item >= m" : "",
+                    (h & 8) ? " items not strictly increasing" : "");
+    }
+    return C2_OK;
+}
+
+c2_status c2_hash_items(const uint64_t *tab, uint32_t t, uint32_t b, uint32_t m, uint32_t *bucket,
+                        void *stream) {
+    if (!tab || !bucket) return fail(C2_E_ARG, "NULL pointer");
+    if (t < 1 || t > 64 || b < 1 || m < 1) return fail(C2_E_ARG, "bad t/b/m");
+    C2_TRY(launch_hash_items(tab, t, b, m, bucket, (hipStream_t)stream), "hash items");
+    return C2_OK;
+}
+
+c2_status c2_frh_keys(const c2_profiles *P, const uint32_t *bucket, uint32_t t, uint32_t *keys,
+                      void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, nullptr, false)) != C2_OK) return st;
+    if (!bucket || !keys) return fail(C2_E_ARG, "NULL pointer");
+    if (t < 1 || t > 64) return fail(C2_E_ARG, "bad t");
+    C2_TRY(launch_frh_keys(P->indptr, P->indices, P->nnz, P->n, P->m, bucket, t, 0xFFFFFFFFu, keys,
+                           (hipStream_t)stream),
+           "frh keys");
+    return C2_OK;
+}
+
+c2_status c2_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_params *p, int form,
+                     const c2_tuning *tune, uint32_t *members, uint32_t *cl_off,
+                     uint32_t *cl_cfg_off, void *ws, size_t ws_bytes, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
+    if ((st = check_form(form)) != C2_OK) return st;
+    if (!bucket || !members || !cl_off || !cl_cfg_off) return fail(C2_E_ARG, "NULL pointer");
+    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_CLUSTER))) != C2_OK)
+        return st;
+    char *base = reinterpret_cast<char *>(ws);
+    return run_cluster(P, bucket, p, form, rounds_from(tune), members, cl_off, cl_cfg_off,
+                       base + kHeader, reinterpret_cast<uint32_t *>(base), (hipStream_t)stream,
+                       nullptr);
+}
+
+c2_status c2_check_complete(const void *ws, void *stream) {
+    if (!ws) return fail(C2_E_ARG, "workspace is NULL");
+    uint32_t h = 0;
+    hipStream_t s = (hipStream_t)stream;
+    C2_TRY(hipMemcpyAsync(&h, ws, 4, hipMemcpyDeviceToHost, s), "status copy");
+    C2_TRY(hipStreamSynchronize(s), "status sync");
+    if (h) return fail(C2_E_INCOMPLETE, "batched clustering needs more split rounds");
+    return C2_OK;
+}
+
+c2_status c2_local_knn(const c2_profiles *P, const uint32_t *members, const uint32_t *cl_off,
+                       const uint32_t *cl_cfg_off, const c2_params *p, int form,
+                       const c2_tuning *tune, uint32_t *part_id, uint32_t *part_I, void *ws,
+                       size_t ws_bytes, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
+    if ((st = check_form(form)) != C2_OK) return st;
+    if (!members || !cl_off || !cl_cfg_off || !part_id || !part_I) return fail(C2_E_ARG, "NULL pointer");
+    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_LOCAL_KNN))) != C2_OK)
+        return st;
+    return run_knn(P, members, cl_off, cl_cfg_off, p->t, p->k, form, tune, part_id, part_I,
+                   reinterpret_cast<char *>(ws) + kHeader, (hipStream_t)stream);
+}
+
+c2_status c2_merge(const c2_profiles *P, const uint32_t *part_id, const uint32_t *part_I,
+                   const c2_params *p, uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U,
+                   void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
+    if (!part_id || !part_I || !knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
+    C2_TRY(launch_merge(P->indptr, P->nnz, P->n, p->t, p->k, part_id, part_I, knn_id, knn_I, knn_U,
+                        (hipStream_t)stream),
+           "merge");
+    return C2_OK;
+}
+
+static c2_status build_impl(const c2_profiles *P, const uint64_t *tab, const c2_params *p,
+                            int form, const c2_tuning *tune, uint32_t rounds_batched,
+                            uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U, char *base,
+                            hipStream_t s, uint32_t *rounds_used) {
+    const BuildLayout L = build_layout(P->n, P->m, p);
+    uint32_t *bucket = reinterpret_cast<uint32_t *>(base + L.bucket);
+    uint32_t *members = reinterpret_cast<uint32_t *>(base + L.members);
+    uint32_t *cl_off = reinterpret_cast<uint32_t *>(base + L.cl_off);
+    uint32_t *cl_cfg = reinterpret_cast<uint32_t *>(base + L.cl_cfg);
+    uint32_t *pid = reinterpret_cast<uint32_t *>(base + L.part_id);
+    uint32_t *pI = reinterpret_cast<uint32_t *>(base + L.part_I);
+    C2_TRY(launch_hash_items(tab, p->t, p->b, P->m, bucket, s), "hash items");
+    c2_status st = run_cluster(P, bucket, p, form, rounds_batched, members, cl_off, cl_cfg,
+                               base + L.scratch, reinterpret_cast<uint32_t *>(base), s,
+                               rounds_used);
+    if (st != C2_OK) return st;
+    st = run_knn(P, members, cl_off, cl_cfg, p->t, p->k, form, tune, pid, pI, base + L.scratch, s);
+    if (st != C2_OK) return st;
+    C2_TRY(launch_merge(P->indptr, P->nnz, P->n, p->t, p->k, pid, pI, knn_id, knn_I, knn_U, s),
+           "merge");
+    return C2_OK;
+}
+
+c2_status c2_build(const c2_profiles *P, const uint64_t *tab, const c2_params *p, int form,
+                   const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U,
+                   void *ws, size_t ws_bytes, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
+    if ((st = check_form(form)) != C2_OK) return st;
+    if (!tab || !knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
+    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_BUILD))) != C2_OK)
+        return st;
+    return build_impl(P, tab, p, form, tune, rounds_from(tune), knn_id, knn_I, knn_U,
+                      reinterpret_cast<char *>(ws), (hipStream_t)stream, nullptr);
+}
+
+c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uint32_t *knn_I,
+                         uint32_t *knn_U, void *ws, size_t ws_bytes, void *stream) {
+    c2_status st;
+    c2_params one = {1, 1, 1, k};
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, &one, true)) != C2_OK) return st;
+    if (!knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
+    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, &one, C2_OP_BRUTE_FORCE))) != C2_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = reinterpret_cast<char *>(ws);
+    size_t off = kHeader;
+    uint32_t *members = reinterpret_cast<uint32_t *>(base + off);
+    off += al(4 * (size_t)P->n);
+    uint32_t *cl_off = reinterpret_cast<uint32_t *>(base + off);
+    off += al(4 * ((size_t)P->n + 1));
+    uint32_t *cl_cfg = reinterpret_cast<uint32_t *>(base + off);
+    off += al(8);
+    uint32_t *pid = reinterpret_cast<uint32_t *>(base + off);
+    off += al(4 * (size_t)P->n * k);
+    uint32_t *pI = reinterpret_cast<uint32_t *>(base + off);
+    off += al(4 * (size_t)P->n * k);
+    // one cluster holding every user: members = 0..n-1, cl_off = {0, n}, cl_cfg = {0, 1}
+    C2_TRY(launch_iota(members, P->n, s), "brute force setup");
+    C2_TRY(launch_fill_u32(cl_off, 0, 1, s), "brute force setup");
+    C2_TRY(launch_fill_u32(cl_off + 1, P->n, 1, s), "brute force setup");
+    C2_TRY(launch_fill_u32(cl_cfg, 0, 1, s), "brute force setup");
+    C2_TRY(launch_fill_u32(cl_cfg + 1, 1, 1, s), "brute force setup");
+    st = run_knn(P, members, cl_off, cl_cfg, 1, k, C2_FORM_BATCHED, nullptr, pid, pI, base + off, s);
+    if (st != C2_OK) return st;
+    C2_TRY(launch_merge(P->indptr, P->nnz, P->n, 1, k, pid, pI, knn_id, knn_I, knn_U, s), "merge");
+    return C2_OK;
+}
+
+struct c2_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint32_t rounds;
+};
+
+c2_status c2_graph_create(const c2_profiles *P, const uint64_t *tab, const c2_params *p,
+                          const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I,
+                          uint32_t *knn_U, void *ws, size_t ws_bytes, void *stream,
+                          c2_graph **out) {
+    c2_status st;
+    if (!out) return fail(C2_E_ARG, "out is NULL");
+    *out = nullptr;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
+    if (!tab || !knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
+    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_BUILD))) != C2_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = reinterpret_cast<char *>(ws);
+    // plain build once: learns the number of split rounds and loads the kernels
+    uint32_t rounds = 0;
+    st = build_impl(P, tab, p, C2_FORM_PLAIN, tune, 0, knn_id, knn_I, knn_U, base, s, &rounds);
+    if (st != C2_OK) return st;
+    C2_TRY(hipStreamSynchronize(s), "graph warm-up");
+    hipStream_t cap;
+    C2_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+    c2_graph *g = new (std::nothrow) c2_graph;
+    if (!g) { hipStreamDestroy(cap); return fail(C2_E_ARG, "out of host memory"); }
+    g->rounds = rounds + 1;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = build_impl(P, tab, p, C2_FORM_BATCHED, tune, g->rounds, knn_id, knn_I, knn_U, base,
+                        cap, nullptr);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (st == C2_OK && e2 != hipSuccess) st = hip_fail(e2, "end capture");
+        if (st == C2_OK) {
+            g->graph = graph;
+            e2 = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            if (e2 != hipSuccess) st = hip_fail(e2, "graph instantiate");
+        } else if (graph) {
+            hipGraphDestroy(graph);
+            graph = nullptr;
+        }
+        if (st != C2_OK && graph) hipGraphDestroy(graph);
+    } else {
+        st = hip_fail(e, "begin capture");
+    }
+    hipStreamDestroy(cap);
+    if (st != C2_OK) {
+        delete g;
+        return st;
+    }
+    *out = g;
+    return C2_OK;
+}
+
+c2_status c2_graph_launch(c2_graph *g, void *stream) {
+    if (!g) return fail(C2_E_ARG, "graph is NULL");
+    C2_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+    return C2_OK;
+}
+
+c2_status c2_graph_destroy(c2_graph *g) {
+    if (!g) return C2_OK;
+    hipGraphExecDestroy(g->exec);
+    hipGraphDestroy(g->graph);
+    delete g;
+    return C2_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Launchers and workspace descriptors shared by the host-side API.
+#pragma once
+
+#include "c2_internal.h"
+
+namespace c2 {
+
+constexpr uint32_t kMaxRounds = 4096;
+
+// ---- hashing / validation
+hipError_t launch_hash_items(const uint64_t *tab, uint32_t t, uint32_t b, uint32_t m,
+                             uint32_t *bucket, hipStream_t s);
+hipError_t launch_frh_keys(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                           uint32_t n, uint32_t m, const uint32_t *bucket, uint32_t t, uint32_t b,
+                           uint32_t *keys, hipStream_t s);
+hipError_t launch_validate(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                           uint32_t n, uint32_t m, uint32_t *err, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t s);
+hipError_t launch_iota(uint32_t *p, uint32_t n, hipStream_t s);
+
+// ---- clustering
+struct ClusterDims {
+    size_t NE;  // t*n slots
+    size_t NP;  // most segments that can be split in one round
+};
+struct ClusterWs {  // byte offsets inside the clustering workspace
+    size_t E_seg, S_state, S_eta1, S_len, mark, mtmp, A_uid, A_rank, P_start, P_len, P_state,
+        P_q0, key, key_alt, val, val_alt, hist, htmp, glb, glen, flg, ftmp, keys0, ctr, status,
+        total;
+};
+struct ClusterPtrs {
+    uint32_t *E_uid, *E_seg, *S_state, *S_eta1, *S_len;
+    uint64_t *mark, *mtmp;
+    uint32_t *A_uid, *A_rank, *P_start, *P_len, *P_state, *P_q0;
+    uint64_t *key, *key_alt;
+    uint32_t *val, *val_alt, *hist, *htmp, *glb, *glen;
+    uint64_t *flg, *ftmp;
+    uint32_t *keys0, *ctr, *status;
+};
+struct ClusterArgs {
+    const int64_t *indptr;
+    const uint32_t *indices;
+    uint64_t nnz;
+    uint32_t n, m, t, b, bb, cap;
+    const uint32_t *bucket;
+    uint32_t NE, NP;
+};
+size_t cluster_ws_elems(const ClusterDims &d, ClusterWs *w);
+hipError_t cluster_init(const ClusterArgs &a, const ClusterPtrs &c, hipStream_t s);
+hipError_t cluster_round(const ClusterArgs &a, const ClusterPtrs &c, uint32_t round,
+                         hipStream_t s);
+hipError_t cluster_finish(const ClusterArgs &a, const ClusterPtrs &c, uint32_t rounds,
+                          uint32_t *cl_off, uint32_t *cl_cfg_off, hipStream_t s);
+
+// ---- local KNN
+struct KnnArgs {
+    const int64_t *indptr;
+    const uint32_t *indices;
+    uint64_t nnz;
+    uint32_t n, m, t, k;
+    const uint32_t *members, *cl_off, *cl_cfg_off;
+    uint32_t NE;    // t*n member slots
+    uint32_t wmax;  // bit-row stride in 32-bit words
+    uint32_t *part_id, *part_I;
+};
+struct KnnWs {
+    size_t rows, rlen, cl_W, nrb, item_off, items, csort_key, csort_key_alt, csort_val,
+        csort_val_alt, hist, htmp, ctr, total;
+};
+struct KnnPtrs {
+    uint32_t *rows, *rlen, *cl_W, *nrb, *item_off;
+    uint64_t *items;
+    uint64_t *csort_key, *csort_key_alt;
+    uint32_t *csort_val, *csort_val_alt, *hist, *htmp, *ctr;
+};
+size_t knn_ws_bytes(uint32_t NE, uint32_t wmax, KnnWs *w);
+uint32_t knn_wmax(uint32_t m);
+size_t knn_stage_lds_bytes(uint32_t m, uint32_t wmax);
+hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, hipStream_t s);
+hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, uint32_t persistent_wgs,
+                       hipStream_t s);
+
+// ---- merge
+hipError_t launch_merge(const int64_t *indptr, uint64_t nnz, uint32_t n, uint32_t t, uint32_t k,
+                        const uint32_t *part_id, const uint32_t *part_I, uint32_t *knn_id,
+                        uint32_t *knn_I, uint32_t *knn_U, hipStream_t s);
+
+}  // namespace c2
