@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: Cluster-and-Conquer KNN-graph builds on one MI355X.
+
+A step is one whole build of the method on one batch of synthetic input with
+the profiles already resident in HBM: item hashing, FastRandomHash keys,
+clustering with recursive splitting, brute-force local KNN in every cluster,
+and the merge (Sections II-D to II-G).  The timed form is the batched build
+replayed as a HIP graph; the plain (host-driven) form is timed beside it.
+
+value = Jaccard evaluations per second of whole-build time, where a Jaccard
+evaluation is one same-cluster pair (the paper's count of similarity
+computations, Section II-F).  The line also carries the quality of the graph
+against the exact graph (Eq. 2), the roofline of the dominant kernel (the
+pairwise local-KNN kernel, timed with HIP events on its own stream), and the
+CPU oracle timed on the host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Jaccard evals/s + KNN-graph build time at quality≥0.95, plain vs batched vs "
+          "learned")
+DEFAULT_WORKLOAD = "n6k_m3.7k"
+VALU_PEAK = 256 * 4 * 16 * 2.4e9      # int32 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+MFMA_I8_PEAK = 5.0e15                 # dense int8 MFMA ops/s
+KNN_KERNEL = "k_knn_mfma"
+MFMA_MIN = 96                         # clusters with at least this many members take the MFMA path
+KNN_SOURCES = ["paper_2010_11497_amd/csrc/k_knn.hip", "paper_2010_11497_amd/csrc/c2_internal.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KNN_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per launch of the local-KNN kernel from the committed PMC
+    summary, only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (KNN_KERNEL, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(P, tab, w, E, budget_s):
+    """The oracle as it stands, on the host's cores, on whole builds of the same
+    workload repeated until about budget_s seconds have passed."""
+    from oracle import oracle
+    threads = min(16, os.cpu_count() or 1)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.build_graph(P.indptr, P.indices, P.n, P.m, tab, w.b, w.cap, w.k, threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or el / reps * (reps + 1) > 3 * budget_s:
+            break
+    return {"value": E * reps / el, "unit": "Jaccard evals/s", "cores": threads, "kind": "oracle",
+            "sample": "%d whole build(s) of %s (hash, cluster, local KNN on a %d-thread pool "
+                      "largest cluster first, merge): %.2f s each" % (reps, w.name, threads, el / reps)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-quality", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2010_11497_amd import c2, metrics, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    log("workload", w.name, "n=%d m=%d t=%d b=%d cap=%d k=%d" % (w.n, w.m, w.t, w.b, w.cap, w.k))
+    P = synth.make_profiles(w)
+    tab = synth.hash_tables(w.t, w.hash_seed)
+    dP = c2.DeviceProfiles.from_synth(P)
+    dtab = c2.tables_to_device(tab)
+    p = c2.params(w.t, w.b, w.cap, w.k)
+    c2.validate(dP)
+
+    # partition statistics for the work counts (GPU clustering, read back)
+    bucket = c2.hash_items(dtab, w.b, w.m)
+    members, cl_off, cfg, _ = c2.cluster(dP, bucket, p, c2.FORM_PLAIN)
+    ncl = int(c2.to_u32(cfg)[-1])
+    work = metrics.cluster_work(c2.to_u32(members), c2.to_u32(cl_off)[: ncl + 1], P.indptr,
+                                P.indices, P.m)
+    E = work["pairs"]
+    log("clusters %d, Jaccard evals %d, max cluster %d" % (ncl, E, int(work["sizes"].max())))
+
+    # HIP-graph form of the batched build
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    g = c2.Graph(dP, dtab, p, c2.tuning(events=ev))
+    for _ in range(args.warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    g.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.launch()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log("graph build: %.3f ms/step" % graph_ms)
+    # dominant kernel: HIP events recorded around it inside each replay
+    knn = []
+    for _ in range(args.steps):
+        g.launch()
+        torch.cuda.synchronize()
+        knn.append(ev[0].elapsed_time(ev[1]))
+    knn_ms = sum(knn) / len(knn)
+    log("local-KNN kernel: %.3f ms (avg of %d)" % (knn_ms, len(knn)))
+    out_graph = [c2.to_u32(x) for x in g.out]
+
+    # batched (eager) and plain forms, same arithmetic
+    def timed(form):
+        ws = c2.workspace(dP, p, c2.OP_BUILD)
+        out = None
+        for _ in range(args.warmup):
+            out = c2.build(dP, dtab, p, form, ws=ws, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = c2.build(dP, dtab, p, form, ws=ws, out=out)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, [c2.to_u32(x) for x in out]
+    batched_ms, out_b = timed(c2.FORM_BATCHED)
+    plain_ms, out_p = timed(c2.FORM_PLAIN)
+    log("batched eager: %.3f ms, plain: %.3f ms" % (batched_ms, plain_ms))
+    same = all(np.array_equal(a, b) for a, b in zip(out_graph, out_b)) and \
+        all(np.array_equal(a, b) for a, b in zip(out_graph, out_p))
+    if not same:
+        raise SystemExit("forms disagree: graph, batched and plain builds differ")
+
+    quality = None
+    if not args.no_quality:
+        bf = c2.brute_force(dP, w.k)
+        torch.cuda.synchronize()
+        quality = metrics.quality(out_graph[1], out_graph[2], c2.to_u32(bf[1]), c2.to_u32(bf[2]))
+        log("quality %.4f" % quality)
+
+    big = work["sizes"] >= MFMA_MIN
+    ops = int((2 * work["sizes"][big].astype(np.int64) ** 2 * work["dict"][big]).sum())
+    achieved = ops / (knn_ms * 1e-3)
+    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_I8_PEAK / 1e12,
+            "unit": "TOP/s", "frac": achieved / MFMA_I8_PEAK,
+            "traffic": traffic_from_profiles(w.name), "kernel": KNN_KERNEL,
+            "ops_per_launch": ops,
+            "ops_def": "sum over clusters with >= %d members of 2*s^2*D: the 0/1 product of the "
+                       "members' rows over the cluster's local dictionary (D = items held by >= "
+                       "2 members)" % MFMA_MIN}
+
+    line = {
+        "metric": METRIC, "value": E / (graph_ms * 1e-3), "unit": "Jaccard evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": graph_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i8",
+        "data": "synthetic: seeded lognormal profile sizes, Zipf item popularity",
+        "config": {"workload": w.name, "n": w.n, "m": w.m, "nnz": P.nnz, "t": w.t, "b": w.b,
+                   "cap": w.cap, "k": w.k, "form": "batched build replayed as a HIP graph"},
+        "build_ms": {"graph": graph_ms, "batched": batched_ms, "plain": plain_ms},
+        "quality": quality, "jaccard_evals": E, "clusters": ncl,
+        "local_knn_ms": knn_ms, "local_knn_evals_per_s": E / (knn_ms * 1e-3),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(P, tab, w, E, args.cpu_budget)
+        line["cpu_baseline"] = cb
+        log("cpu oracle: %.3g evals/s on %d threads" % (cb["value"], cb["cores"]))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

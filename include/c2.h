@@ -96,6 +96,8 @@ typedef struct c2_tuning {
     uint32_t persistent_wgs;  /* workgroups of the persistent launch (batched form) */
     uint32_t split_rounds;    /* split rounds enqueued by the batched form */
     uint32_t reserved;
+    void *ev_knn_begin;       /* optional hipEvent_t (host handles, caller-owned): recorded on */
+    void *ev_knn_end;         /* the stream right before / after the pairwise local-KNN kernel */
 } c2_tuning;
 
 /* Workspace queries: which call the size is for. */

@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("mfma_min_rows", ctypes.c_uint32), ("persistent_wgs", ctypes.c_uint32),
-                ("split_rounds", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("split_rounds", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("ev_knn_begin", ctypes.c_void_p), ("ev_knn_end", ctypes.c_void_p)]
 
 
 _lib = None
@@ -136,8 +137,17 @@ def params(t, b, cap, k) -> Params:
     return Params(int(t), int(b), int(cap), int(k))
 
 
-def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0) -> Tuning:
-    return Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), 0)
+def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0, events=None) -> Tuning:
+    """events: optional (begin, end) torch.cuda.Event(enable_timing=True) pair
+    recorded around the local-KNN kernel."""
+    tu = Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), 0, None, None)
+    if events is not None:
+        for ev in events:
+            ev.record()           # materialise the underlying hipEvent_t
+        torch.cuda.current_stream().synchronize()
+        tu.ev_knn_begin = ctypes.c_void_p(events[0].cuda_event)
+        tu.ev_knn_end = ctypes.c_void_p(events[1].cuda_event)
+    return tu
 
 
 def workspace_bytes(P: DeviceProfiles, p: Optional[Params], op: int) -> int:

@@ -84,7 +84,7 @@ BuildLayout build_layout(uint32_t n, uint32_t m, const c2_params *p) {
     L.part_I = take(4 * NE * p->k);
     L.scratch = off;
     const size_t cw = cluster_ws_elems(cdims(n, p), nullptr);
-    const size_t kw = knn_ws_bytes((uint32_t)NE, knn_wmax(m), nullptr);
+    const size_t kw = knn_ws_bytes(n, (uint32_t)NE, knn_wmax(m), nullptr);
     L.total = off + (cw > kw ? cw : kw);
     return L;
 }
@@ -128,10 +128,10 @@ KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
     auto u64 = [&](size_t o) { return reinterpret_cast<uint64_t *>(base + o); };
     k.rows = u32(w.rows);
     k.rlen = u32(w.rlen);
-    k.cl_W = u32(w.cl_W);
-    k.nrb = u32(w.nrb);
-    k.item_off = u32(w.item_off);
-    k.items = u64(w.items);
+    k.cnt = u64(w.cnt);
+    k.items_m = u64(w.items_m);
+    k.items_b = u64(w.items_b);
+    k.ctmp = u64(w.ctmp);
     k.csort_key = u64(w.csort_key);
     k.csort_key_alt = u64(w.csort_key_alt);
     k.csort_val = u32(w.csort_val);
@@ -196,7 +196,7 @@ c2_status run_knn(const c2_profiles *P, const uint32_t *members, const uint32_t 
     KnnWs w;
     const uint32_t NE = t * P->n;
     const uint32_t wmax = knn_wmax(P->m);
-    knn_ws_bytes(NE, wmax, &w);
+    knn_ws_bytes(P->n, NE, wmax, &w);
     KnnArgs a;
     a.indptr = P->indptr;
     a.indices = P->indices;
@@ -213,8 +213,15 @@ c2_status run_knn(const c2_profiles *P, const uint32_t *members, const uint32_t 
     a.part_id = part_id;
     a.part_I = part_I;
     const KnnPtrs kp = knn_ptrs(scratch, w);
-    if (form == C2_FORM_PLAIN) C2_TRY(knn_plain(a, kp, s), "local knn");
-    else C2_TRY(knn_batched(a, kp, tune ? tune->persistent_wgs : 0, s), "local knn");
+    KnnOpts o;
+    if (tune) {
+        o.persistent_wgs = tune->persistent_wgs;
+        o.mfma_min = tune->mfma_min_rows;
+        o.ev_begin = (hipEvent_t)tune->ev_knn_begin;
+        o.ev_end = (hipEvent_t)tune->ev_knn_end;
+    }
+    if (form == C2_FORM_PLAIN) C2_TRY(knn_plain(a, kp, o, s), "local knn");
+    else C2_TRY(knn_batched(a, kp, o, s), "local knn");
     return C2_OK;
 }
 
@@ -246,7 +253,7 @@ size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params 
         return kHeader + cluster_ws_elems(cdims(n, p), nullptr);
     case C2_OP_LOCAL_KNN:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
-        return kHeader + knn_ws_bytes(p->t * n, knn_wmax(m), nullptr);
+        return kHeader + knn_ws_bytes(n, p->t * n, knn_wmax(m), nullptr);
     case C2_OP_BUILD:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
         return build_layout(n, m, p).total;
@@ -255,7 +262,7 @@ size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params 
         if (check_sizes(n, m, nnz, &one, true) != C2_OK) return 0;
         const size_t head = kHeader + al(4 * (size_t)n) + al(4 * ((size_t)n + 1)) + al(8) +
                             2 * al(4 * (size_t)n * one.k);
-        return head + knn_ws_bytes(n, knn_wmax(m), nullptr);
+        return head + knn_ws_bytes(n, n, knn_wmax(m), nullptr);
     }
     default:
         fail(C2_E_ARG, "unknown op %d", op);

@@ -30,6 +30,15 @@ C2_DEV void row_range(const int64_t *indptr, uint32_t u, uint64_t nnz, uint64_t 
     e = (uint64_t)y;
 }
 
+// Workgroup barrier that waits only for this wave's LDS operations: global
+// loads issued before it stay in flight (a plain __syncthreads() also drains
+// them, which defeats software prefetching).
+C2_DEV void lds_barrier() {
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // Exact Jaccard order: does (Ia, Ua, va) rank before (Ib, Ub, vb)?
 C2_DEV bool jbetter(uint32_t Ia, uint32_t Ua, uint32_t va, uint32_t Ib, uint32_t Ub,
                     uint32_t vb) {

@@ -60,25 +60,31 @@ struct KnnArgs {
     uint32_t n, m, t, k;
     const uint32_t *members, *cl_off, *cl_cfg_off;
     uint32_t NE;    // t*n member slots
-    uint32_t wmax;  // bit-row stride in 32-bit words
+    uint32_t wmax;  // words per user bit row (item universe padded to 64)
     uint32_t *part_id, *part_I;
 };
 struct KnnWs {
-    size_t rows, rlen, cl_W, nrb, item_off, items, csort_key, csort_key_alt, csort_val,
-        csort_val_alt, hist, htmp, ctr, total;
+    size_t rows, rlen, cnt, items_m, items_b, csort_key, csort_key_alt, csort_val, csort_val_alt,
+        hist, htmp, ctmp, ctr, total;
 };
 struct KnnPtrs {
-    uint32_t *rows, *rlen, *cl_W, *nrb, *item_off;
-    uint64_t *items;
+    uint32_t *rows, *rlen;
+    uint64_t *cnt, *items_m, *items_b;
     uint64_t *csort_key, *csort_key_alt;
-    uint32_t *csort_val, *csort_val_alt, *hist, *htmp, *ctr;
+    uint32_t *csort_val, *csort_val_alt, *hist, *htmp;
+    uint64_t *ctmp;
+    uint32_t *ctr;
 };
-size_t knn_ws_bytes(uint32_t NE, uint32_t wmax, KnnWs *w);
+size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w);
 uint32_t knn_wmax(uint32_t m);
 size_t knn_stage_lds_bytes(uint32_t m, uint32_t wmax);
-hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, hipStream_t s);
-hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, uint32_t persistent_wgs,
-                       hipStream_t s);
+struct KnnOpts {
+    uint32_t persistent_wgs = 0;
+    uint32_t mfma_min = 0;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+};
+hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s);
+hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s);
 
 // ---- merge
 hipError_t launch_merge(const int64_t *indptr, uint64_t nnz, uint32_t n, uint32_t t, uint32_t k,

@@ -1,15 +1,16 @@
 // Step 2 on the device: exact brute-force KNN inside every cluster
 // (Section II-F, Algorithm 2, brute-force branch).
 //
-// Staging: per cluster, the local dictionary is the set of items held by at
-// least two members (an item held once can never be in an intersection);
-// each member becomes a bit row over that dictionary, padded to a multiple of
-// 64 items.  Intersection sizes |P_u & P_v| are then dot products of bit rows;
-// |P_u | P_v| = |P_u| + |P_v| - |P_u & P_v| uses the full profile lengths.
-//
-// Per-user selection: every member of the row block owns a bounded heap of
-// its k best candidates in LDS (worst at the root, exact Jaccard order), and
-// offers each candidate that beats the root.
+// Every user's profile is stored once as a bit row over the item universe
+// (padded to a multiple of 64 items).  |P_u & P_v| is the dot product of two
+// bit rows; |P_u | P_v| = |P_u| + |P_v| - |P_u & P_v|.  Two paths compute the
+// dot products of a cluster's members, in tiles of (row block x column block):
+//   - int8 MFMA: 64-item chunks of the bit rows are expanded to 0/1 bytes in
+//     LDS and multiplied with v_mfma_i32_32x32x32_i8 (exact int32 sums);
+//   - bitmap: AND + population count of 32-bit words, for small clusters.
+// Selection: every member of the row block owns a bounded heap of its k best
+// candidates in LDS (worst at the root, exact Jaccard order) and offers each
+// candidate that beats the root.
 #include "c2_internal.h"
 #include "c2_kernels.h"
 
@@ -17,14 +18,22 @@ namespace c2 {
 
 constexpr int kStageThreads = 256;
 constexpr int kStageWaves = kStageThreads / 64;
-constexpr uint32_t kRowBlock = 64;   // rows (members) per work item
-constexpr int kWordChunk = 16;       // bit-row words staged per step
+constexpr uint32_t kRowBlock = 64;   // rows (members) per bitmap work item
+constexpr int kWordChunk = 16;       // bit-row words staged per step (bitmap path)
+constexpr uint32_t kMR = 128;        // rows per MFMA work item (row owners)
+constexpr uint32_t kMC = 128;        // columns per MFMA step
+constexpr int kOpStride = 80;        // bytes per staged 64-item row (padded: no bank conflicts)
+constexpr int kTileStride = 132;     // u32 per row of the transposed result tile
+constexpr uint32_t kDefaultMfmaMin = 96;
+constexpr uint32_t kPf = 8;          // chunks of bit rows prefetched ahead (MFMA path)
 
-uint32_t knn_wmax(uint32_t m) { return 2 * (uint32_t)div_up(m, 64); }
+// Words per bit row: the item universe padded to a multiple of 64 * kPf items,
+// so the MFMA K loop runs whole unrolled groups.
+uint32_t knn_wmax(uint32_t m) { return 2 * kPf * (uint32_t)div_up(m, 64 * kPf); }
 
 size_t knn_stage_lds_bytes(uint32_t m, uint32_t wmax) {
-    const size_t mw = div_up(m, 32);
-    return 4 * (3 * mw + (size_t)kStageWaves * wmax);
+    (void)m;
+    return 4 * (size_t)kStageWaves * wmax;
 }
 
 C2_DEV void wave_sync() {
@@ -33,103 +42,63 @@ C2_DEV void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ------------------------------------------------------------------ staging
+// ------------------------------------------------------------------ bit rows
 
-__global__ __launch_bounds__(kStageThreads) void k_knn_stage(
-    const int64_t *__restrict__ indptr, const uint32_t *__restrict__ indices, uint64_t nnz,
-    uint32_t n, uint32_t m, uint32_t t, uint32_t k, const uint32_t *__restrict__ members,
-    const uint32_t *__restrict__ cl_off, const uint32_t *__restrict__ cl_cfg_off, uint32_t wmax,
-    uint32_t *__restrict__ rows, uint32_t *__restrict__ rlen, uint32_t *__restrict__ cl_W,
-    uint32_t *__restrict__ part_id, uint32_t *__restrict__ part_I) {
+// ubits[u][w]: bit (i & 31) of word i >> 5 is set iff item i is in P_u; rows
+// are padded to a multiple of 64 items.  ulen[u] = |P_u|.  Row n is all zero:
+// padding members of a tile point at it, so tile loads need no predicate.
+// One wave per user, the row assembled in LDS and written out whole.
+__global__ __launch_bounds__(kStageThreads) void k_user_bits(const int64_t *__restrict__ indptr,
+                                                             const uint32_t *__restrict__ indices,
+                                                             uint64_t nnz, uint32_t n, uint32_t m,
+                                                             uint32_t Wg,
+                                                             uint32_t *__restrict__ ubits,
+                                                             uint32_t *__restrict__ ulen,
+                                                             uint32_t *maxlen) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wsum[kStageWaves + 1];
-    const uint32_t mw = (m + 31) / 32;
-    uint32_t *seen1 = lds, *seen2 = lds + mw, *pref = lds + 2 * mw;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    uint32_t *rb = lds + 3 * mw + wid * wmax;
-    const uint32_t ncl = cl_cfg_off[t];
-    const uint32_t per = (mw + kStageThreads - 1) / kStageThreads;
-    for (uint32_t c = blockIdx.x; c < ncl; c += gridDim.x) {
-        const uint32_t o = cl_off[c], s = cl_off[c + 1] - o;
-        if (s <= 1) {
-            const uint32_t u = s == 1 ? members[o] : n, j = o / n;
-            if (u < n && j < t && tid < k) {
-                part_id[((size_t)u * t + j) * k + tid] = kPad;
-                part_I[((size_t)u * t + j) * k + tid] = 0;
-            }
-            if (tid == 0) cl_W[c] = 0;
-            continue;
-        }
-        for (uint32_t w = tid; w < mw; w += kStageThreads) seen1[w] = seen2[w] = 0;
-        __syncthreads();
-        for (uint32_t a = wid; a < s; a += kStageWaves) {
-            uint64_t p0, p1;
-            row_range(indptr, members[o + a], nnz, p0, p1);
-            for (uint64_t p = p0 + lane; p < p1; p += 64) {
-                const uint32_t i = indices[p];
-                if (i < m) {
-                    const uint32_t bit = 1u << (i & 31);
-                    if (atomicOr(&seen1[i >> 5], bit) & bit) atomicOr(&seen2[i >> 5], bit);
-                }
-            }
-        }
-        __syncthreads();
-        // dictionary rank of every twice-seen item: prefix popcount over words
-        uint32_t loc = 0;
-        for (uint32_t w = tid * per; w < mw && w < (tid + 1) * per; ++w) loc += __popc(seen2[w]);
-        uint32_t D;
-        uint32_t pre = block_excl_scan<uint32_t, kStageThreads>(loc, wsum, &D);
-        for (uint32_t w = tid * per; w < mw && w < (tid + 1) * per; ++w) {
-            pref[w] = pre;
-            pre += __popc(seen2[w]);
-        }
-        const uint32_t W = 2 * ((D + 63) / 64);
-        if (tid == 0) cl_W[c] = W;
-        __syncthreads();
-        for (uint32_t a = wid; a < s; a += kStageWaves) {
-            const uint32_t u = members[o + a];
-            for (uint32_t w = lane; w < W; w += 64) rb[w] = 0;
-            wave_sync();
-            uint64_t p0, p1;
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t *rb = lds + wid * Wg;
+    uint32_t longest = 0;
+    for (uint32_t u = blockIdx.x * kStageWaves + wid; u <= n; u += gridDim.x * kStageWaves) {
+        for (uint32_t w = lane; w < Wg; w += 64) rb[w] = 0;
+        wave_sync();
+        uint64_t p0 = 0, p1 = 0;
+        if (u < n) {
             row_range(indptr, u, nnz, p0, p1);
             for (uint64_t p = p0 + lane; p < p1; p += 64) {
                 const uint32_t i = indices[p];
-                if (i < m) {
-                    const uint32_t bit = 1u << (i & 31), sw = seen2[i >> 5];
-                    if (sw & bit) {
-                        const uint32_t li = pref[i >> 5] + __popc(sw & (bit - 1));
-                        atomicOr(&rb[li >> 5], 1u << (li & 31));
-                    }
-                }
+                if (i < m) atomicOr(&rb[i >> 5], 1u << (i & 31));
             }
-            wave_sync();
-            uint32_t *out = rows + (size_t)(o + a) * wmax;
-            for (uint32_t w = lane; w < W; w += 64) out[w] = rb[w];
-            if (lane == 0) rlen[o + a] = (uint32_t)(p1 - p0);
-            wave_sync();
         }
-        __syncthreads();
+        wave_sync();
+        uint32_t *out = ubits + (size_t)u * Wg;
+        for (uint32_t w = lane; w < Wg; w += 64) out[w] = rb[w];
+        if (lane == 0) ulen[u] = (uint32_t)(p1 - p0);
+        if (p1 - p0 > longest) longest = (uint32_t)(p1 - p0);
+        wave_sync();
     }
+    if (lane == 0 && longest) atomicMax(maxlen, longest);
 }
 
 // --------------------------------------------------------------- selection
 
 // Bounded heap of one row's best candidates, structure-of-arrays in LDS with
-// the row's lane as the minor index (conflict-free).  Root = worst kept.
+// the owner's index as the minor index (conflict-free).  Root = worst kept.
+template <uint32_t STRIDE>
 struct RowHeap {
-    uint32_t *hI, *hU, *hV;  // [kMaxK][64]
-    uint32_t lane, k, cnt;
+    uint32_t *hI, *hU, *hV;  // [kMaxK][STRIDE]
+    uint32_t me, k, cnt;
     uint32_t rI, rU, rV;     // root copy
 
     C2_DEV void get(uint32_t i, uint32_t &I, uint32_t &U, uint32_t &V) const {
-        I = hI[i * 64 + lane];
-        U = hU[i * 64 + lane];
-        V = hV[i * 64 + lane];
+        I = hI[i * STRIDE + me];
+        U = hU[i * STRIDE + me];
+        V = hV[i * STRIDE + me];
     }
     C2_DEV void put(uint32_t i, uint32_t I, uint32_t U, uint32_t V) {
-        hI[i * 64 + lane] = I;
-        hU[i * 64 + lane] = U;
-        hV[i * 64 + lane] = V;
+        hI[i * STRIDE + me] = I;
+        hU[i * STRIDE + me] = U;
+        hV[i * STRIDE + me] = V;
     }
     // Sift (I, U, V) down from the root over `size` entries.
     C2_DEV void sift_down(uint32_t I, uint32_t U, uint32_t V, uint32_t size) {
@@ -149,6 +118,9 @@ struct RowHeap {
             pos = l;
         }
         put(pos, I, U, V);
+    }
+    C2_DEV void init(uint32_t *I, uint32_t *U, uint32_t *V, uint32_t owner, uint32_t kk) {
+        hI = I; hU = U; hV = V; me = owner; k = kk; cnt = 0; rI = 0; rU = 1; rV = kPad;
     }
     C2_DEV void offer(uint32_t I, uint32_t U, uint32_t V) {
         if (cnt < k) {
@@ -188,6 +160,24 @@ struct RowHeap {
     }
 };
 
+// Cluster c as seen by a work item.
+struct ClusterView {
+    uint32_t o, s, j;
+};
+
+C2_DEV ClusterView view(const KnnArgs &a, uint32_t c) {
+    ClusterView v;
+    v.o = a.cl_off[c];
+    v.s = a.cl_off[c + 1] - v.o;
+    v.j = v.o / a.n;
+    return v;
+}
+
+C2_DEV uint32_t member(const KnnArgs &a, const ClusterView &v, uint32_t idx) {
+    const uint32_t u = idx < v.s ? a.members[v.o + idx] : a.n;
+    return u < a.n ? u : a.n;
+}
+
 // ------------------------------------------------------------ bitmap path
 //
 // One wave per work item (cluster, block of 64 rows); lane = row owner.  The
@@ -195,29 +185,30 @@ struct RowHeap {
 // popcount against each column row of a 64-column tile staged in LDS (read
 // as a broadcast).
 
-struct BitmapLds {
+struct __attribute__((aligned(16))) BitmapLds {
     uint32_t colw[kRowBlock][kWordChunk];
     uint32_t clen[kRowBlock], cuid[kRowBlock];
     uint32_t hI[kMaxK * 64], hU[kMaxK * 64], hV[kMaxK * 64];
 };
 
-C2_DEV void bitmap_item(const KnnArgs &a, const uint32_t *rows, const uint32_t *rlen,
-                        const uint32_t *cl_W, uint32_t c, uint32_t rb, BitmapLds &L) {
+C2_DEV void bitmap_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *ulen,
+                        uint32_t c, uint32_t rb, BitmapLds &L) {
     const uint32_t lane = threadIdx.x;
-    const uint32_t o = a.cl_off[c], s = a.cl_off[c + 1] - o, j = o / a.n;
-    const uint32_t W = cl_W[c], wmax = a.wmax;
+    const ClusterView cv = view(a, c);
+    const uint32_t s = cv.s, W = a.wmax;
     const uint32_t ra = rb * kRowBlock + lane;
-    const bool active = ra < s;
-    const uint32_t Lr = active ? rlen[o + ra] : 0;
-    RowHeap h;
-    h.hI = L.hI; h.hU = L.hU; h.hV = L.hV;
-    h.lane = lane; h.k = a.k; h.cnt = 0; h.rI = 0; h.rU = 1; h.rV = kPad;
-    const uint32_t *myrow = rows + (size_t)(o + (active ? ra : 0)) * wmax;
+    const uint32_t ur = member(a, cv, ra);
+    const bool active = ur < a.n;
+    const uint32_t Lr = active ? ulen[ur] : 0;
+    RowHeap<64> h;
+    h.init(L.hI, L.hU, L.hV, lane, a.k);
+    const uint32_t *myrow = ubits + (size_t)(active ? ur : 0) * W;
     for (uint32_t cb = 0; cb * kRowBlock < s; ++cb) {
-        const uint32_t ci = cb * kRowBlock + lane;
         __syncthreads();
-        L.clen[lane] = ci < s ? rlen[o + ci] : 0;
-        L.cuid[lane] = ci < s ? a.members[o + ci] : kPad;
+        const uint32_t uc = member(a, cv, cb * kRowBlock + lane);
+        L.clen[lane] = uc < a.n ? ulen[uc] : 0;
+        L.cuid[lane] = uc;
+        __syncthreads();
         uint32_t acc[kRowBlock];
 #pragma unroll
         for (int q = 0; q < (int)kRowBlock; ++q) acc[q] = 0;
@@ -227,9 +218,8 @@ C2_DEV void bitmap_item(const KnnArgs &a, const uint32_t *rows, const uint32_t *
             for (int it = 0; it < kWordChunk; ++it) {
                 const uint32_t idx = it * 64 + lane;
                 const uint32_t cc = idx / kWordChunk, ww = idx % kWordChunk;
-                const uint32_t col = cb * kRowBlock + cc;
-                L.colw[cc][ww] = (col < s && w0 + ww < W) ? rows[(size_t)(o + col) * wmax + w0 + ww]
-                                                          : 0u;
+                const uint32_t ucc = L.cuid[cc];
+                L.colw[cc][ww] = (ucc < a.n && w0 + ww < W) ? ubits[(size_t)ucc * W + w0 + ww] : 0u;
             }
             uint32_t r[kWordChunk];
 #pragma unroll
@@ -249,7 +239,6 @@ C2_DEV void bitmap_item(const KnnArgs &a, const uint32_t *rows, const uint32_t *
                 acc[q] = x;
             }
         }
-        __syncthreads();
         if (active) {
 #pragma unroll
             for (int q = 0; q < (int)kRowBlock; ++q) {
@@ -261,18 +250,16 @@ C2_DEV void bitmap_item(const KnnArgs &a, const uint32_t *rows, const uint32_t *
             }
         }
     }
-    const uint32_t u = active ? a.members[o + ra] : a.n;
-    if (u < a.n && j < a.t) {
-        const size_t base = ((size_t)u * a.t + j) * a.k;
+    if (active && cv.j < a.t) {
+        const size_t base = ((size_t)ur * a.t + cv.j) * a.k;
         h.drain(a.part_id + base, a.part_I + base);
     }
 }
 
 // Plain form: block b handles items[b].  Batched form: persistent blocks take
 // items from a device cursor until the list is exhausted.
-__global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *rows,
-                                                   const uint32_t *rlen, const uint32_t *cl_W,
-                                                   const uint64_t *items,
+__global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *ubits,
+                                                   const uint32_t *ulen, const uint64_t *items,
                                                    const uint32_t *n_items, uint32_t *cursor) {
     __shared__ BitmapLds L;
     __shared__ uint32_t next;
@@ -280,7 +267,7 @@ __global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *ro
     if (!cursor) {
         if (blockIdx.x >= total) return;
         const uint64_t it = items[blockIdx.x];
-        bitmap_item(a, rows, rlen, cl_W, (uint32_t)(it >> 32), (uint32_t)it, L);
+        bitmap_item(a, ubits, ulen, (uint32_t)(it >> 32), (uint32_t)it, L);
         return;
     }
     for (;;) {
@@ -290,39 +277,337 @@ __global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *ro
         const uint32_t i = next;
         if (i >= total) break;
         const uint64_t it = items[i];
-        bitmap_item(a, rows, rlen, cl_W, (uint32_t)(it >> 32), (uint32_t)it, L);
+        bitmap_item(a, ubits, ulen, (uint32_t)(it >> 32), (uint32_t)it, L);
+    }
+}
+
+// -------------------------------------------------------------- MFMA path
+//
+// One block of 4 waves per work item (cluster, block of 128 rows).  For every
+// 128-column tile of the cluster the block computes the 128 x 128 matrix of
+// intersection counts: 256 threads each expand one staged row's next 64 bits
+// into 64 bytes of 0/1 (double-buffered in LDS), and each wave multiplies a
+// 64 x 64 sub-tile as 2 x 2 v_mfma_i32_32x32x32_i8.  The counts are written
+// to LDS transposed (16 bits each) so that thread t < 128 reads row t.
+//
+// Selection on this path uses an exact 32-bit similarity key,
+//   key(I, U) = floor(I * (2^32 - 1) / U),
+// which preserves the order of I/U exactly when U < 2^16 (two different
+// fractions with denominators below 2^16 differ by more than 1/(2^32 - 1)),
+// so the path is taken only when every profile has fewer than 2^15 items.
+// A heap entry is the u64 (key << 32) | (0xFFFFFFFF - id): larger is better.
+// Each tile is first filtered against the heap root (exactly, without a
+// division: key(I, U) > key_T  <=>  I * (2^32 - 1) >= (key_T + 1) * U), then
+// the candidates that passed are inserted in a wave-uniform loop.
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kTile16Stride = 136;   // u16 per row of the transposed result tile
+constexpr uint32_t kMfmaMaxLen = 1u << 15;
+
+struct __attribute__((aligned(16))) MfmaLds {
+    union __attribute__((aligned(16))) {
+        uint8_t op[2][kMR + kMC][kOpStride];
+        uint16_t itile[kMR][kTile16Stride];
+    } u;
+    uint32_t cuid[kMC], clen[kMC];
+    uint64_t hk[kMaxK * kMR];
+};
+
+// 64 bits -> 64 bytes of 0/1, byte x = bit x.
+C2_DEV void expand64(uint64_t bits, uint8_t *dst) {
+    const uint32_t lo = (uint32_t)bits, hi = (uint32_t)(bits >> 32);
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t w = q < 2 ? lo : hi;
+        const int sh = (q & 1) * 16;
+        uint4 v;
+        v.x = __umul24((w >> (sh + 0)) & 15u, 0x204081u) & 0x01010101u;
+        v.y = __umul24((w >> (sh + 4)) & 15u, 0x204081u) & 0x01010101u;
+        v.z = __umul24((w >> (sh + 8)) & 15u, 0x204081u) & 0x01010101u;
+        v.w = __umul24((w >> (sh + 12)) & 15u, 0x204081u) & 0x01010101u;
+        d[q] = v;
+    }
+}
+
+// Unconditional load (chunk clamped into the row) so the compiler can count
+// outstanding loads; values past the row are expanded into the idle stage
+// buffer but never multiplied.
+C2_DEV uint64_t load_bits(const uint64_t *row, uint32_t chunk, uint32_t nchunks) {
+    return row[chunk < nchunks ? chunk : nchunks - 1];
+}
+
+// floor(I * (2^32 - 1) / U) for 0 <= I <= U < 2^16, U >= 1: a double
+// estimate (absolute error < 2^-20) and one exact integer correction.
+C2_DEV uint32_t jkey(uint32_t I, uint32_t U) {
+    const uint64_t N = ((uint64_t)I << 32) - I;
+    uint64_t q = (uint64_t)((double)N / (double)U);
+    const uint64_t p = q * U;
+    if (p > N) q -= 1;
+    else if (p + U <= N) q += 1;
+    return (uint32_t)q;
+}
+
+// I from key(I, U) and S = |P_u| + |P_v| (U = S - I): I/(S - I) is strictly
+// increasing in I, and S*key/(2^32 - 1 + key) is within 2^-16 of I.
+C2_DEV uint32_t key_to_I(uint32_t key, uint32_t S) {
+    const double x = (double)S * (double)key / (4294967295.0 + (double)key);
+    return (uint32_t)(x + 0.5);
+}
+
+// Is (I, U, uid) better than the heap root hk?  Exact.
+C2_DEV bool beats(uint32_t I, uint32_t U, uint32_t uid, uint64_t hk) {
+    const uint32_t kt = (uint32_t)(hk >> 32);
+    const uint64_t A = ((uint64_t)I << 32) - I;   // I * (2^32 - 1)
+    const uint64_t B = (uint64_t)kt * U;          // key_T * U
+    if (A < B) return false;                      // key < key_T
+    if (A >= B + U) return true;                  // key > key_T
+    return uid < 0xFFFFFFFFu - (uint32_t)hk;      // equal keys: smaller id wins
+}
+
+struct KeyHeap {
+    uint64_t *hk;  // [kMaxK][kMR], minor index = owner
+    uint32_t me, k, cnt;
+    uint64_t root;
+
+    C2_DEV uint64_t get(uint32_t i) const { return hk[i * kMR + me]; }
+    C2_DEV void put(uint32_t i, uint64_t v) { hk[i * kMR + me] = v; }
+    C2_DEV void sift_down(uint64_t v, uint32_t size) {
+        uint32_t pos = 0;
+        for (;;) {
+            uint32_t l = 2 * pos + 1;
+            if (l >= size) break;
+            uint64_t c = get(l);
+            if (l + 1 < size) {
+                const uint64_t d = get(l + 1);
+                if (d < c) { c = d; l = l + 1; }
+            }
+            if (v <= c) break;
+            put(pos, c);
+            pos = l;
+        }
+        put(pos, v);
+    }
+    C2_DEV bool full() const { return cnt >= k; }
+    C2_DEV void insert(uint64_t v) {
+        if (cnt < k) {
+            uint32_t pos = cnt++;
+            while (pos > 0) {
+                const uint32_t par = (pos - 1) >> 1;
+                const uint64_t pv = get(par);
+                if (pv <= v) break;
+                put(pos, pv);
+                pos = par;
+            }
+            put(pos, v);
+        } else {
+            sift_down(v, k);
+        }
+        root = get(0);
+    }
+};
+
+C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *ulen, uint32_t c,
+                      uint32_t rb, MfmaLds &L) {
+    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint32_t wr = w >> 1, wc = w & 1;
+    const ClusterView cv = view(a, c);
+    const uint32_t s = cv.s, W = a.wmax, nchunks = W / 2;
+    // row owner state (threads 0..127)
+    const uint32_t ra = rb * kMR + t;
+    const uint32_t ur = t < kMR ? member(a, cv, ra) : a.n;
+    const bool owner = ur < a.n;
+    const uint32_t Lr = owner ? ulen[ur] : 0;
+    KeyHeap h;
+    h.hk = L.hk;
+    h.me = t < kMR ? t : 0;
+    h.k = a.k;
+    h.cnt = 0;
+    h.root = 0;
+    const uint32_t hl = (lane >> 5) * 16;  // byte offset of this lane's 16 k-values
+    for (uint32_t cb = 0; cb * kMC < s; ++cb) {
+        // staged row of this thread: owner row t, or column t - 128
+        const uint32_t us = t < kMR ? ur : member(a, cv, cb * kMC + (t - kMR));
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(ubits + (size_t)us * W);
+        if (t >= kMR) {
+            L.cuid[t - kMR] = us;
+            L.clen[t - kMR] = us < a.n ? ulen[us] : 0;
+        }
+        v16i acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
+        // bits of chunk ch live in pf[ch % kPf] from kPf - 1 chunks before use;
+        // the loop is unrolled by kPf so every slot index is a constant
+        uint64_t pf[kPf];
+#pragma unroll
+        for (int q = 1; q < (int)kPf; ++q) pf[q] = load_bits(src, q, nchunks);
+        expand64(load_bits(src, 0, nchunks), L.u.op[0][t]);
+        pf[0] = load_bits(src, kPf, nchunks);
+        // nchunks is a multiple of kPf: the unrolled body has no branch, so the
+        // compiler can wait for exactly the one load each expansion needs
+        for (uint32_t ch0 = 0; ch0 < nchunks; ch0 += kPf) {
+#pragma unroll
+            for (int u = 0; u < (int)kPf; ++u) {
+                const uint32_t ch = ch0 + u;
+                lds_barrier();
+                const uint32_t st = u & 1;
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    const uint32_t off = kk * 32 + hl;
+                    const v4i A0 = *reinterpret_cast<const v4i *>(&L.u.op[st][wr * 64 + (lane & 31)][off]);
+                    const v4i A1 = *reinterpret_cast<const v4i *>(&L.u.op[st][wr * 64 + 32 + (lane & 31)][off]);
+                    const v4i B0 = *reinterpret_cast<const v4i *>(&L.u.op[st][kMR + wc * 64 + (lane & 31)][off]);
+                    const v4i B1 = *reinterpret_cast<const v4i *>(&L.u.op[st][kMR + wc * 64 + 32 + (lane & 31)][off]);
+                    acc00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B0, acc00, 0, 0, 0);
+                    acc01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B1, acc01, 0, 0, 0);
+                    acc10 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B0, acc10, 0, 0, 0);
+                    acc11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B1, acc11, 0, 0, 0);
+                }
+                const int nx = (u + 1) % kPf;
+                expand64(pf[nx], L.u.op[st ^ 1][t]);
+                pf[nx] = load_bits(src, ch + 1 + kPf, nchunks);
+            }
+        }
+        __syncthreads();
+        // transpose through LDS: C[i][j] of a 32x32 block sits in lane j (+32),
+        // register r at row 8*(r/4) + 4*(lane/32) + r%4
+        {
+            const uint32_t j0 = wc * 64 + (lane & 31), i0 = wr * 64 + 4 * (lane >> 5);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t i = i0 + 8 * (r >> 2) + (r & 3);
+                L.u.itile[i][j0] = (uint16_t)acc00[r];
+                L.u.itile[i][j0 + 32] = (uint16_t)acc01[r];
+                L.u.itile[i + 32][j0] = (uint16_t)acc10[r];
+                L.u.itile[i + 32][j0 + 32] = (uint16_t)acc11[r];
+            }
+        }
+        __syncthreads();
+        if (t < kMR) {
+            const uint32_t ncol = s - cb * kMC < kMC ? s - cb * kMC : kMC;
+            const uint32_t self = ra - cb * kMC;  // column index of the owner's own row
+            uint32_t msk[4] = {0u, 0u, 0u, 0u};
+            if (owner) {
+                for (uint32_t q8 = 0; q8 < ncol; q8 += 8) {
+                    const uint4 raw = *reinterpret_cast<const uint4 *>(&L.u.itile[t][q8]);
+                    const uint32_t pr[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const uint32_t q = q8 + e;
+                        const uint32_t I = (pr[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                        const bool ok = q < ncol && q != self &&
+                                        (!h.full() || beats(I, Lr + L.clen[q] - I, L.cuid[q], h.root));
+                        if (ok) msk[q >> 5] |= 1u << (q & 31);
+                    }
+                }
+            }
+            // wave-uniform loop: each lane inserts its next passing candidate
+            while (__any((msk[0] | msk[1] | msk[2] | msk[3]) != 0u)) {
+                const int wsel = msk[0] ? 0 : msk[1] ? 1 : msk[2] ? 2 : msk[3] ? 3 : -1;
+                if (wsel >= 0) {
+                    const uint32_t bit = __ffs(msk[wsel]) - 1;
+                    msk[wsel] &= msk[wsel] - 1;
+                    const uint32_t q = wsel * 32 + bit;
+                    const uint32_t I = L.u.itile[t][q];
+                    const uint32_t U = Lr + L.clen[q] - I, uid = L.cuid[q];
+                    if (!h.full() || beats(I, U, uid, h.root))
+                        h.insert(((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (owner && cv.j < a.t) {
+        const size_t base = ((size_t)ur * a.t + cv.j) * a.k;
+        uint32_t *oid = a.part_id + base, *oI = a.part_I + base;
+        for (uint32_t r = h.cnt; r < a.k; ++r) {
+            oid[r] = kPad;
+            oI[r] = 0;
+        }
+        for (uint32_t size = h.cnt; size > 0; --size) {
+            const uint64_t v = h.get(0);
+            const uint32_t uid = 0xFFFFFFFFu - (uint32_t)v;
+            oid[size - 1] = uid;
+            oI[size - 1] = key_to_I((uint32_t)(v >> 32), Lr + ulen[uid]);
+            if (size > 1) h.sift_down(h.get(size - 1), size - 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_knn_mfma(KnnArgs a, const uint32_t *ubits,
+                                                     const uint32_t *ulen, const uint64_t *items,
+                                                     const uint32_t *n_items, uint32_t *cursor) {
+    __shared__ MfmaLds L;
+    __shared__ uint32_t next;
+    const uint32_t total = *n_items;
+    if (!cursor) {
+        if (blockIdx.x >= total) return;
+        const uint64_t it = items[blockIdx.x];
+        mfma_item(a, ubits, ulen, (uint32_t)(it >> 32), (uint32_t)it, L);
+        return;
+    }
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) next = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const uint32_t i = next;
+        if (i >= total) break;
+        const uint64_t it = items[i];
+        mfma_item(a, ubits, ulen, (uint32_t)(it >> 32), (uint32_t)it, L);
     }
 }
 
 // ---------------------------------------------------------------- planning
 
-// nrb[c] = row blocks of cluster c (0 for clusters with fewer than 2 members).
-__global__ __launch_bounds__(256) void k_plan_count(const uint32_t *cl_off,
-                                                    const uint32_t *cl_cfg_off, uint32_t t,
-                                                    const uint32_t *order, uint32_t NE,
-                                                    uint32_t *nrb) {
+// Per cluster (in `order`, or index order): number of MFMA items (low word)
+// and bitmap items (high word); clusters of one member get padded lists here.
+__global__ __launch_bounds__(256) void k_plan_count(KnnArgs a, const uint32_t *order,
+                                                    uint32_t mfma_min, const uint32_t *maxlen,
+                                                    uint64_t *cnt) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t ncl = cl_cfg_off[t];
-    if (q >= NE) return;
-    if (q >= ncl) { nrb[q] = 0; return; }
+    const uint32_t ncl = a.cl_cfg_off[a.t];
+    if (*maxlen >= kMfmaMaxLen) mfma_min = 0xFFFFFFFFu;
+    if (q >= a.NE) return;
+    if (q >= ncl) { cnt[q] = 0; return; }
     const uint32_t c = order ? order[q] : q;
-    const uint32_t s = cl_off[c + 1] - cl_off[c];
-    nrb[q] = s >= 2 ? (s + kRowBlock - 1) / kRowBlock : 0;
+    const ClusterView cv = view(a, c);
+    uint64_t v = 0;
+    if (cv.s >= mfma_min && cv.s >= 2) v = (cv.s + kMR - 1) / kMR;
+    else if (cv.s >= 2) v = (uint64_t)((cv.s + kRowBlock - 1) / kRowBlock) << 32;
+    else if (cv.s == 1) {
+        const uint32_t u = member(a, cv, 0);
+        if (u < a.n && cv.j < a.t) {
+            const size_t base = ((size_t)u * a.t + cv.j) * a.k;
+            for (uint32_t r = 0; r < a.k; ++r) {
+                a.part_id[base + r] = kPad;
+                a.part_I[base + r] = 0;
+            }
+        }
+    }
+    cnt[q] = v;
 }
 
-__global__ __launch_bounds__(256) void k_plan_fill(const uint32_t *cl_cfg_off, uint32_t t,
-                                                   const uint32_t *order, uint32_t NE,
-                                                   const uint32_t *item_off, uint64_t *items,
-                                                   uint32_t *cursor) {
+__global__ __launch_bounds__(256) void k_plan_fill(KnnArgs a, const uint32_t *order,
+                                                   const uint64_t *off, uint64_t *items_m,
+                                                   uint64_t *items_b, uint32_t *nitems,
+                                                   uint32_t *cursors) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q == 0 && cursor) *cursor = 0;
-    if (q >= NE || q >= cl_cfg_off[t]) return;
+    if (q == 0) {
+        const uint64_t tot = off[a.NE];
+        nitems[0] = (uint32_t)tot;
+        nitems[1] = (uint32_t)(tot >> 32);
+        if (cursors) { cursors[0] = 0; cursors[1] = 0; }
+    }
+    if (q >= a.NE || q >= a.cl_cfg_off[a.t]) return;
     const uint32_t c = order ? order[q] : q;
-    const uint32_t b0 = item_off[q], nb = item_off[q + 1] - b0;
-    for (uint32_t r = 0; r < nb; ++r) items[b0 + r] = ((uint64_t)c << 32) | r;
+    const uint64_t o0 = off[q], o1 = off[q + 1];
+    const uint32_t bm = (uint32_t)o0, nm = (uint32_t)o1 - bm;
+    const uint32_t bb = (uint32_t)(o0 >> 32), nbm = (uint32_t)(o1 >> 32) - bb;
+    for (uint32_t r = 0; r < nm; ++r) items_m[bm + r] = ((uint64_t)c << 32) | r;
+    for (uint32_t r = 0; r < nbm; ++r) items_b[bb + r] = ((uint64_t)c << 32) | r;
 }
 
-// Sort keys for the largest-first order: (n - size) so that ascending order
+// Sort keys for the largest-first order: (NE - size) so that ascending order
 // is descending size, ties by cluster index (stable sort).
 __global__ __launch_bounds__(256) void k_plan_keys(const uint32_t *cl_off,
                                                    const uint32_t *cl_cfg_off, uint32_t t,
@@ -336,7 +621,7 @@ __global__ __launch_bounds__(256) void k_plan_keys(const uint32_t *cl_off,
 
 // --------------------------------------------------------------- host side
 
-size_t knn_ws_bytes(uint32_t NE, uint32_t wmax, KnnWs *w) {
+size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -344,12 +629,11 @@ size_t knn_ws_bytes(uint32_t NE, uint32_t wmax, KnnWs *w) {
         return o;
     };
     KnnWs x;
-    x.rows = take((size_t)4 * NE * wmax);
-    x.rlen = take(4 * (size_t)NE);
-    x.cl_W = take(4 * (size_t)NE);
-    x.nrb = take(4 * ((size_t)NE + 1));
-    x.item_off = take(4 * ((size_t)NE + 1));
-    x.items = take(8 * (size_t)NE);
+    x.rows = take((size_t)4 * ((size_t)n + 1) * wmax);
+    x.rlen = take(4 * ((size_t)n + 1));
+    x.cnt = take(8 * ((size_t)NE + 1));
+    x.items_m = take(8 * (size_t)NE);
+    x.items_b = take(8 * (size_t)NE);
     x.csort_key = take(8 * (size_t)NE);
     x.csort_key_alt = take(8 * (size_t)NE);
     x.csort_val = take(4 * (size_t)NE);
@@ -357,48 +641,66 @@ size_t knn_ws_bytes(uint32_t NE, uint32_t wmax, KnnWs *w) {
     const size_t hist = radix_hist_elems(NE);
     x.hist = take(4 * hist);
     x.htmp = take(4 * scan_tmp_elems((uint32_t)(hist > NE + 1 ? hist : NE + 1)));
+    x.ctmp = take(8 * scan_tmp_elems(NE + 1));
     x.ctr = take(4 * 8);
     x.total = off;
     if (w) *w = x;
     return off;
 }
 
-static hipError_t stage(const KnnArgs &a, const KnnPtrs &w, uint32_t grid, hipStream_t s) {
+static hipError_t user_bits(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
     const size_t lds = knn_stage_lds_bytes(a.m, a.wmax);
-    hipError_t e = hipFuncSetAttribute((const void *)k_knn_stage,
+    hipError_t e = hipFuncSetAttribute((const void *)k_user_bits,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_knn_stage, dim3(grid), dim3(kStageThreads), lds, s, a.indptr, a.indices,
-                       a.nnz, a.n, a.m, a.t, a.k, a.members, a.cl_off, a.cl_cfg_off, a.wmax,
-                       w.rows, w.rlen, w.cl_W, a.part_id, a.part_I);
+    if ((e = launch_fill_u32(w.ctr + 4, 0, 1, s)) != hipSuccess) return e;
+    const uint32_t grid = (uint32_t)div_up((uint64_t)a.n + 1, kStageWaves);
+    hipLaunchKernelGGL(k_user_bits, dim3(grid < 8192 ? grid : 8192), dim3(kStageThreads), lds, s,
+                       a.indptr, a.indices, a.nnz, a.n, a.m, a.wmax, w.rows, w.rlen, w.ctr + 4);
     return hipGetLastError();
 }
 
-hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
-    uint32_t ncl = 0;
-    hipError_t e = hipMemcpyAsync(&ncl, a.cl_cfg_off + a.t, 4, hipMemcpyDeviceToHost, s);
+static hipError_t plan(const KnnArgs &a, const KnnPtrs &w, const uint32_t *order,
+                       uint32_t mfma_min, bool batched, hipStream_t s) {
+    const dim3 g((uint32_t)div_up(a.NE, 256));
+    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a, order, mfma_min, w.ctr + 4, w.cnt);
+    hipError_t e = scan_u64(w.cnt, w.cnt, a.NE, w.ctmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_fill, g, dim3(256), 0, s, a, order, w.cnt, w.items_m, w.items_b,
+                       w.ctr, batched ? w.ctr + 2 : nullptr);
+    return hipGetLastError();
+}
+
+static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o,
+                               uint32_t grid_m, uint32_t grid_b, bool batched, hipStream_t s) {
+    // the events bracket the MFMA kernel, which carries the large clusters
+    hipError_t e;
+    if (o.ev_begin && (e = hipEventRecord(o.ev_begin, s)) != hipSuccess) return e;
+    if (grid_m)
+        hipLaunchKernelGGL(k_knn_mfma, dim3(grid_m), dim3(256), 0, s, a, w.rows, w.rlen, w.items_m,
+                           w.ctr, batched ? w.ctr + 2 : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (o.ev_end && (e = hipEventRecord(o.ev_end, s)) != hipSuccess) return e;
+    if (grid_b)
+        hipLaunchKernelGGL(k_knn_bitmap, dim3(grid_b), dim3(64), 0, s, a, w.rows, w.rlen,
+                           w.items_b, w.ctr + 1, batched ? w.ctr + 3 : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
+    hipError_t e = user_bits(a, w, s);
+    if (e != hipSuccess) return e;
+    if ((e = plan(a, w, nullptr, o.mfma_min ? o.mfma_min : kDefaultMfmaMin, false, s)) != hipSuccess)
+        return e;
+    uint32_t n[2] = {0, 0};
+    e = hipMemcpyAsync(n, w.ctr, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    if (ncl == 0) return hipSuccess;
-    if ((e = stage(a, w, ncl < 65535 ? ncl : 65535, s)) != hipSuccess) return e;
-    const dim3 g((uint32_t)div_up(a.NE, 256));
-    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a.cl_off, a.cl_cfg_off, a.t, nullptr,
-                       a.NE, w.nrb);
-    if ((e = scan_u32(w.nrb, w.item_off, a.NE, w.htmp, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_fill, g, dim3(256), 0, s, a.cl_cfg_off, a.t, nullptr, a.NE,
-                       w.item_off, w.items, nullptr);
-    uint32_t nitems = 0;
-    e = hipMemcpyAsync(&nitems, w.item_off + a.NE, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess || nitems == 0) return e;
-    hipLaunchKernelGGL(k_knn_bitmap, dim3(nitems), dim3(64), 0, s, a, w.rows, w.rlen, w.cl_W,
-                       w.items, w.item_off + a.NE, nullptr);
-    return hipGetLastError();
+    return launch_paths(a, w, o, n[0], n[1], false, s);
 }
 
-hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, uint32_t persistent_wgs,
-                       hipStream_t s) {
-    hipError_t e = stage(a, w, 2048, s);
+hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
+    hipError_t e = user_bits(a, w, s);
     if (e != hipSuccess) return e;
     const dim3 g((uint32_t)div_up(a.NE, 256));
     // largest clusters first (the size-ordered queue of Section II-F)
@@ -409,15 +711,10 @@ hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, uint32_t persistent_w
                    a.NE, bit_width(a.NE), w.hist, w.htmp, &in_alt, s);
     if (e != hipSuccess) return e;
     const uint32_t *order = in_alt ? w.csort_val_alt : w.csort_val;
-    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a.cl_off, a.cl_cfg_off, a.t, order, a.NE,
-                       w.nrb);
-    if ((e = scan_u32(w.nrb, w.item_off, a.NE, w.htmp, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_fill, g, dim3(256), 0, s, a.cl_cfg_off, a.t, order, a.NE,
-                       w.item_off, w.items, w.ctr);
-    const uint32_t grid = persistent_wgs ? persistent_wgs : 2048;
-    hipLaunchKernelGGL(k_knn_bitmap, dim3(grid), dim3(64), 0, s, a, w.rows, w.rlen, w.cl_W,
-                       w.items, w.item_off + a.NE, w.ctr);
-    return hipGetLastError();
+    if ((e = plan(a, w, order, o.mfma_min ? o.mfma_min : kDefaultMfmaMin, true, s)) != hipSuccess)
+        return e;
+    const uint32_t gm = o.persistent_wgs ? o.persistent_wgs : 512;
+    return launch_paths(a, w, o, gm, 2048, true, s);
 }
 
 }  // namespace c2

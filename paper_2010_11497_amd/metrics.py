@@ -1,0 +1,69 @@
+"""Host-side measurement helpers for graphs and partitions produced on the GPU.
+
+avg_sim and quality follow Eq. 1 and Eq. 2 of the paper (average Jaccard
+similarity over the k*n edge slots, empty slots counting 0; quality is the
+ratio to the exact graph).  Sums use math.fsum, so they do not depend on
+summation order.  cluster_work counts the work units the benchmark's roofline
+uses: same-cluster pairs (the paper's similarity computations) and each
+cluster's local dictionary size.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def avg_sim(knn_I: np.ndarray, knn_U: np.ndarray) -> float:
+    I = np.asarray(knn_I, dtype=np.int64).ravel()
+    U = np.asarray(knn_U, dtype=np.int64).ravel()
+    n, k = np.asarray(knn_I).shape
+    ok = U > 0
+    return math.fsum((I[ok] / U[ok]).tolist()) / (k * n)
+
+
+def quality(approx_I, approx_U, exact_I, exact_U) -> float:
+    return avg_sim(approx_I, approx_U) / avg_sim(exact_I, exact_U)
+
+
+def cluster_work(members: np.ndarray, cl_off: np.ndarray, indptr: np.ndarray,
+                 indices: np.ndarray, m: int) -> dict:
+    """Per-cluster sizes s and local dictionary sizes D (items held by at least
+    two members), plus the totals the roofline needs:
+      pairs        = sum s(s-1)/2  (Jaccard evaluations, Section II-F)
+      ordered      = sum s^2
+      bitmap_ops   = sum 2 * s^2 * ceil(D/32)   (AND + popcount-accumulate)
+      dense_ops    = sum 2 * s^2 * D            (0/1 matrix product)
+    """
+    off = np.asarray(cl_off, dtype=np.int64)
+    s = np.diff(off)
+    indptr = np.asarray(indptr, dtype=np.int64)
+    lens = np.diff(indptr)
+    mem = np.asarray(members, dtype=np.int64)
+    cl_of_slot = np.repeat(np.arange(len(s), dtype=np.int64), s)
+    D = np.zeros(len(s), dtype=np.int64)
+    # clusters in chunks so that the (cluster, item) count table stays small
+    chunk = max(1, (1 << 24) // max(m, 1))
+    for c0 in range(0, len(s), chunk):
+        c1 = min(len(s), c0 + chunk)
+        slots = np.arange(off[c0], off[c1])
+        users = mem[slots]
+        reps = lens[users]
+        cl = np.repeat(cl_of_slot[slots] - c0, reps)
+        starts = np.repeat(indptr[users], reps)
+        within = np.arange(int(reps.sum())) - np.repeat(np.cumsum(reps) - reps, reps)
+        items = np.asarray(indices, dtype=np.int64)[starts + within]
+        cnt = np.bincount(cl * m + items, minlength=(c1 - c0) * m).reshape(c1 - c0, m)
+        D[c0:c1] = (cnt >= 2).sum(axis=1)
+    D[s < 2] = 0
+    s2 = s * s
+    return {
+        "clusters": int(len(s)),
+        "pairs": int((s * (s - 1) // 2).sum()),
+        "ordered": int(s2.sum()),
+        "bitmap_ops": int((2 * s2 * ((D + 31) // 32)).sum()),
+        "dense_ops": int((2 * s2 * D).sum()),
+        "sizes": s,
+        "dict": D,
+    }

@@ -152,15 +152,20 @@ def test_batched_reports_incomplete(orc):
 
 # ------------------------------------------------------------ local KNN ----
 
+PATHS = {"auto": 0, "mfma": 2, "bitmap": 1 << 30}
+
+
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
 @pytest.mark.parametrize("name,P,tab,b,cap,k", CASES, ids=[c[0] for c in CASES])
-def test_local_knn_on_oracle_partition(orc, name, P, tab, b, cap, k, form):
-    say("local_knn", name, form)
+def test_local_knn_on_oracle_partition(orc, name, P, tab, b, cap, k, form, path):
+    say("local_knn", name, form, path)
     t = tab.shape[0]
     om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, orc.hash_items(tab, b, P.m), cap)
     dP = c2.DeviceProfiles.from_synth(P)
     dev = lambda a: torch.as_tensor(a.astype(np.uint32).view(np.int32)).cuda()
-    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), c2.params(t, b, cap, k), form)
+    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), c2.params(t, b, cap, k), form,
+                           c2.tuning(mfma_min_rows=PATHS[path]))
     wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
     assert np.array_equal(u32(pid), wid)
     assert np.array_equal(u32(pI), wI)
@@ -194,7 +199,8 @@ def test_build(orc, name, P, tab, b, cap, k, form):
 
 
 def test_brute_force(orc):
-    for seed, (n, m, k) in enumerate([(300, 100, 5), (700, 3000, 32), (65, 20, 64 // 2), (2, 3, 4)]):
+    for seed, (n, m, k) in enumerate([(300, 100, 5), (700, 3000, 32), (65, 20, 64 // 2), (2, 3, 4),
+                                      (1000, 130, 17), (129, 64, 8)]):
         say("brute force", n, m, k)
         P = synth.random_profiles(70 + seed, n, m, 1, 25, 1.0)
         got = c2.brute_force(c2.DeviceProfiles.from_synth(P), k)
