@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -161,6 +163,14 @@ def main():
         all(np.array_equal(a, b) for a, b in zip(out_graph, out_p))
     if not same:
         raise SystemExit("forms disagree: graph, batched and plain builds differ")
+
+    if args.calibrate_copy_mb:
+        src = torch.empty(args.calibrate_copy_mb << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB x 3" % args.calibrate_copy_mb)
 
     quality = None
     if not args.no_quality:

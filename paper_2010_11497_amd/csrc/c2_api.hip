@@ -131,6 +131,10 @@ KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
     k.cnt = u64(w.cnt);
     k.items_m = u64(w.items_m);
     k.items_b = u64(w.items_b);
+    k.slots = u32(w.slots);
+    k.sbase = u32(w.sbase);
+    k.rb_done = u32(w.rb_done);
+    k.skeys = u64(w.skeys);
     k.ctmp = u64(w.ctmp);
     k.csort_key = u64(w.csort_key);
     k.csort_key_alt = u64(w.csort_key_alt);

@@ -65,7 +65,19 @@ C2_DEV uint32_t group_min_above(const int64_t *indptr, const uint32_t *indices, 
     uint64_t a, e;
     row_range(indptr, u, nnz, a, e);
     uint32_t best = b;
-    for (uint64_t p = a + gl; p < e; p += G) {
+    // four independent index -> bucket gathers in flight per lane
+    uint64_t p = a + gl;
+    for (; p + 3 * G < e; p += 4 * G) {
+        const uint32_t i0 = indices[p], i1 = indices[p + G], i2 = indices[p + 2 * G],
+                       i3 = indices[p + 3 * G];
+        const uint32_t h0 = i0 < m ? bucket_j[i0] : b, h1 = i1 < m ? bucket_j[i1] : b;
+        const uint32_t h2 = i2 < m ? bucket_j[i2] : b, h3 = i3 < m ? bucket_j[i3] : b;
+        if (h0 >= thr && h0 < best) best = h0;
+        if (h1 >= thr && h1 < best) best = h1;
+        if (h2 >= thr && h2 < best) best = h2;
+        if (h3 >= thr && h3 < best) best = h3;
+    }
+    for (; p < e; p += G) {
         const uint32_t i = indices[p];
         if (i < m) {
             const uint32_t h = bucket_j[i];

@@ -64,12 +64,14 @@ struct KnnArgs {
     uint32_t *part_id, *part_I;
 };
 struct KnnWs {
-    size_t rows, rlen, cnt, items_m, items_b, csort_key, csort_key_alt, csort_val, csort_val_alt,
-        hist, htmp, ctmp, ctr, total;
+    size_t rows, rlen, cnt, items_m, items_b, slots, sbase, rb_done, skeys, csort_key,
+        csort_key_alt, csort_val, csort_val_alt, hist, htmp, ctmp, ctr, total;
 };
 struct KnnPtrs {
     uint32_t *rows, *rlen;
     uint64_t *cnt, *items_m, *items_b;
+    uint32_t *slots, *sbase, *rb_done;
+    uint64_t *skeys;
     uint64_t *csort_key, *csort_key_alt;
     uint32_t *csort_val, *csort_val_alt, *hist, *htmp;
     uint64_t *ctmp;

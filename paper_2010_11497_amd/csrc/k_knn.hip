@@ -24,8 +24,10 @@ constexpr uint32_t kMR = 128;        // rows per MFMA work item (row owners)
 constexpr uint32_t kMC = 128;        // columns per MFMA step
 constexpr int kOpStride = 80;        // bytes per staged 64-item row (padded: no bank conflicts)
 constexpr int kTileStride = 132;     // u32 per row of the transposed result tile
-constexpr uint32_t kDefaultMfmaMin = 96;
+constexpr uint32_t kDefaultMfmaMin = 2;
 constexpr uint32_t kPf = 8;          // chunks of bit rows prefetched ahead (MFMA path)
+constexpr uint32_t kGroupTiles = 4;  // column tiles per work item before a row block is split
+constexpr uint32_t kMaxGroups = 4;   // column groups a row block is split into at most
 
 // Words per bit row: the item universe padded to a multiple of 64 * kPf items,
 // so the MFMA K loop runs whole unrolled groups.
@@ -77,7 +79,13 @@ __global__ __launch_bounds__(kStageThreads) void k_user_bits(const int64_t *__re
         if (p1 - p0 > longest) longest = (uint32_t)(p1 - p0);
         wave_sync();
     }
-    if (lane == 0 && longest) atomicMax(maxlen, longest);
+    // one atomic per block (the grid is capped), not per user
+    __shared__ uint32_t bmax;
+    if (threadIdx.x == 0) bmax = 0;
+    __syncthreads();
+    if (lane == 0 && longest) atomicMax(&bmax, longest);
+    __syncthreads();
+    if (threadIdx.x == 0 && bmax) atomicMax(maxlen, bmax);
 }
 
 // --------------------------------------------------------------- selection
@@ -370,12 +378,12 @@ C2_DEV bool beats(uint32_t I, uint32_t U, uint32_t uid, uint64_t hk) {
 struct KeyHeap {
     uint64_t *hk;  // [kMaxK][kMR], minor index = owner
     uint32_t me, k, cnt;
-    uint64_t root;
+    uint64_t root;  // valid once full
+    float sigma;    // key_T / (2^32 - 1 + key_T): I >= sigma * (|P_u| + |P_v|) is necessary
 
     C2_DEV uint64_t get(uint32_t i) const { return hk[i * kMR + me]; }
     C2_DEV void put(uint32_t i, uint64_t v) { hk[i * kMR + me] = v; }
-    C2_DEV void sift_down(uint64_t v, uint32_t size) {
-        uint32_t pos = 0;
+    C2_DEV void sift_down(uint32_t pos, uint64_t v, uint32_t size) {
         for (;;) {
             uint32_t l = 2 * pos + 1;
             if (l >= size) break;
@@ -391,26 +399,52 @@ struct KeyHeap {
         put(pos, v);
     }
     C2_DEV bool full() const { return cnt >= k; }
+    C2_DEV void set_root() {
+        root = get(0);
+        const float kt = (float)(uint32_t)(root >> 32);
+        sigma = kt / (4294967295.0f + kt);
+    }
+    // Until the heap holds k entries, entries are appended and then heapified
+    // once; afterwards v replaces the root (the caller checked it beats it).
     C2_DEV void insert(uint64_t v) {
         if (cnt < k) {
-            uint32_t pos = cnt++;
-            while (pos > 0) {
-                const uint32_t par = (pos - 1) >> 1;
-                const uint64_t pv = get(par);
-                if (pv <= v) break;
-                put(pos, pv);
-                pos = par;
+            put(cnt++, v);
+            if (cnt == k) {
+                for (int i = (int)k / 2 - 1; i >= 0; --i) sift_down((uint32_t)i, get(i), k);
+                set_root();
             }
-            put(pos, v);
         } else {
-            sift_down(v, k);
+            sift_down(0, v, k);
+            set_root();
         }
-        root = get(0);
     }
 };
 
-C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *ulen, uint32_t c,
-                      uint32_t rb, MfmaLds &L) {
+// Necessary condition for a candidate to beat the root, in fp32 with a margin
+// that covers rounding: J > J_T implies I > sigma_T * (|P_u| + |P_v|).
+C2_DEV bool may_beat(uint32_t I, uint32_t S, float sigma) {
+    return (float)I >= sigma * (float)S * 0.999999f;
+}
+
+// Work item of the MFMA path: cluster c, row block rb, column group g of ng.
+// A row block whose cluster spans more than kGroupTiles column tiles is split
+// into ng <= kMaxGroups items over disjoint column ranges; each leaves its
+// rows' k best (sorted keys) in scratch, and the item that finishes last
+// merges them.  No item waits for another.
+C2_DEV uint64_t mfma_item_code(uint32_t c, uint32_t rb, uint32_t g, uint32_t ng) {
+    return ((uint64_t)c << 32) | ((uint64_t)rb << 8) | (g << 4) | (ng - 1);
+}
+
+struct MfmaScratch {
+    uint64_t *keys;       // [slot][kMR][kMaxK]
+    uint32_t *rb_done;    // per (cluster, row block) of a split row block
+    const uint32_t *sbase;  // first slot of each cluster
+};
+
+C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *ulen,
+                      const MfmaScratch &sc, uint64_t code, MfmaLds &L) {
+    const uint32_t c = (uint32_t)(code >> 32), rb = (uint32_t)code >> 8;
+    const uint32_t g = ((uint32_t)code >> 4) & 15u, ng = ((uint32_t)code & 15u) + 1;
     const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
     const uint32_t wr = w >> 1, wc = w & 1;
     const ClusterView cv = view(a, c);
@@ -426,8 +460,11 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     h.k = a.k;
     h.cnt = 0;
     h.root = 0;
+    h.sigma = 0.0f;
     const uint32_t hl = (lane >> 5) * 16;  // byte offset of this lane's 16 k-values
-    for (uint32_t cb = 0; cb * kMC < s; ++cb) {
+    const uint32_t tiles = (s + kMC - 1) / kMC, per = (tiles + ng - 1) / ng;
+    const uint32_t cb_end = (g + 1) * per < tiles ? (g + 1) * per : tiles;
+    for (uint32_t cb = g * per; cb < cb_end; ++cb) {
         // staged row of this thread: owner row t, or column t - 128
         const uint32_t us = t < kMR ? ur : member(a, cv, cb * kMC + (t - kMR));
         const uint64_t *src = reinterpret_cast<const uint64_t *>(ubits + (size_t)us * W);
@@ -495,8 +532,10 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
                     for (int e = 0; e < 8; ++e) {
                         const uint32_t q = q8 + e;
                         const uint32_t I = (pr[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                        const uint32_t S = Lr + L.clen[q];
                         const bool ok = q < ncol && q != self &&
-                                        (!h.full() || beats(I, Lr + L.clen[q] - I, L.cuid[q], h.root));
+                                        (!h.full() || (may_beat(I, S, h.sigma) &&
+                                                       beats(I, S - I, L.cuid[q], h.root)));
                         if (ok) msk[q >> 5] |= 1u << (q & 31);
                     }
                 }
@@ -517,33 +556,88 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
         }
         __syncthreads();
     }
-    if (owner && cv.j < a.t) {
-        const size_t base = ((size_t)ur * a.t + cv.j) * a.k;
-        uint32_t *oid = a.part_id + base, *oI = a.part_I + base;
-        for (uint32_t r = h.cnt; r < a.k; ++r) {
-            oid[r] = kPad;
-            oI[r] = 0;
+    // fewer than k candidates: the appended entries were never heapified
+    if (owner && h.cnt < h.k)
+        for (int i = (int)h.cnt / 2 - 1; i >= 0; --i) h.sift_down((uint32_t)i, h.get(i), h.cnt);
+    if (ng == 1) {
+        if (owner && cv.j < a.t) {
+            const size_t base = ((size_t)ur * a.t + cv.j) * a.k;
+            uint32_t *oid = a.part_id + base, *oI = a.part_I + base;
+            for (uint32_t r = h.cnt; r < a.k; ++r) {
+                oid[r] = kPad;
+                oI[r] = 0;
+            }
+            for (uint32_t size = h.cnt; size > 0; --size) {
+                const uint64_t v = h.get(0);
+                const uint32_t uid = 0xFFFFFFFFu - (uint32_t)v;
+                oid[size - 1] = uid;
+                oI[size - 1] = key_to_I((uint32_t)(v >> 32), Lr + ulen[uid]);
+                if (size > 1) h.sift_down(0, h.get(size - 1), size - 1);
+            }
         }
+        return;
+    }
+    // split row block: leave this group's sorted keys (0 = none) in scratch
+    const uint32_t slot0 = sc.sbase[c] + rb * ng;
+    if (owner) {
+        uint64_t *out = sc.keys + ((size_t)(slot0 + g) * kMR + t) * kMaxK;
+        for (uint32_t r = h.cnt; r < a.k; ++r) out[r] = 0;
         for (uint32_t size = h.cnt; size > 0; --size) {
-            const uint64_t v = h.get(0);
+            out[size - 1] = h.get(0);
+            if (size > 1) h.sift_down(0, h.get(size - 1), size - 1);
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    __shared__ uint32_t last;
+    if (t == 0) last = atomicAdd(&sc.rb_done[slot0], 1u) == ng - 1;
+    __syncthreads();
+    if (!last || !owner || cv.j >= a.t) return;
+    __threadfence();
+    // the last group merges the ng sorted lists of each row (disjoint columns)
+    const uint64_t *in = sc.keys + ((size_t)slot0 * kMR + t) * kMaxK;
+    uint32_t ptr[kMaxGroups];
+    uint64_t head[kMaxGroups];
+#pragma unroll
+    for (uint32_t q = 0; q < kMaxGroups; ++q) {
+        ptr[q] = 0;
+        head[q] = q < ng ? in[(size_t)q * kMR * kMaxK] : 0;
+    }
+    const size_t base = ((size_t)ur * a.t + cv.j) * a.k;
+    for (uint32_t r = 0; r < a.k; ++r) {
+        uint32_t best = 0;
+#pragma unroll
+        for (uint32_t q = 1; q < kMaxGroups; ++q)
+            if (head[q] > head[best]) best = q;
+        uint64_t v = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kMaxGroups; ++q)
+            if (q == best) {
+                v = head[q];
+                ++ptr[q];
+                head[q] = (v != 0 && ptr[q] < a.k) ? in[(size_t)q * kMR * kMaxK + ptr[q]] : 0;
+            }
+        if (v == 0) {
+            a.part_id[base + r] = kPad;
+            a.part_I[base + r] = 0;
+        } else {
             const uint32_t uid = 0xFFFFFFFFu - (uint32_t)v;
-            oid[size - 1] = uid;
-            oI[size - 1] = key_to_I((uint32_t)(v >> 32), Lr + ulen[uid]);
-            if (size > 1) h.sift_down(h.get(size - 1), size - 1);
+            a.part_id[base + r] = uid;
+            a.part_I[base + r] = key_to_I((uint32_t)(v >> 32), Lr + ulen[uid]);
         }
     }
 }
 
 __global__ __launch_bounds__(256, 2) void k_knn_mfma(KnnArgs a, const uint32_t *ubits,
-                                                     const uint32_t *ulen, const uint64_t *items,
+                                                     const uint32_t *ulen, MfmaScratch sc,
+                                                     const uint64_t *items,
                                                      const uint32_t *n_items, uint32_t *cursor) {
     __shared__ MfmaLds L;
     __shared__ uint32_t next;
     const uint32_t total = *n_items;
     if (!cursor) {
         if (blockIdx.x >= total) return;
-        const uint64_t it = items[blockIdx.x];
-        mfma_item(a, ubits, ulen, (uint32_t)(it >> 32), (uint32_t)it, L);
+        mfma_item(a, ubits, ulen, sc, items[blockIdx.x], L);
         return;
     }
     for (;;) {
@@ -552,29 +646,42 @@ __global__ __launch_bounds__(256, 2) void k_knn_mfma(KnnArgs a, const uint32_t *
         __syncthreads();
         const uint32_t i = next;
         if (i >= total) break;
-        const uint64_t it = items[i];
-        mfma_item(a, ubits, ulen, (uint32_t)(it >> 32), (uint32_t)it, L);
+        mfma_item(a, ubits, ulen, sc, items[i], L);
     }
 }
 
 // ---------------------------------------------------------------- planning
 
+// Column groups of an MFMA cluster of s members.
+C2_DEV uint32_t mfma_groups(uint32_t s) {
+    const uint32_t tiles = (s + kMC - 1) / kMC;
+    if (tiles <= kGroupTiles) return 1;
+    const uint32_t ng = (tiles + kGroupTiles - 1) / kGroupTiles;
+    return ng < kMaxGroups ? ng : kMaxGroups;
+}
+
 // Per cluster (in `order`, or index order): number of MFMA items (low word)
-// and bitmap items (high word); clusters of one member get padded lists here.
+// and bitmap items (high word), and the scratch slots of split row blocks;
+// clusters of one member get padded lists here.
 __global__ __launch_bounds__(256) void k_plan_count(KnnArgs a, const uint32_t *order,
                                                     uint32_t mfma_min, const uint32_t *maxlen,
-                                                    uint64_t *cnt) {
+                                                    uint64_t *cnt, uint32_t *slots) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ncl = a.cl_cfg_off[a.t];
     if (*maxlen >= kMfmaMaxLen) mfma_min = 0xFFFFFFFFu;
     if (q >= a.NE) return;
-    if (q >= ncl) { cnt[q] = 0; return; }
+    if (q >= ncl) { cnt[q] = 0; slots[q] = 0; return; }
     const uint32_t c = order ? order[q] : q;
     const ClusterView cv = view(a, c);
     uint64_t v = 0;
-    if (cv.s >= mfma_min && cv.s >= 2) v = (cv.s + kMR - 1) / kMR;
-    else if (cv.s >= 2) v = (uint64_t)((cv.s + kRowBlock - 1) / kRowBlock) << 32;
-    else if (cv.s == 1) {
+    uint32_t sl = 0;
+    if (cv.s >= mfma_min && cv.s >= 2) {
+        const uint32_t ng = mfma_groups(cv.s);
+        v = (uint64_t)((cv.s + kMR - 1) / kMR) * ng;
+        sl = ng > 1 ? (uint32_t)v : 0;
+    } else if (cv.s >= 2) {
+        v = (uint64_t)((cv.s + kRowBlock - 1) / kRowBlock) << 32;
+    } else if (cv.s == 1) {
         const uint32_t u = member(a, cv, 0);
         if (u < a.n && cv.j < a.t) {
             const size_t base = ((size_t)u * a.t + cv.j) * a.k;
@@ -585,12 +692,14 @@ __global__ __launch_bounds__(256) void k_plan_count(KnnArgs a, const uint32_t *o
         }
     }
     cnt[q] = v;
+    slots[q] = sl;
 }
 
 __global__ __launch_bounds__(256) void k_plan_fill(KnnArgs a, const uint32_t *order,
-                                                   const uint64_t *off, uint64_t *items_m,
-                                                   uint64_t *items_b, uint32_t *nitems,
-                                                   uint32_t *cursors) {
+                                                   const uint64_t *off, const uint32_t *slot_off,
+                                                   uint64_t *items_m, uint64_t *items_b,
+                                                   uint32_t *sbase, uint32_t *rb_done,
+                                                   uint32_t *nitems, uint32_t *cursors) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q == 0) {
         const uint64_t tot = off[a.NE];
@@ -603,7 +712,15 @@ __global__ __launch_bounds__(256) void k_plan_fill(KnnArgs a, const uint32_t *or
     const uint64_t o0 = off[q], o1 = off[q + 1];
     const uint32_t bm = (uint32_t)o0, nm = (uint32_t)o1 - bm;
     const uint32_t bb = (uint32_t)(o0 >> 32), nbm = (uint32_t)(o1 >> 32) - bb;
-    for (uint32_t r = 0; r < nm; ++r) items_m[bm + r] = ((uint64_t)c << 32) | r;
+    if (nm) {
+        const uint32_t s = a.cl_off[c + 1] - a.cl_off[c];
+        const uint32_t ng = mfma_groups(s), nrb = nm / ng;
+        sbase[c] = slot_off[q];
+        for (uint32_t r = 0; r < nrb; ++r) {
+            for (uint32_t g = 0; g < ng; ++g) items_m[bm + r * ng + g] = mfma_item_code(c, r, g, ng);
+            if (ng > 1) rb_done[slot_off[q] + r * ng] = 0;
+        }
+    }
     for (uint32_t r = 0; r < nbm; ++r) items_b[bb + r] = ((uint64_t)c << 32) | r;
 }
 
@@ -621,6 +738,11 @@ __global__ __launch_bounds__(256) void k_plan_keys(const uint32_t *cl_off,
 
 // --------------------------------------------------------------- host side
 
+// Scratch slots of split row blocks: a cluster is split only when it spans
+// more than kGroupTiles column tiles (s > 512), and then takes
+// ceil(s/128) * ng <= s/25 slots.
+size_t knn_max_slots(uint32_t NE) { return (size_t)NE / 25 + 8; }
+
 size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -632,7 +754,12 @@ size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w) {
     x.rows = take((size_t)4 * ((size_t)n + 1) * wmax);
     x.rlen = take(4 * ((size_t)n + 1));
     x.cnt = take(8 * ((size_t)NE + 1));
-    x.items_m = take(8 * (size_t)NE);
+    x.items_m = take(8 * ((size_t)NE + NE / 16 + 64));
+    x.slots = take(4 * ((size_t)NE + 1));
+    x.sbase = take(4 * (size_t)NE);
+    const size_t nslot = knn_max_slots(NE);
+    x.rb_done = take(4 * nslot);
+    x.skeys = take(8 * nslot * kMR * kMaxK);
     x.items_b = take(8 * (size_t)NE);
     x.csort_key = take(8 * (size_t)NE);
     x.csort_key_alt = take(8 * (size_t)NE);
@@ -655,7 +782,7 @@ static hipError_t user_bits(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
     if (e != hipSuccess) return e;
     if ((e = launch_fill_u32(w.ctr + 4, 0, 1, s)) != hipSuccess) return e;
     const uint32_t grid = (uint32_t)div_up((uint64_t)a.n + 1, kStageWaves);
-    hipLaunchKernelGGL(k_user_bits, dim3(grid < 8192 ? grid : 8192), dim3(kStageThreads), lds, s,
+    hipLaunchKernelGGL(k_user_bits, dim3(grid < 512 ? grid : 512), dim3(kStageThreads), lds, s,
                        a.indptr, a.indices, a.nnz, a.n, a.m, a.wmax, w.rows, w.rlen, w.ctr + 4);
     return hipGetLastError();
 }
@@ -663,11 +790,13 @@ static hipError_t user_bits(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
 static hipError_t plan(const KnnArgs &a, const KnnPtrs &w, const uint32_t *order,
                        uint32_t mfma_min, bool batched, hipStream_t s) {
     const dim3 g((uint32_t)div_up(a.NE, 256));
-    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a, order, mfma_min, w.ctr + 4, w.cnt);
+    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a, order, mfma_min, w.ctr + 4, w.cnt,
+                       w.slots);
     hipError_t e = scan_u64(w.cnt, w.cnt, a.NE, w.ctmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_fill, g, dim3(256), 0, s, a, order, w.cnt, w.items_m, w.items_b,
-                       w.ctr, batched ? w.ctr + 2 : nullptr);
+    if ((e = scan_u32(w.slots, w.slots, a.NE, w.htmp, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_fill, g, dim3(256), 0, s, a, order, w.cnt, w.slots, w.items_m,
+                       w.items_b, w.sbase, w.rb_done, w.ctr, batched ? w.ctr + 2 : nullptr);
     return hipGetLastError();
 }
 
@@ -676,9 +805,13 @@ static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts
     // the events bracket the MFMA kernel, which carries the large clusters
     hipError_t e;
     if (o.ev_begin && (e = hipEventRecord(o.ev_begin, s)) != hipSuccess) return e;
+    MfmaScratch sc;
+    sc.keys = w.skeys;
+    sc.rb_done = w.rb_done;
+    sc.sbase = w.sbase;
     if (grid_m)
-        hipLaunchKernelGGL(k_knn_mfma, dim3(grid_m), dim3(256), 0, s, a, w.rows, w.rlen, w.items_m,
-                           w.ctr, batched ? w.ctr + 2 : nullptr);
+        hipLaunchKernelGGL(k_knn_mfma, dim3(grid_m), dim3(256), 0, s, a, w.rows, w.rlen, sc,
+                           w.items_m, w.ctr, batched ? w.ctr + 2 : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (o.ev_end && (e = hipEventRecord(o.ev_end, s)) != hipSuccess) return e;
     if (grid_b)

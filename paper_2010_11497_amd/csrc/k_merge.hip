@@ -10,39 +10,65 @@
 
 namespace c2 {
 
+constexpr int kMergeThreads = 64;
+
+// One wave of 64 lanes serves 64/G users.  The wave first copies its users'
+// t lists (contiguous in part_*) into LDS with U computed, coalesced; the
+// selection loop then runs from LDS.
 template <int G>
-__global__ __launch_bounds__(256) void k_merge(const int64_t *__restrict__ indptr, uint64_t nnz,
-                                               uint32_t n, uint32_t t, uint32_t k,
-                                               const uint32_t *__restrict__ part_id,
-                                               const uint32_t *__restrict__ part_I,
-                                               uint32_t *__restrict__ knn_id,
-                                               uint32_t *__restrict__ knn_I,
-                                               uint32_t *__restrict__ knn_U) {
-    const uint64_t gth = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t u = (uint32_t)(gth / G);
-    const uint32_t j = threadIdx.x % G;
+__global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restrict__ indptr,
+                                                         uint64_t nnz, uint32_t n, uint32_t t,
+                                                         uint32_t k,
+                                                         const uint32_t *__restrict__ part_id,
+                                                         const uint32_t *__restrict__ part_I,
+                                                         uint32_t *__restrict__ knn_id,
+                                                         uint32_t *__restrict__ knn_I,
+                                                         uint32_t *__restrict__ knn_U) {
+    constexpr int UPW = kMergeThreads / G;  // users per wave
+    __shared__ uint32_t sv[UPW * G * kMaxK], sI[UPW * G * kMaxK], sU[UPW * G * kMaxK];
+    const uint32_t lane = threadIdx.x;
+    const uint64_t u0 = (uint64_t)blockIdx.x * UPW;
+    // stage: entries of users u0 .. u0+UPW-1, list j, slot r at ((ul*G + j)*k + r)
+    {
+        const uint32_t nu = (uint32_t)(u0 + UPW <= n ? UPW : (u0 < n ? n - u0 : 0));
+        const uint32_t total = nu * t * k;
+        const size_t base = (size_t)u0 * t * k;
+        for (uint32_t e = lane; e < total; e += kMergeThreads) {
+            const uint32_t ul = e / (t * k), rem = e % (t * k);
+            const uint32_t j = rem / k, r = rem % k;
+            const uint32_t d = (ul * G + j) * k + r;
+            const uint32_t v = part_id[base + e];
+            uint32_t I = 0, U = 0, vv = kPad;
+            if (v != kPad && v < n) {
+                uint64_t a0, a1, b0, b1;
+                row_range(indptr, (uint32_t)(u0 + ul), nnz, a0, a1);
+                row_range(indptr, v, nnz, b0, b1);
+                I = part_I[base + e];
+                U = (uint32_t)(a1 - a0) + (uint32_t)(b1 - b0) - I;
+                vv = v;
+            }
+            sv[d] = vv;
+            sI[d] = I;
+            sU[d] = U;
+        }
+    }
+    __syncthreads();
+    const uint32_t ul = lane / G, j = lane % G;
+    const uint64_t u = u0 + ul;
     if (u >= n) return;
-    uint64_t a, e;
-    row_range(indptr, u, nnz, a, e);
-    const uint32_t Lu = (uint32_t)(e - a);
-    const size_t lbase = ((size_t)u * t + j) * k;
+    const uint32_t lb = (ul * G + j) * k;
     uint32_t ptr = 0, hv = kPad, hI = 0, hU = 0;
     auto load = [&]() {
         hv = kPad;
         if (j < t && ptr < k) {
-            const uint32_t v = part_id[lbase + ptr];
-            if (v != kPad && v < n) {
-                uint64_t va, ve;
-                row_range(indptr, v, nnz, va, ve);
-                hv = v;
-                hI = part_I[lbase + ptr];
-                hU = Lu + (uint32_t)(ve - va) - hI;
-            }
+            hv = sv[lb + ptr];
+            hI = sI[lb + ptr];
+            hU = sU[lb + ptr];
         }
     };
     load();
     uint32_t out = 0, last = kPad;
-    uint32_t *oid = knn_id + (size_t)u * k, *oI = knn_I + (size_t)u * k, *oU = knn_U + (size_t)u * k;
+    uint32_t *oid = knn_id + u * k, *oI = knn_I + u * k, *oU = knn_U + u * k;
     while (out < k) {
         bool ok = hv != kPad;
         uint32_t bI = hI, bU = hU, bv = hv, bj = j;
@@ -86,11 +112,11 @@ hipError_t launch_merge(const int64_t *indptr, uint64_t nnz, uint32_t n, uint32_
                         uint32_t *knn_I, uint32_t *knn_U, hipStream_t s) {
     uint32_t G = 1;
     while (G < t) G <<= 1;
-    const dim3 grid((uint32_t)div_up((uint64_t)n * G, 256));
+    const dim3 grid((uint32_t)div_up((uint64_t)n * G, kMergeThreads));
 #define C2_MERGE(GG)                                                                           \
     case GG:                                                                                   \
-        hipLaunchKernelGGL(k_merge<GG>, grid, dim3(256), 0, s, indptr, nnz, n, t, k, part_id, \
-                           part_I, knn_id, knn_I, knn_U);                                     \
+        hipLaunchKernelGGL(k_merge<GG>, grid, dim3(kMergeThreads), 0, s, indptr, nnz, n, t, k,  \
+                           part_id, part_I, knn_id, knn_I, knn_U);                           \
         break;
     switch (G) {
         C2_MERGE(1) C2_MERGE(2) C2_MERGE(4) C2_MERGE(8) C2_MERGE(16) C2_MERGE(32) C2_MERGE(64)

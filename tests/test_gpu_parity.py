@@ -285,3 +285,26 @@ def test_workload_full_parity(orc, name):
     want = orc.brute_force(P.indptr, P.indices, P.n, P.m, w.k, rows=rows, threads=THREADS)
     for g, ww in zip(bf, want):
         assert np.array_equal(u32(g)[rows], ww)
+
+
+def test_long_profiles_take_exact_fallback(orc):
+    # profiles of 2^15 items or more leave the 16-bit key range of the MFMA
+    # path; the general path must still match the oracle bit for bit
+    rng = np.random.Generator(np.random.PCG64(77))
+    m = 40000
+    sets = []
+    for u in range(150):
+        size = 33000 if u % 25 == 0 else int(rng.integers(5, 400))
+        sets.append(set(rng.choice(m, size=size, replace=False).tolist()))
+    P = synth.profiles_from_sets(sets, m)
+    k = 7
+    got = c2.brute_force(c2.DeviceProfiles.from_synth(P), k)
+    want = orc.brute_force(P.indptr, P.indices, P.n, P.m, k, threads=THREADS)
+    for g, w in zip(got, want):
+        assert np.array_equal(u32(g), w)
+    tab = synth.hash_tables(3, 78)
+    dP, dtab = gpu_inputs(P, tab)
+    got = c2.build(dP, dtab, c2.params(3, 4, 60, k), c2.FORM_BATCHED)
+    r = orc.build_graph(P.indptr, P.indices, P.n, P.m, tab, 4, 60, k, THREADS)
+    for g, w in zip(got, (r.knn_id, r.knn_I, r.knn_U)):
+        assert np.array_equal(u32(g), w)
