@@ -95,7 +95,9 @@ typedef struct c2_tuning {
                                  int8 MFMA path, smaller ones the bitmap path */
     uint32_t persistent_wgs;  /* workgroups of the persistent launch (batched form) */
     uint32_t split_rounds;    /* split rounds enqueued by the batched form */
-    uint32_t reserved;
+    uint32_t group_tiles;     /* MFMA path: a block of 128 rows whose cluster spans more than
+                                 this many 128-column tiles is split into up to 4 work items
+                                 over disjoint column ranges (default 4) */
     void *ev_knn_begin;       /* optional hipEvent_t (host handles, caller-owned): recorded on */
     void *ev_knn_end;         /* the stream right before / after the pairwise local-KNN kernel */
 } c2_tuning;

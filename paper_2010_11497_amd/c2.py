@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("mfma_min_rows", ctypes.c_uint32), ("persistent_wgs", ctypes.c_uint32),
-                ("split_rounds", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("split_rounds", ctypes.c_uint32), ("group_tiles", ctypes.c_uint32),
                 ("ev_knn_begin", ctypes.c_void_p), ("ev_knn_end", ctypes.c_void_p)]
 
 
@@ -137,10 +137,12 @@ def params(t, b, cap, k) -> Params:
     return Params(int(t), int(b), int(cap), int(k))
 
 
-def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0, events=None) -> Tuning:
+def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0, group_tiles=0,
+           events=None) -> Tuning:
     """events: optional (begin, end) torch.cuda.Event(enable_timing=True) pair
     recorded around the local-KNN kernel."""
-    tu = Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), 0, None, None)
+    tu = Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), int(group_tiles),
+                None, None)
     if events is not None:
         for ev in events:
             ev.record()           # materialise the underlying hipEvent_t

@@ -221,6 +221,7 @@ c2_status run_knn(const c2_profiles *P, const uint32_t *members, const uint32_t 
     if (tune) {
         o.persistent_wgs = tune->persistent_wgs;
         o.mfma_min = tune->mfma_min_rows;
+        o.group_tiles = tune->group_tiles;
         o.ev_begin = (hipEvent_t)tune->ev_knn_begin;
         o.ev_end = (hipEvent_t)tune->ev_knn_end;
     }

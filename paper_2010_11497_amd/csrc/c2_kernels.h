@@ -83,6 +83,7 @@ size_t knn_stage_lds_bytes(uint32_t m, uint32_t wmax);
 struct KnnOpts {
     uint32_t persistent_wgs = 0;
     uint32_t mfma_min = 0;
+    uint32_t group_tiles = 0;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
 hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s);

@@ -653,10 +653,10 @@ __global__ __launch_bounds__(256, 2) void k_knn_mfma(KnnArgs a, const uint32_t *
 // ---------------------------------------------------------------- planning
 
 // Column groups of an MFMA cluster of s members.
-C2_DEV uint32_t mfma_groups(uint32_t s) {
+C2_DEV uint32_t mfma_groups(uint32_t s, uint32_t group_tiles) {
     const uint32_t tiles = (s + kMC - 1) / kMC;
-    if (tiles <= kGroupTiles) return 1;
-    const uint32_t ng = (tiles + kGroupTiles - 1) / kGroupTiles;
+    if (tiles <= group_tiles) return 1;
+    const uint32_t ng = (tiles + group_tiles - 1) / group_tiles;
     return ng < kMaxGroups ? ng : kMaxGroups;
 }
 
@@ -664,8 +664,9 @@ C2_DEV uint32_t mfma_groups(uint32_t s) {
 // and bitmap items (high word), and the scratch slots of split row blocks;
 // clusters of one member get padded lists here.
 __global__ __launch_bounds__(256) void k_plan_count(KnnArgs a, const uint32_t *order,
-                                                    uint32_t mfma_min, const uint32_t *maxlen,
-                                                    uint64_t *cnt, uint32_t *slots) {
+                                                    uint32_t mfma_min, uint32_t group_tiles,
+                                                    const uint32_t *maxlen, uint64_t *cnt,
+                                                    uint32_t *slots) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ncl = a.cl_cfg_off[a.t];
     if (*maxlen >= kMfmaMaxLen) mfma_min = 0xFFFFFFFFu;
@@ -676,7 +677,7 @@ __global__ __launch_bounds__(256) void k_plan_count(KnnArgs a, const uint32_t *o
     uint64_t v = 0;
     uint32_t sl = 0;
     if (cv.s >= mfma_min && cv.s >= 2) {
-        const uint32_t ng = mfma_groups(cv.s);
+        const uint32_t ng = mfma_groups(cv.s, group_tiles);
         v = (uint64_t)((cv.s + kMR - 1) / kMR) * ng;
         sl = ng > 1 ? (uint32_t)v : 0;
     } else if (cv.s >= 2) {
@@ -696,7 +697,8 @@ __global__ __launch_bounds__(256) void k_plan_count(KnnArgs a, const uint32_t *o
 }
 
 __global__ __launch_bounds__(256) void k_plan_fill(KnnArgs a, const uint32_t *order,
-                                                   const uint64_t *off, const uint32_t *slot_off,
+                                                   uint32_t group_tiles, const uint64_t *off,
+                                                   const uint32_t *slot_off,
                                                    uint64_t *items_m, uint64_t *items_b,
                                                    uint32_t *sbase, uint32_t *rb_done,
                                                    uint32_t *nitems, uint32_t *cursors) {
@@ -714,7 +716,7 @@ __global__ __launch_bounds__(256) void k_plan_fill(KnnArgs a, const uint32_t *or
     const uint32_t bb = (uint32_t)(o0 >> 32), nbm = (uint32_t)(o1 >> 32) - bb;
     if (nm) {
         const uint32_t s = a.cl_off[c + 1] - a.cl_off[c];
-        const uint32_t ng = mfma_groups(s), nrb = nm / ng;
+        const uint32_t ng = mfma_groups(s, group_tiles), nrb = nm / ng;
         sbase[c] = slot_off[q];
         for (uint32_t r = 0; r < nrb; ++r) {
             for (uint32_t g = 0; g < ng; ++g) items_m[bm + r * ng + g] = mfma_item_code(c, r, g, ng);
@@ -739,9 +741,9 @@ __global__ __launch_bounds__(256) void k_plan_keys(const uint32_t *cl_off,
 // --------------------------------------------------------------- host side
 
 // Scratch slots of split row blocks: a cluster is split only when it spans
-// more than kGroupTiles column tiles (s > 512), and then takes
-// ceil(s/128) * ng <= s/25 slots.
-size_t knn_max_slots(uint32_t NE) { return (size_t)NE / 25 + 8; }
+// more than one column tile (s > 128), and then takes
+// ceil(s/128) * ng <= (s/128 + 1) * 4 < s/16 slots.
+size_t knn_max_slots(uint32_t NE) { return (size_t)NE / 16 + 8; }
 
 size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w) {
     size_t off = 0;
@@ -788,14 +790,16 @@ static hipError_t user_bits(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
 }
 
 static hipError_t plan(const KnnArgs &a, const KnnPtrs &w, const uint32_t *order,
-                       uint32_t mfma_min, bool batched, hipStream_t s) {
+                       const KnnOpts &o, bool batched, hipStream_t s) {
+    const uint32_t mfma_min = o.mfma_min ? o.mfma_min : kDefaultMfmaMin;
+    const uint32_t gt = o.group_tiles ? o.group_tiles : kGroupTiles;  // >= 1
     const dim3 g((uint32_t)div_up(a.NE, 256));
-    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a, order, mfma_min, w.ctr + 4, w.cnt,
+    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a, order, mfma_min, gt, w.ctr + 4, w.cnt,
                        w.slots);
     hipError_t e = scan_u64(w.cnt, w.cnt, a.NE, w.ctmp, s);
     if (e != hipSuccess) return e;
     if ((e = scan_u32(w.slots, w.slots, a.NE, w.htmp, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_fill, g, dim3(256), 0, s, a, order, w.cnt, w.slots, w.items_m,
+    hipLaunchKernelGGL(k_plan_fill, g, dim3(256), 0, s, a, order, gt, w.cnt, w.slots, w.items_m,
                        w.items_b, w.sbase, w.rb_done, w.ctr, batched ? w.ctr + 2 : nullptr);
     return hipGetLastError();
 }
@@ -823,8 +827,7 @@ static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts
 hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
     hipError_t e = user_bits(a, w, s);
     if (e != hipSuccess) return e;
-    if ((e = plan(a, w, nullptr, o.mfma_min ? o.mfma_min : kDefaultMfmaMin, false, s)) != hipSuccess)
-        return e;
+    if ((e = plan(a, w, nullptr, o, false, s)) != hipSuccess) return e;
     uint32_t n[2] = {0, 0};
     e = hipMemcpyAsync(n, w.ctr, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -844,8 +847,7 @@ hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hip
                    a.NE, bit_width(a.NE), w.hist, w.htmp, &in_alt, s);
     if (e != hipSuccess) return e;
     const uint32_t *order = in_alt ? w.csort_val_alt : w.csort_val;
-    if ((e = plan(a, w, order, o.mfma_min ? o.mfma_min : kDefaultMfmaMin, true, s)) != hipSuccess)
-        return e;
+    if ((e = plan(a, w, order, o, true, s)) != hipSuccess) return e;
     const uint32_t gm = o.persistent_wgs ? o.persistent_wgs : 512;
     return launch_paths(a, w, o, gm, 2048, true, s);
 }

@@ -28,28 +28,43 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
     __shared__ uint32_t sv[UPW * G * kMaxK], sI[UPW * G * kMaxK], sU[UPW * G * kMaxK];
     const uint32_t lane = threadIdx.x;
     const uint64_t u0 = (uint64_t)blockIdx.x * UPW;
-    // stage: entries of users u0 .. u0+UPW-1, list j, slot r at ((ul*G + j)*k + r)
+    // stage: entries of users u0 .. u0+UPW-1, list j, slot r at ((ul*G + j)*k + r);
+    // four entries per lane per step so that their dependent loads overlap
     {
         const uint32_t nu = (uint32_t)(u0 + UPW <= n ? UPW : (u0 < n ? n - u0 : 0));
         const uint32_t total = nu * t * k;
         const size_t base = (size_t)u0 * t * k;
-        for (uint32_t e = lane; e < total; e += kMergeThreads) {
-            const uint32_t ul = e / (t * k), rem = e % (t * k);
-            const uint32_t j = rem / k, r = rem % k;
-            const uint32_t d = (ul * G + j) * k + r;
-            const uint32_t v = part_id[base + e];
-            uint32_t I = 0, U = 0, vv = kPad;
-            if (v != kPad && v < n) {
-                uint64_t a0, a1, b0, b1;
-                row_range(indptr, (uint32_t)(u0 + ul), nnz, a0, a1);
-                row_range(indptr, v, nnz, b0, b1);
-                I = part_I[base + e];
-                U = (uint32_t)(a1 - a0) + (uint32_t)(b1 - b0) - I;
-                vv = v;
+        for (uint32_t e0 = 0; e0 < total; e0 += 4 * kMergeThreads) {
+            uint32_t v[4], I[4], lu[4], lv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t e = e0 + q * kMergeThreads + lane;
+                v[q] = e < total ? part_id[base + e] : kPad;
+                I[q] = e < total ? part_I[base + e] : 0;
             }
-            sv[d] = vv;
-            sI[d] = I;
-            sU[d] = U;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t e = e0 + q * kMergeThreads + lane;
+                lu[q] = lv[q] = 0;
+                if (e < total && v[q] < n) {
+                    uint64_t a0, a1, b0, b1;
+                    row_range(indptr, (uint32_t)(u0 + e / (t * k)), nnz, a0, a1);
+                    row_range(indptr, v[q], nnz, b0, b1);
+                    lu[q] = (uint32_t)(a1 - a0);
+                    lv[q] = (uint32_t)(b1 - b0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t e = e0 + q * kMergeThreads + lane;
+                if (e >= total) continue;
+                const uint32_t ul = e / (t * k), rem = e % (t * k);
+                const uint32_t d = (ul * G + rem / k) * k + rem % k;
+                const bool ok = v[q] != kPad && v[q] < n;
+                sv[d] = ok ? v[q] : kPad;
+                sI[d] = ok ? I[q] : 0;
+                sU[d] = ok ? lu[q] + lv[q] - I[q] : 0;
+            }
         }
     }
     __syncthreads();
