@@ -33,7 +33,7 @@ DEFAULT_WORKLOAD = "n6k_m3.7k"
 VALU_PEAK = 256 * 4 * 16 * 2.4e9      # int32 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 MFMA_I8_PEAK = 5.0e15                 # dense int8 MFMA ops/s
 KNN_KERNEL = "k_knn_mfma"
-MFMA_MIN = 96                         # clusters with at least this many members take the MFMA path
+MFMA_MIN_DEFAULT = 2                  # library default: clusters of >= 2 members take the MFMA path
 KNN_SOURCES = ["paper_2010_11497_amd/csrc/k_knn.hip", "paper_2010_11497_amd/csrc/c2_internal.h"]
 
 
@@ -120,9 +120,13 @@ def main():
     E = work["pairs"]
     log("clusters %d, Jaccard evals %d, max cluster %d" % (ncl, E, int(work["sizes"].max())))
 
-    # HIP-graph form of the batched build
+    # HIP-graph form of the batched build, with the autotuner's schedule if one
+    # was recorded for this workload
+    from paper_2010_11497_amd import autotune
+    tuned = autotune.load_table(w.name) or {}
+    log("tuning", tuned if tuned else "built-in defaults")
     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    g = c2.Graph(dP, dtab, p, c2.tuning(events=ev))
+    g = c2.Graph(dP, dtab, p, c2.tuning(events=ev, **tuned))
     for _ in range(args.warmup):
         g.launch()
     torch.cuda.synchronize()
@@ -147,13 +151,14 @@ def main():
     # batched (eager) and plain forms, same arithmetic
     def timed(form):
         ws = c2.workspace(dP, p, c2.OP_BUILD)
+        tu = c2.tuning(**tuned)
         out = None
         for _ in range(args.warmup):
-            out = c2.build(dP, dtab, p, form, ws=ws, out=out)
+            out = c2.build(dP, dtab, p, form, tu, ws=ws, out=out)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            out = c2.build(dP, dtab, p, form, ws=ws, out=out)
+            out = c2.build(dP, dtab, p, form, tu, ws=ws, out=out)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / args.steps, [c2.to_u32(x) for x in out]
     batched_ms, out_b = timed(c2.FORM_BATCHED)
@@ -179,7 +184,8 @@ def main():
         quality = metrics.quality(out_graph[1], out_graph[2], c2.to_u32(bf[1]), c2.to_u32(bf[2]))
         log("quality %.4f" % quality)
 
-    big = work["sizes"] >= MFMA_MIN
+    mfma_min = int(tuned.get("mfma_min_rows", MFMA_MIN_DEFAULT))
+    big = work["sizes"] >= mfma_min
     ops = int((2 * work["sizes"][big].astype(np.int64) ** 2 * work["dict"][big]).sum())
     achieved = ops / (knn_ms * 1e-3)
     roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_I8_PEAK / 1e12,
@@ -188,7 +194,7 @@ def main():
             "ops_per_launch": ops,
             "ops_def": "sum over clusters with >= %d members of 2*s^2*D: the 0/1 product of the "
                        "members' rows over the cluster's local dictionary (D = items held by >= "
-                       "2 members)" % MFMA_MIN}
+                       "2 members)" % mfma_min}
 
     line = {
         "metric": METRIC, "value": E / (graph_ms * 1e-3), "unit": "Jaccard evals/s",
@@ -196,7 +202,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i8",
         "data": "synthetic: seeded lognormal profile sizes, Zipf item popularity",
         "config": {"workload": w.name, "n": w.n, "m": w.m, "nnz": P.nnz, "t": w.t, "b": w.b,
-                   "cap": w.cap, "k": w.k, "form": "batched build replayed as a HIP graph"},
+                   "cap": w.cap, "k": w.k, "form": "batched build replayed as a HIP graph",
+                   "tuning": tuned or "defaults"},
         "build_ms": {"graph": graph_ms, "batched": batched_ms, "plain": plain_ms},
         "quality": quality, "jaccard_evals": E, "clusters": ncl,
         "local_knn_ms": knn_ms, "local_knn_evals_per_s": E / (knn_ms * 1e-3),

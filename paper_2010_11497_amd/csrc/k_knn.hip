@@ -449,14 +449,19 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     const uint32_t wr = w >> 1, wc = w & 1;
     const ClusterView cv = view(a, c);
     const uint32_t s = cv.s, W = a.wmax, nchunks = W / 2;
-    // row owner state (threads 0..127)
-    const uint32_t ra = rb * kMR + t;
-    const uint32_t ur = t < kMR ? member(a, cv, ra) : a.n;
-    const bool owner = ur < a.n;
-    const uint32_t Lr = owner ? ulen[ur] : 0;
+    // selection: row r of the block belongs to the thread pair (2r, 2r + 1);
+    // both filter half of each tile, the even thread keeps the heap
+    const uint32_t r = t >> 1, half = t & 1;
+    const uint32_t ra = rb * kMR + r;
+    const uint32_t ur = member(a, cv, ra);
+    const bool active = ur < a.n;
+    const bool owner = active && half == 0;
+    const uint32_t Lr = active ? ulen[ur] : 0;
+    // staging: thread t < 128 expands row t of the block, t >= 128 column t - 128
+    const uint32_t us_row = t < kMR ? member(a, cv, rb * kMR + t) : a.n;
     KeyHeap h;
     h.hk = L.hk;
-    h.me = t < kMR ? t : 0;
+    h.me = r;
     h.k = a.k;
     h.cnt = 0;
     h.root = 0;
@@ -466,7 +471,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     const uint32_t cb_end = (g + 1) * per < tiles ? (g + 1) * per : tiles;
     for (uint32_t cb = g * per; cb < cb_end; ++cb) {
         // staged row of this thread: owner row t, or column t - 128
-        const uint32_t us = t < kMR ? ur : member(a, cv, cb * kMC + (t - kMR));
+        const uint32_t us = t < kMR ? us_row : member(a, cv, cb * kMC + (t - kMR));
         const uint64_t *src = reinterpret_cast<const uint64_t *>(ubits + (size_t)us * W);
         if (t >= kMR) {
             L.cuid[t - kMR] = us;
@@ -520,13 +525,20 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
             }
         }
         __syncthreads();
-        if (t < kMR) {
+        {
             const uint32_t ncol = s - cb * kMC < kMC ? s - cb * kMC : kMC;
-            const uint32_t self = ra - cb * kMC;  // column index of the owner's own row
-            uint32_t msk[4] = {0u, 0u, 0u, 0u};
-            if (owner) {
-                for (uint32_t q8 = 0; q8 < ncol; q8 += 8) {
-                    const uint4 raw = *reinterpret_cast<const uint4 *>(&L.u.itile[t][q8]);
+            const uint32_t self = ra - cb * kMC;  // column index of the row's own member
+            // the owner's heap state, shared with its helper lane
+            const uint32_t rlo = __shfl((uint32_t)h.root, lane & ~1u);
+            const uint32_t rhi = __shfl((uint32_t)(h.root >> 32), lane & ~1u);
+            const uint64_t root = ((uint64_t)rhi << 32) | rlo;
+            const float sigma = __shfl(h.sigma, lane & ~1u);
+            const bool full = __shfl((int)h.full(), lane & ~1u) != 0;
+            uint32_t m0 = 0u, m1 = 0u;  // candidates half*64 .. half*64 + 63 that pass
+            if (active) {
+                const uint32_t q0 = half * 64;
+                for (uint32_t q8 = q0; q8 < q0 + 64 && q8 < ncol; q8 += 8) {
+                    const uint4 raw = *reinterpret_cast<const uint4 *>(&L.u.itile[r][q8]);
                     const uint32_t pr[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
@@ -534,20 +546,27 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
                         const uint32_t I = (pr[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
                         const uint32_t S = Lr + L.clen[q];
                         const bool ok = q < ncol && q != self &&
-                                        (!h.full() || (may_beat(I, S, h.sigma) &&
-                                                       beats(I, S - I, L.cuid[q], h.root)));
-                        if (ok) msk[q >> 5] |= 1u << (q & 31);
+                                        (!full || (may_beat(I, S, sigma) &&
+                                                   beats(I, S - I, L.cuid[q], root)));
+                        if (ok) {
+                            if (q - q0 < 32) m0 |= 1u << (q - q0);
+                            else m1 |= 1u << (q - q0 - 32);
+                        }
                     }
                 }
             }
-            // wave-uniform loop: each lane inserts its next passing candidate
+            // the owner takes its helper's masks (adjacent lane)
+            const uint32_t o0 = __shfl(m0, lane | 1u), o1 = __shfl(m1, lane | 1u);
+            uint32_t msk[4] = {m0, m1, o0, o1};
+            if (!owner) msk[0] = msk[1] = msk[2] = msk[3] = 0u;
+            // wave-uniform loop: each owner inserts its next passing candidate
             while (__any((msk[0] | msk[1] | msk[2] | msk[3]) != 0u)) {
                 const int wsel = msk[0] ? 0 : msk[1] ? 1 : msk[2] ? 2 : msk[3] ? 3 : -1;
                 if (wsel >= 0) {
                     const uint32_t bit = __ffs(msk[wsel]) - 1;
                     msk[wsel] &= msk[wsel] - 1;
                     const uint32_t q = wsel * 32 + bit;
-                    const uint32_t I = L.u.itile[t][q];
+                    const uint32_t I = L.u.itile[r][q];
                     const uint32_t U = Lr + L.clen[q] - I, uid = L.cuid[q];
                     if (!h.full() || beats(I, U, uid, h.root))
                         h.insert(((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid));
@@ -580,7 +599,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     // split row block: leave this group's sorted keys (0 = none) in scratch
     const uint32_t slot0 = sc.sbase[c] + rb * ng;
     if (owner) {
-        uint64_t *out = sc.keys + ((size_t)(slot0 + g) * kMR + t) * kMaxK;
+        uint64_t *out = sc.keys + ((size_t)(slot0 + g) * kMR + r) * kMaxK;
         for (uint32_t r = h.cnt; r < a.k; ++r) out[r] = 0;
         for (uint32_t size = h.cnt; size > 0; --size) {
             out[size - 1] = h.get(0);
@@ -595,7 +614,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     if (!last || !owner || cv.j >= a.t) return;
     __threadfence();
     // the last group merges the ng sorted lists of each row (disjoint columns)
-    const uint64_t *in = sc.keys + ((size_t)slot0 * kMR + t) * kMaxK;
+    const uint64_t *in = sc.keys + ((size_t)slot0 * kMR + r) * kMaxK;
     uint32_t ptr[kMaxGroups];
     uint64_t head[kMaxGroups];
 #pragma unroll
