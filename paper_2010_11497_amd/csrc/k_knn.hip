@@ -313,6 +313,8 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kTile16Stride = 136;   // u16 per row of the transposed result tile
 constexpr uint32_t kMfmaMaxLen = 1u << 15;
+constexpr uint32_t kBisectSlack = 8;  // tile prefilter once more than k + this many pass
+constexpr int kBisectSteps = 9;        // brackets the tile's k-th best code to 1/512 of the largest
 
 struct __attribute__((aligned(16))) MfmaLds {
     union __attribute__((aligned(16))) {
@@ -370,52 +372,63 @@ C2_DEV bool beats(uint32_t I, uint32_t U, uint32_t uid, uint64_t hk) {
     const uint32_t kt = (uint32_t)(hk >> 32);
     const uint64_t A = ((uint64_t)I << 32) - I;   // I * (2^32 - 1)
     const uint64_t B = (uint64_t)kt * U;          // key_T * U
-    if (A < B) return false;                      // key < key_T
-    if (A >= B + U) return true;                  // key > key_T
-    return uid < 0xFFFFFFFFu - (uint32_t)hk;      // equal keys: smaller id wins
+    const bool gt = A >= B + U;                   // key > key_T
+    const bool eq = (A >= B) & !gt;               // equal keys: smaller id wins
+    return gt | (eq & (uid < 0xFFFFFFFFu - (uint32_t)hk));
 }
 
 struct KeyHeap {
     uint64_t *hk;  // [kMaxK][kMR], minor index = owner
     uint32_t me, k, cnt;
     uint64_t root;  // valid once full
-    float sigma;    // key_T / (2^32 - 1 + key_T): I >= sigma * (|P_u| + |P_v|) is necessary
 
     C2_DEV uint64_t get(uint32_t i) const { return hk[i * kMR + me]; }
     C2_DEV void put(uint32_t i, uint64_t v) { hk[i * kMR + me] = v; }
-    C2_DEV void sift_down(uint32_t pos, uint64_t v, uint32_t size) {
+    // 4-ary min-heap: the children of p are 4p+1 .. 4p+4.  The four child
+    // slots are read together (an index past the end reads the last entry
+    // again, which never wins the strict comparisons), so each level costs one
+    // LDS round trip.  Returns the entry that ends up at pos.
+    C2_DEV uint64_t sift_down(uint32_t pos, uint64_t v, uint32_t size) {
+        uint64_t top = v;
+        bool moved = false;
         for (;;) {
-            uint32_t l = 2 * pos + 1;
-            if (l >= size) break;
-            uint64_t c = get(l);
-            if (l + 1 < size) {
-                const uint64_t d = get(l + 1);
-                if (d < c) { c = d; l = l + 1; }
-            }
-            if (v <= c) break;
-            put(pos, c);
-            pos = l;
+            const uint32_t c0 = 4 * pos + 1;
+            if (c0 >= size) break;
+            const uint32_t last = size - 1;
+            const uint64_t x0 = get(c0);
+            const uint64_t x1 = get(c0 + 1 < last ? c0 + 1 : last);
+            const uint64_t x2 = get(c0 + 2 < last ? c0 + 2 : last);
+            const uint64_t x3 = get(c0 + 3 < last ? c0 + 3 : last);
+            uint64_t best = x0;
+            uint32_t bi = c0;
+            if (x1 < best) { best = x1; bi = c0 + 1; }
+            if (x2 < best) { best = x2; bi = c0 + 2; }
+            if (x3 < best) { best = x3; bi = c0 + 3; }
+            if (v <= best) break;
+            if (!moved) top = best;
+            moved = true;
+            put(pos, best);
+            pos = bi;
         }
         put(pos, v);
+        return top;
+    }
+    C2_DEV void heapify(uint32_t size) {
+        if (size < 2) return;
+        for (int i = (int)(size - 2) / 4; i >= 0; --i) sift_down((uint32_t)i, get(i), size);
     }
     C2_DEV bool full() const { return cnt >= k; }
-    C2_DEV void set_root() {
-        root = get(0);
-        const float kt = (float)(uint32_t)(root >> 32);
-        sigma = kt / (4294967295.0f + kt);
-    }
     // Until the heap holds k entries, entries are appended and then heapified
     // once; afterwards v replaces the root (the caller checked it beats it).
     C2_DEV void insert(uint64_t v) {
         if (cnt < k) {
             put(cnt++, v);
             if (cnt == k) {
-                for (int i = (int)k / 2 - 1; i >= 0; --i) sift_down((uint32_t)i, get(i), k);
-                set_root();
+                heapify(k);
+                root = get(0);
             }
         } else {
-            sift_down(0, v, k);
-            set_root();
+            root = sift_down(0, v, k);
         }
     }
 };
@@ -424,6 +437,24 @@ struct KeyHeap {
 // that covers rounding: J > J_T implies I > sigma_T * (|P_u| + |P_v|).
 C2_DEV bool may_beat(uint32_t I, uint32_t S, float sigma) {
     return (float)I >= sigma * (float)S * 0.999999f;
+}
+
+// floor(2^16 * I / S) for 0 <= I <= S/2, clamped to 15 bits (0 when S = 0).
+// The fp32 estimate is within a relative 2^-22 of I/S.
+C2_DEV uint32_t ratio_code(uint32_t I, uint32_t S) {
+    const float f = (float)I * __builtin_amdgcn_rcpf((float)(S ? S : 1u)) * 65536.0f;
+    const uint32_t c = (uint32_t)f;
+    return c < 0x7FFFu ? c : 0x7FFFu;
+}
+
+// How many of the 64 codes packed two per word (15 bits each) are >= M, for
+// M <= 0x7FFF: per half, bit 15 of (code | 0x8000) - M is set iff code >= M.
+C2_DEV uint32_t codes_at_least(const uint32_t (&pk)[32], uint32_t M) {
+    const uint32_t MM = M * 0x10001u;
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) c += __popc(((pk[j] | 0x80008000u) - MM) & 0x80008000u);
+    return c;
 }
 
 // Work item of the MFMA path: cluster c, row block rb, column group g of ng.
@@ -465,7 +496,6 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     h.k = a.k;
     h.cnt = 0;
     h.root = 0;
-    h.sigma = 0.0f;
     const uint32_t hl = (lane >> 5) * 16;  // byte offset of this lane's 16 k-values
     const uint32_t tiles = (s + kMC - 1) / kMC, per = (tiles + ng - 1) / ng;
     const uint32_t cb_end = (g + 1) * per < tiles ? (g + 1) * per : tiles;
@@ -532,27 +562,82 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
             const uint32_t rlo = __shfl((uint32_t)h.root, lane & ~1u);
             const uint32_t rhi = __shfl((uint32_t)(h.root >> 32), lane & ~1u);
             const uint64_t root = ((uint64_t)rhi << 32) | rlo;
-            const float sigma = __shfl(h.sigma, lane & ~1u);
             const bool full = __shfl((int)h.full(), lane & ~1u) != 0;
-            uint32_t m0 = 0u, m1 = 0u;  // candidates half*64 .. half*64 + 63 that pass
-            if (active) {
-                const uint32_t q0 = half * 64;
-                for (uint32_t q8 = q0; q8 < q0 + 64 && q8 < ncol; q8 += 8) {
-                    const uint4 raw = *reinterpret_cast<const uint4 *>(&L.u.itile[r][q8]);
-                    const uint32_t pr[4] = {raw.x, raw.y, raw.z, raw.w};
+            // sigma = key_T / (2^32 - 1 + key_T): I >= sigma * (|P_u| + |P_v|) is necessary
+            const float kt = (float)rhi;
+            const float sigma = kt / (4294967295.0f + kt);
+            // candidates half*64 .. half*64 + 63 that may beat the root (the
+            // exact test is made again at insertion, against the root then)
+            uint32_t m0 = 0u, m1 = 0u;
+            const uint32_t q0 = half * 64;
+#pragma unroll 1
+            for (uint32_t q8 = 0; q8 < 64; q8 += 8) {
+                const uint4 raw = *reinterpret_cast<const uint4 *>(&L.u.itile[r][q0 + q8]);
+                const uint4 l0 = *reinterpret_cast<const uint4 *>(&L.clen[q0 + q8]);
+                const uint4 l1 = *reinterpret_cast<const uint4 *>(&L.clen[q0 + q8 + 4]);
+                const uint32_t pr[4] = {raw.x, raw.y, raw.z, raw.w};
+                const uint32_t cl[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+                uint32_t bits = 0;
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const uint32_t q = q8 + e;
-                        const uint32_t I = (pr[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-                        const uint32_t S = Lr + L.clen[q];
-                        const bool ok = q < ncol && q != self &&
-                                        (!full || (may_beat(I, S, sigma) &&
-                                                   beats(I, S - I, L.cuid[q], root)));
-                        if (ok) {
-                            if (q - q0 < 32) m0 |= 1u << (q - q0);
-                            else m1 |= 1u << (q - q0 - 32);
-                        }
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t q = q0 + q8 + e;
+                    const uint32_t I = (pr[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                    const bool ok = active & (q < ncol) & (q != self) &
+                                    (!full | may_beat(I, Lr + cl[e], sigma));
+                    bits |= (ok ? 1u : 0u) << e;
+                }
+                if (q8 < 32) m0 |= bits << q8;
+                else m1 |= bits << (q8 - 32);
+            }
+            // When many candidates of a row pass (always in the first tile of
+            // an item, where the heap is not yet full), drop those that are not
+            // among the tile's own k best: a candidate with k better ones in
+            // the same tile cannot be among the row's k best.  Each candidate
+            // gets a 15-bit code of its I/S (floor(2^16 * I/S) in fp32, two
+            // codes per word, 0 for columns that are not candidates), and
+            // bisection finds a level L with at least k codes >= L.  A candidate
+            // is dropped only when its code is below L - 1, a margin larger
+            // than the rounding of the fp32 ratios, so those k candidates are
+            // strictly better in exact arithmetic.
+            const uint32_t npass = __popc(m0) + __popc(m1);
+            const uint32_t npair = npass + __shfl_xor(npass, 1);
+            if (__any(npair > a.k + kBisectSlack)) {
+                uint32_t pk[32];
+#pragma unroll
+                for (int q2 = 0; q2 < 64; q2 += 2) {
+                    const uint32_t q = q0 + q2;
+                    const uint32_t I2 = *reinterpret_cast<const uint32_t *>(&L.u.itile[r][q]);
+                    const uint2 l2 = *reinterpret_cast<const uint2 *>(&L.clen[q]);
+                    const uint32_t c0 = active && q < ncol && q != self
+                                            ? ratio_code(I2 & 0xFFFFu, Lr + l2.x) : 0u;
+                    const uint32_t c1 = active && q + 1 < ncol && q + 1 != self
+                                            ? ratio_code(I2 >> 16, Lr + l2.y) : 0u;
+                    pk[q2 >> 1] = c0 | (c1 << 16);
+                }
+                uint32_t hi = 0;
+#pragma unroll
+                for (int j = 0; j < 32; ++j) hi = max(hi, max(pk[j] & 0xFFFFu, pk[j] >> 16));
+                hi = max(hi, (uint32_t)__shfl_xor(hi, 1)) + 1;  // no code reaches hi
+                uint32_t lo = 0;  // invariant: at least k codes >= lo
+#pragma unroll 1
+                for (int it = 0; it < kBisectSteps; ++it) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    const uint32_t c = codes_at_least(pk, mid);
+                    if (c + __shfl_xor(c, 1) >= a.k) lo = mid;
+                    else hi = mid;
+                }
+                if (npair > a.k + kBisectSlack && lo >= 2) {
+                    const uint32_t M = (lo - 1) * 0x10001u;
+                    uint32_t k0 = 0, k1 = 0;  // candidates whose code is >= lo - 1
+#pragma unroll
+                    for (int j = 0; j < 32; ++j) {
+                        const uint32_t ge = ((pk[j] | 0x80008000u) - M) & 0x80008000u;
+                        const uint32_t two = ((ge >> 15) & 1u) | ((ge >> 30) & 2u);
+                        if (j < 16) k0 |= two << (2 * j);
+                        else k1 |= two << (2 * (j - 16));
                     }
+                    m0 &= k0;
+                    m1 &= k1;
                 }
             }
             // the owner takes its helper's masks (adjacent lane)
@@ -576,8 +661,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
         __syncthreads();
     }
     // fewer than k candidates: the appended entries were never heapified
-    if (owner && h.cnt < h.k)
-        for (int i = (int)h.cnt / 2 - 1; i >= 0; --i) h.sift_down((uint32_t)i, h.get(i), h.cnt);
+    if (owner && h.cnt < h.k) h.heapify(h.cnt);
     if (ng == 1) {
         if (owner && cv.j < a.t) {
             const size_t base = ((size_t)ur * a.t + cv.j) * a.k;

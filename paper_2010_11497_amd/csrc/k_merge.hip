@@ -1,9 +1,11 @@
 // Step 3 on the device: merge of each user's t partial lists (Section II-G,
 // Algorithm 3).  A group of G >= t lanes serves one user; lane j holds the
 // head of list j (each list is best first).  Each step the group picks the
-// best head (exact Jaccard order; equal entries -- the same neighbour found in
-// several lists -- resolved to the lowest lane), emits it unless it repeats
-// the previous output, and that lane advances.  Similarities found in Step 2
+// best head in the exact Jaccard order and emits it, and every lane whose head
+// is that neighbour advances: a neighbour found in several lists has the same
+// I and U in all of them, and when it is the best head it is the head of every
+// list that holds it (each list is sorted and holds a neighbour once), so each
+// step emits a new neighbour and k steps suffice.  Similarities found in Step 2
 // are reused; nothing is recomputed except U from the profile lengths.
 #include "c2_internal.h"
 #include "c2_kernels.h"
@@ -82,35 +84,28 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
         }
     };
     load();
-    uint32_t out = 0, last = kPad;
+    uint32_t out = 0;
     uint32_t *oid = knn_id + u * k, *oI = knn_I + u * k, *oU = knn_U + u * k;
     while (out < k) {
+        // the group maximum of the heads (kPad: list exhausted)
         bool ok = hv != kPad;
-        uint32_t bI = hI, bU = hU, bv = hv, bj = j;
+        uint32_t bI = hI, bU = hU, bv = hv;
 #pragma unroll
         for (int d = G / 2; d > 0; d >>= 1) {
             const bool ook = __shfl_xor((int)ok, d, G) != 0;
             const uint32_t oI2 = __shfl_xor(bI, d, G), oU2 = __shfl_xor(bU, d, G);
-            const uint32_t ov = __shfl_xor(bv, d, G), oj = __shfl_xor(bj, d, G);
-            bool take;
-            if (ok != ook) take = ook;
-            else if (!ok) take = oj < bj;
-            else if (jbetter(oI2, oU2, ov, bI, bU, bv)) take = true;
-            else if (jbetter(bI, bU, bv, oI2, oU2, ov)) take = false;
-            else take = oj < bj;
-            if (take) { ok = ook; bI = oI2; bU = oU2; bv = ov; bj = oj; }
+            const uint32_t ov = __shfl_xor(bv, d, G);
+            const bool take = ook && (!ok || jbetter(oI2, oU2, ov, bI, bU, bv));
+            if (take) { ok = true; bI = oI2; bU = oU2; bv = ov; }
         }
         if (!ok) break;
-        if (bv != last) {
-            if (j == 0) {
-                oid[out] = bv;
-                oI[out] = bI;
-                oU[out] = bU;
-            }
-            ++out;
-            last = bv;
+        if (j == 0) {
+            oid[out] = bv;
+            oI[out] = bI;
+            oU[out] = bU;
         }
-        if (j == bj) {
+        ++out;
+        if (hv == bv) {
             ++ptr;
             load();
         }
