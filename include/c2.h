@@ -174,10 +174,12 @@ c2_status c2_check_complete(const void *ws, void *stream);
  *   part_id[(u*t + j)*k + r], part_I[(u*t + j)*k + r]  (device, [n][t][k]),
  * best first, padded with (C2_PAD, 0).  Every (u, j) slot is written exactly
  * once, so every user must appear once per configuration.
- * Pairwise intersections are exact integer counts: clusters are staged as
- * bit rows over their local dictionary (items present at least twice in the
- * cluster); the int8 MFMA path multiplies the 0/1 rows as a matrix product
- * with int32 accumulation, the bitmap path uses AND and population count.
+ * Pairwise intersections are exact integer counts over per-user bit rows
+ * (one bit per item, all m items): the int8 MFMA path expands 64-item chunks
+ * of the rows to 0/1 bytes and multiplies them as a matrix product with int32
+ * accumulation (used when every profile has fewer than 2^15 items, where an
+ * exact 32-bit similarity key exists); the bitmap path uses AND and
+ * population count.
  * form: C2_FORM_PLAIN reads the cluster table back (synchronises once) and
  * launches one grid over (cluster, row block) pairs in cluster order;
  * C2_FORM_BATCHED plans on the device and runs one persistent launch that
