@@ -92,7 +92,7 @@ typedef struct c2_params {
  * NULL pointer or a zero field means the built-in default. */
 typedef struct c2_tuning {
     uint32_t mfma_min_rows;   /* clusters with at least this many members use the
-                                 int8 MFMA path, smaller ones the bitmap path */
+                                 MFMA path, smaller ones the bitmap path */
     uint32_t persistent_wgs;  /* workgroups of the persistent launch (batched form) */
     uint32_t split_rounds;    /* split rounds enqueued by the batched form */
     uint32_t group_tiles;     /* MFMA path: a block of 128 rows whose cluster spans more than
@@ -175,9 +175,10 @@ c2_status c2_check_complete(const void *ws, void *stream);
  * best first, padded with (C2_PAD, 0).  Every (u, j) slot is written exactly
  * once, so every user must appear once per configuration.
  * Pairwise intersections are exact integer counts over per-user bit rows
- * (one bit per item, all m items): the int8 MFMA path expands 64-item chunks
- * of the rows to 0/1 bytes and multiplies them as a matrix product with int32
- * accumulation (used when every profile has fewer than 2^15 items, where an
+ * (one bit per item, all m items): the MFMA path expands 64-item chunks of
+ * the rows to fp4 (e2m1) values 0 and 1 and multiplies them with the gfx950
+ * block-scaled MFMA at unit scale, whose fp32 sums of 0/1 products are exact
+ * integer counts (used when every profile has fewer than 2^15 items, where an
  * exact 32-bit similarity key exists); the bitmap path uses AND and
  * population count.
  * form: C2_FORM_PLAIN reads the cluster table back (synchronises once) and

@@ -5,8 +5,10 @@
 // (padded to a multiple of 64 items).  |P_u & P_v| is the dot product of two
 // bit rows; |P_u | P_v| = |P_u| + |P_v| - |P_u & P_v|.  Two paths compute the
 // dot products of a cluster's members, in tiles of (row block x column block):
-//   - int8 MFMA: 64-item chunks of the bit rows are expanded to 0/1 bytes in
-//     LDS and multiplied with v_mfma_i32_32x32x32_i8 (exact int32 sums);
+//   - MFMA: 64-item chunks of the bit rows are expanded in LDS to 4-bit
+//     e2m1 values (0 or 1.0) and multiplied with the gfx950 block-scaled
+//     v_mfma_scale_f32_32x32x64_f8f6f4 at unit scale; the fp32 sums are
+//     integer counts below 2^24, hence exact;
 //   - bitmap: AND + population count of 32-bit words, for small clusters.
 // Selection: every member of the row block owns a bounded heap of its k best
 // candidates in LDS (worst at the root, exact Jaccard order) and offers each
@@ -22,7 +24,7 @@ constexpr uint32_t kRowBlock = 64;   // rows (members) per bitmap work item
 constexpr int kWordChunk = 16;       // bit-row words staged per step (bitmap path)
 constexpr uint32_t kMR = 128;        // rows per MFMA work item (row owners)
 constexpr uint32_t kMC = 128;        // columns per MFMA step
-constexpr int kOpStride = 80;        // bytes per staged 64-item row (padded: no bank conflicts)
+constexpr int kOpStride = 48;        // bytes per staged 64-item row of nibbles (32 + pad: no bank conflicts)
 constexpr int kTileStride = 132;     // u32 per row of the transposed result tile
 constexpr uint32_t kDefaultMfmaMin = 2;
 constexpr uint32_t kPf = 8;          // chunks of bit rows prefetched ahead (MFMA path)
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *ub
 // 128-column tile of the cluster the block computes the 128 x 128 matrix of
 // intersection counts: 256 threads each expand one staged row's next 64 bits
 // into 64 bytes of 0/1 (double-buffered in LDS), and each wave multiplies a
-// 64 x 64 sub-tile as 2 x 2 v_mfma_i32_32x32x32_i8.  The counts are written
+// 64 x 64 sub-tile as 2 x 2 fp4 MFMAs of 32 x 32 x 64.  The counts are written
 // to LDS transposed (16 bits each) so that thread t < 128 reads row t.
 //
 // Selection on this path uses an exact 32-bit similarity key,
@@ -309,7 +311,23 @@ __global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *ub
 // the candidates that passed are inserted in a wave-uniform loop.
 
 typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// E8M0 block scales of 2^0 for all four operand blocks.
+constexpr int kUnitScale = 0x7F7F7F7F;
+// Operand format code of e2m1 (fp4) for the f8f6f4 MFMA family.
+constexpr int kFmtFp4 = 4;
+
+// C += A * B^T over 64 items for one 32 x 32 block: A and B hold, in lane l,
+// 32 nibbles of row / column l % 32 for items [32 * (l / 32), +32).  Only the
+// first four dwords of the 8-dword operands are read for fp4.
+C2_DEV v16f mfma_fp4(v4i a, v4i b, v16f c) {
+    const v8i A = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
+    const v8i B = {b[0], b[1], b[2], b[3], 0, 0, 0, 0};
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, B, c, kFmtFp4, kFmtFp4, 0,
+                                                           kUnitScale, 0, kUnitScale);
+}
 
 constexpr int kTile16Stride = 136;   // u16 per row of the transposed result tile
 constexpr uint32_t kMfmaMaxLen = 1u << 15;
@@ -325,21 +343,24 @@ struct __attribute__((aligned(16))) MfmaLds {
     uint64_t hk[kMaxK * kMR];
 };
 
-// 64 bits -> 64 bytes of 0/1, byte x = bit x.
+// 64 bits -> 32 bytes of e2m1 nibbles (0x2 = 1.0 for a set bit).  Dword q
+// holds bits 8q .. 8q+7, bit 8q+i in nibble 2i and bit 8q+4+i in nibble
+// 2i+1: (x * 0x408102) moves bit i of a 4-bit x to bit 8i+1 with no carries
+// (the partial products are 7 apart), and the high half is moved up 4 bits.
+// Every row is expanded the same way, so item pairs stay aligned in the dot
+// product whatever order the MFMA assigns to the nibbles.
+C2_DEV uint32_t nibbles8(uint32_t w, int s) {
+    const uint32_t x = w >> s;
+    const uint32_t y = __umul24(x & 0x0Fu, 0x408102u);
+    const uint32_t z = __umul24(x & 0xF0u, 0x408102u);  // (high half * 0x408102) << 4
+    return (z | y) & 0x22222222u;
+}
+
 C2_DEV void expand64(uint64_t bits, uint8_t *dst) {
     const uint32_t lo = (uint32_t)bits, hi = (uint32_t)(bits >> 32);
     uint4 *d = reinterpret_cast<uint4 *>(dst);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint32_t w = q < 2 ? lo : hi;
-        const int sh = (q & 1) * 16;
-        uint4 v;
-        v.x = __umul24((w >> (sh + 0)) & 15u, 0x204081u) & 0x01010101u;
-        v.y = __umul24((w >> (sh + 4)) & 15u, 0x204081u) & 0x01010101u;
-        v.z = __umul24((w >> (sh + 8)) & 15u, 0x204081u) & 0x01010101u;
-        v.w = __umul24((w >> (sh + 12)) & 15u, 0x204081u) & 0x01010101u;
-        d[q] = v;
-    }
+    d[0] = make_uint4(nibbles8(lo, 0), nibbles8(lo, 8), nibbles8(lo, 16), nibbles8(lo, 24));
+    d[1] = make_uint4(nibbles8(hi, 0), nibbles8(hi, 8), nibbles8(hi, 16), nibbles8(hi, 24));
 }
 
 // Unconditional load (chunk clamped into the row) so the compiler can count
@@ -496,7 +517,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     h.k = a.k;
     h.cnt = 0;
     h.root = 0;
-    const uint32_t hl = (lane >> 5) * 16;  // byte offset of this lane's 16 k-values
+    const uint32_t hl = (lane >> 5) * 16;  // byte offset of this lane's 32 items (nibbles)
     const uint32_t tiles = (s + kMC - 1) / kMC, per = (tiles + ng - 1) / ng;
     const uint32_t cb_end = (g + 1) * per < tiles ? (g + 1) * per : tiles;
     for (uint32_t cb = g * per; cb < cb_end; ++cb) {
@@ -507,7 +528,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
             L.cuid[t - kMR] = us;
             L.clen[t - kMR] = us < a.n ? ulen[us] : 0;
         }
-        v16i acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
+        v16f acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
         // bits of chunk ch live in pf[ch % kPf] from kPf - 1 chunks before use;
         // the loop is unrolled by kPf so every slot index is a constant
         uint64_t pf[kPf];
@@ -523,17 +544,15 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
                 const uint32_t ch = ch0 + u;
                 lds_barrier();
                 const uint32_t st = u & 1;
-#pragma unroll
-                for (int kk = 0; kk < 2; ++kk) {
-                    const uint32_t off = kk * 32 + hl;
-                    const v4i A0 = *reinterpret_cast<const v4i *>(&L.u.op[st][wr * 64 + (lane & 31)][off]);
-                    const v4i A1 = *reinterpret_cast<const v4i *>(&L.u.op[st][wr * 64 + 32 + (lane & 31)][off]);
-                    const v4i B0 = *reinterpret_cast<const v4i *>(&L.u.op[st][kMR + wc * 64 + (lane & 31)][off]);
-                    const v4i B1 = *reinterpret_cast<const v4i *>(&L.u.op[st][kMR + wc * 64 + 32 + (lane & 31)][off]);
-                    acc00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B0, acc00, 0, 0, 0);
-                    acc01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B1, acc01, 0, 0, 0);
-                    acc10 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B0, acc10, 0, 0, 0);
-                    acc11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B1, acc11, 0, 0, 0);
+                {
+                    const v4i A0 = *reinterpret_cast<const v4i *>(&L.u.op[st][wr * 64 + (lane & 31)][hl]);
+                    const v4i A1 = *reinterpret_cast<const v4i *>(&L.u.op[st][wr * 64 + 32 + (lane & 31)][hl]);
+                    const v4i B0 = *reinterpret_cast<const v4i *>(&L.u.op[st][kMR + wc * 64 + (lane & 31)][hl]);
+                    const v4i B1 = *reinterpret_cast<const v4i *>(&L.u.op[st][kMR + wc * 64 + 32 + (lane & 31)][hl]);
+                    acc00 = mfma_fp4(A0, B0, acc00);
+                    acc01 = mfma_fp4(A0, B1, acc01);
+                    acc10 = mfma_fp4(A1, B0, acc10);
+                    acc11 = mfma_fp4(A1, B1, acc11);
                 }
                 const int nx = (u + 1) % kPf;
                 expand64(pf[nx], L.u.op[st ^ 1][t]);
@@ -548,10 +567,10 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const uint32_t i = i0 + 8 * (r >> 2) + (r & 3);
-                L.u.itile[i][j0] = (uint16_t)acc00[r];
-                L.u.itile[i][j0 + 32] = (uint16_t)acc01[r];
-                L.u.itile[i + 32][j0] = (uint16_t)acc10[r];
-                L.u.itile[i + 32][j0 + 32] = (uint16_t)acc11[r];
+                L.u.itile[i][j0] = (uint16_t)(uint32_t)acc00[r];
+                L.u.itile[i][j0 + 32] = (uint16_t)(uint32_t)acc01[r];
+                L.u.itile[i + 32][j0] = (uint16_t)(uint32_t)acc10[r];
+                L.u.itile[i + 32][j0 + 32] = (uint16_t)(uint32_t)acc11[r];
             }
         }
         __syncthreads();
