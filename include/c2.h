@@ -98,6 +98,9 @@ typedef struct c2_tuning {
     uint32_t group_tiles;     /* MFMA path: a block of 128 rows whose cluster spans more than
                                  this many 128-column tiles is split into up to 4 work items
                                  over disjoint column ranges (default 4) */
+    uint32_t cluster_path;    /* 0: automatic; 1: grid rounds (any size); 2: one workgroup per
+                                 configuration with every split round in LDS (n <= 8192 and
+                                 bit_width(b) <= 20; otherwise the grid rounds are used) */
     void *ev_knn_begin;       /* optional hipEvent_t (host handles, caller-owned): recorded on */
     void *ev_knn_end;         /* the stream right before / after the pairwise local-KNN kernel */
 } c2_tuning;

@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("mfma_min_rows", ctypes.c_uint32), ("persistent_wgs", ctypes.c_uint32),
                 ("split_rounds", ctypes.c_uint32), ("group_tiles", ctypes.c_uint32),
+                ("cluster_path", ctypes.c_uint32),
                 ("ev_knn_begin", ctypes.c_void_p), ("ev_knn_end", ctypes.c_void_p)]
 
 
@@ -137,12 +138,15 @@ def params(t, b, cap, k) -> Params:
     return Params(int(t), int(b), int(cap), int(k))
 
 
+CLUSTER_AUTO, CLUSTER_GRID, CLUSTER_WORKGROUP = 0, 1, 2
+
+
 def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0, group_tiles=0,
-           events=None) -> Tuning:
+           cluster_path=CLUSTER_AUTO, events=None) -> Tuning:
     """events: optional (begin, end) torch.cuda.Event(enable_timing=True) pair
     recorded around the local-KNN kernel."""
     tu = Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), int(group_tiles),
-                None, None)
+                int(cluster_path), None, None)
     if events is not None:
         for ev in events:
             ev.record()           # materialise the underlying hipEvent_t

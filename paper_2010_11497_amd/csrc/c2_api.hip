@@ -67,6 +67,14 @@ ClusterDims cdims(uint32_t n, const c2_params *p) {
     return d;
 }
 
+// Scratch of the clustering step: the grid rounds' state, or the workgroup
+// path's signatures and cluster starts, whichever is larger.
+size_t cluster_scratch_bytes(uint32_t n, const c2_params *p) {
+    const size_t g = cluster_ws_elems(cdims(n, p), nullptr);
+    const size_t w = cluster_wg_ws_bytes(n, p->t);
+    return g > w ? g : w;
+}
+
 struct BuildLayout {
     size_t bucket, members, cl_off, cl_cfg, part_id, part_I, scratch, total;
 };
@@ -83,7 +91,7 @@ BuildLayout build_layout(uint32_t n, uint32_t m, const c2_params *p) {
     L.part_id = take(4 * NE * p->k);
     L.part_I = take(4 * NE * p->k);
     L.scratch = off;
-    const size_t cw = cluster_ws_elems(cdims(n, p), nullptr);
+    const size_t cw = cluster_scratch_bytes(n, p);
     const size_t kw = knn_ws_bytes(n, (uint32_t)NE, knn_wmax(m), nullptr);
     L.total = off + (cw > kw ? cw : kw);
     return L;
@@ -153,7 +161,7 @@ uint32_t rounds_from(const c2_tuning *tune) {
 
 // Clustering on an explicit scratch region (clusters of `ws` header status).
 c2_status run_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_params *p, int form,
-                      uint32_t rounds_batched, uint32_t *members, uint32_t *cl_off,
+                      const c2_tuning *tune, uint32_t rounds_batched, uint32_t *members, uint32_t *cl_off,
                       uint32_t *cl_cfg_off, char *scratch, uint32_t *status, hipStream_t s,
                       uint32_t *rounds_used) {
     ClusterWs w;
@@ -173,6 +181,22 @@ c2_status run_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_par
     a.bucket = bucket;
     a.NE = (uint32_t)d.NE;
     a.NP = (uint32_t)d.NP;
+    const uint32_t path = tune ? tune->cluster_path : 0;
+    if (path != 1 && cluster_wg_fits(a.n, a.b)) {
+        uint32_t *rctr = nullptr;
+        const uint32_t maxr = form == C2_FORM_PLAIN ? kMaxRounds : rounds_batched;
+        C2_TRY(cluster_wg_run(a, members, cl_off, cl_cfg_off, scratch, status, maxr, &rctr, s),
+               "cluster (workgroup)");
+        if (form == C2_FORM_PLAIN) {
+            uint32_t h[2] = {0, 0};
+            C2_TRY(hipMemcpyAsync(&h[0], rctr, 4, hipMemcpyDeviceToHost, s), "copy");
+            C2_TRY(hipMemcpyAsync(&h[1], status, 4, hipMemcpyDeviceToHost, s), "copy");
+            C2_TRY(hipStreamSynchronize(s), "sync");
+            if (h[1]) return fail(C2_E_UNSUPPORTED, "more than %u split rounds", kMaxRounds);
+            if (rounds_used) *rounds_used = h[0];
+        }
+        return C2_OK;
+    }
     C2_TRY(cluster_init(a, c, s), "cluster init");
     uint32_t r = 0;
     if (form == C2_FORM_PLAIN) {
@@ -255,7 +279,7 @@ size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params 
         return kHeader;
     case C2_OP_CLUSTER:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
-        return kHeader + cluster_ws_elems(cdims(n, p), nullptr);
+        return kHeader + cluster_scratch_bytes(n, p);
     case C2_OP_LOCAL_KNN:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
         return kHeader + knn_ws_bytes(n, p->t * n, knn_wmax(m), nullptr);
@@ -327,7 +351,7 @@ c2_status c2_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_para
     if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_CLUSTER))) != C2_OK)
         return st;
     char *base = reinterpret_cast<char *>(ws);
-    return run_cluster(P, bucket, p, form, rounds_from(tune), members, cl_off, cl_cfg_off,
+    return run_cluster(P, bucket, p, form, tune, rounds_from(tune), members, cl_off, cl_cfg_off,
                        base + kHeader, reinterpret_cast<uint32_t *>(base), (hipStream_t)stream,
                        nullptr);
 }
@@ -382,7 +406,7 @@ static c2_status build_impl(const c2_profiles *P, const uint64_t *tab, const c2_
     uint32_t *pid = reinterpret_cast<uint32_t *>(base + L.part_id);
     uint32_t *pI = reinterpret_cast<uint32_t *>(base + L.part_I);
     C2_TRY(launch_hash_items(tab, p->t, p->b, P->m, bucket, s), "hash items");
-    c2_status st = run_cluster(P, bucket, p, form, rounds_batched, members, cl_off, cl_cfg,
+    c2_status st = run_cluster(P, bucket, p, form, tune, rounds_batched, members, cl_off, cl_cfg,
                                base + L.scratch, reinterpret_cast<uint32_t *>(base), s,
                                rounds_used);
     if (st != C2_OK) return st;

@@ -92,6 +92,8 @@ C2_DEV uint32_t group_min_above(const int64_t *indptr, const uint32_t *indices, 
     return best;
 }
 
+C2_DEV uint32_t bit_width_dev(uint32_t x) { return x ? 32u - (uint32_t)__clz(x) : 0u; }
+
 // Block-wide exclusive scan of one value per thread; returns the block total
 // through *total.  NT threads (a multiple of 64), LDS for NT/64 wave sums.
 template <typename T, int NT>

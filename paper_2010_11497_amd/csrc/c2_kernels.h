@@ -46,6 +46,14 @@ struct ClusterArgs {
     uint32_t NE, NP;
 };
 size_t cluster_ws_elems(const ClusterDims &d, ClusterWs *w);
+// one workgroup per configuration (n <= kWgMaxN), all split rounds in LDS
+constexpr uint32_t kWgMaxN = 8192;
+constexpr int kSigD = 8;  // smallest distinct hash values kept per (configuration, user)
+size_t cluster_wg_ws_bytes(uint32_t n, uint32_t t);
+bool cluster_wg_fits(uint32_t n, uint32_t b);
+hipError_t cluster_wg_run(const ClusterArgs &a, uint32_t *members, uint32_t *cl_off,
+                          uint32_t *cl_cfg_off, char *scratch, uint32_t *status,
+                          uint32_t max_rounds, uint32_t **rctr_out, hipStream_t s);
 hipError_t cluster_init(const ClusterArgs &a, const ClusterPtrs &c, hipStream_t s);
 hipError_t cluster_round(const ClusterArgs &a, const ClusterPtrs &c, uint32_t round,
                          hipStream_t s);

@@ -93,13 +93,18 @@ def test_frh_keys(orc, name, P, tab, b, cap, k):
 
 # ---------------------------------------------------------- clustering ----
 
-def check_cluster(orc, P, bucket_np, cap, form, dP=None, dbucket=None):
+# clustering paths: one workgroup per configuration (all rounds in LDS, used
+# automatically up to 8192 users) and the grid rounds (any size)
+CPATHS = {"workgroup": c2.CLUSTER_WORKGROUP, "grid": c2.CLUSTER_GRID}
+
+
+def check_cluster(orc, P, bucket_np, cap, form, dP=None, dbucket=None, path=0):
     t = bucket_np.shape[0]
     dP = dP or c2.DeviceProfiles.from_synth(P)
     dbucket = dbucket if dbucket is not None else torch.as_tensor(bucket_np.view(np.int32)).cuda()
     p = c2.params(t, int(bucket_np.max()) + 1, cap, 1)
-    members, cl_off, cfg, ws = c2.cluster(dP, dbucket, p, form,
-                                          c2.tuning(split_rounds=64) if form else None)
+    tu = c2.tuning(split_rounds=64 if form else 0, cluster_path=path)
+    members, cl_off, cfg, ws = c2.cluster(dP, dbucket, p, form, tu)
     torch.cuda.synchronize()
     if form == c2.FORM_BATCHED:
         c2.check_complete(ws)
@@ -112,39 +117,57 @@ def check_cluster(orc, P, bucket_np, cap, form, dP=None, dbucket=None):
     assert np.array_equal(gm, om)
 
 
+@pytest.mark.parametrize("path", list(CPATHS))
 @pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
 @pytest.mark.parametrize("fixture", ["fig3_split.json", "singleton_stays.json",
                                      "frh_worked_example.json"])
-def test_cluster_fixtures(orc, fixture, form):
-    say("cluster fixture", fixture, form)
+def test_cluster_fixtures(orc, fixture, form, path):
+    say("cluster fixture", fixture, form, path)
     g = json.load(open(os.path.join(GOLDEN, fixture)))
     P = synth.profiles_from_sets(g["profiles"], g["m"])
     bucket = np.array(g["bucket"], dtype=np.uint32)
-    check_cluster(orc, P, bucket, g.get("cap", 10), form)
+    check_cluster(orc, P, bucket, g.get("cap", 10), form, path=CPATHS[path])
 
 
+@pytest.mark.parametrize("path", list(CPATHS))
 @pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
 @pytest.mark.parametrize("name,P,tab,b,cap,k", CASES, ids=[c[0] for c in CASES])
-def test_cluster_random(orc, name, P, tab, b, cap, k, form):
-    say("cluster", name, form)
-    check_cluster(orc, P, orc.hash_items(tab, b, P.m), cap, form)
+def test_cluster_random(orc, name, P, tab, b, cap, k, form, path):
+    say("cluster", name, form, path)
+    check_cluster(orc, P, orc.hash_items(tab, b, P.m), cap, form, path=CPATHS[path])
 
 
-def test_cluster_identical_profiles_deep(orc):
-    # 40 identical users with 30 distinct hash values: a chain of splits
+@pytest.mark.parametrize("path", list(CPATHS))
+def test_cluster_identical_profiles_deep(orc, path):
+    # 40 identical users with 30 distinct hash values: a chain of splits deeper
+    # than the workgroup path's 8 precomputed values per user
+    say("cluster deep chain", path)
     sets = [set(range(30))] * 40
     P = synth.profiles_from_sets(sets, 30)
     bucket = np.arange(30, dtype=np.uint32)[None, :]
-    check_cluster(orc, P, bucket, 5, c2.FORM_PLAIN)
+    check_cluster(orc, P, bucket, 5, c2.FORM_PLAIN, path=CPATHS[path])
 
 
-def test_batched_reports_incomplete(orc):
+@pytest.mark.parametrize("n", [8192, 8193])
+def test_cluster_workgroup_size_limit(orc, n):
+    # the largest configuration the workgroup path takes, and one user more
+    # (the automatic choice then runs the grid rounds)
+    say("cluster size limit", n)
+    P = synth.random_profiles(77, n, 600, 1, 25, 1.0)
+    tab = synth.hash_tables(2, 78)
+    check_cluster(orc, P, orc.hash_items(tab, 64, P.m), 300, c2.FORM_BATCHED)
+
+
+@pytest.mark.parametrize("path", list(CPATHS))
+def test_batched_reports_incomplete(orc, path):
+    say("incomplete", path)
     sets = [set(range(30))] * 40
     P = synth.profiles_from_sets(sets, 30)
     dP = c2.DeviceProfiles.from_synth(P)
     bucket = torch.as_tensor(np.arange(30, dtype=np.int32)[None, :]).cuda()
     p = c2.params(1, 30, 5, 1)
-    _, _, _, ws = c2.cluster(dP, bucket, p, c2.FORM_BATCHED, c2.tuning(split_rounds=3))
+    _, _, _, ws = c2.cluster(dP, bucket, p, c2.FORM_BATCHED,
+                             c2.tuning(split_rounds=3, cluster_path=CPATHS[path]))
     with pytest.raises(c2.C2Error) as e:
         c2.check_complete(ws)
     assert e.value.status == -6
@@ -187,12 +210,13 @@ def test_merge_on_oracle_lists(orc, name, P, tab, b, cap, k):
 
 @pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
 @pytest.mark.parametrize("name,P,tab,b,cap,k", CASES, ids=[c[0] for c in CASES])
-def test_build(orc, name, P, tab, b, cap, k, form):
-    say("build", name, form)
+@pytest.mark.parametrize("path", list(CPATHS))
+def test_build(orc, name, P, tab, b, cap, k, form, path):
+    say("build", name, form, path)
     t = tab.shape[0]
     dP, dtab = gpu_inputs(P, tab)
     got = c2.build(dP, dtab, c2.params(t, b, cap, k), form,
-                   c2.tuning(split_rounds=64) if form else None)
+                   c2.tuning(split_rounds=64 if form else 0, cluster_path=CPATHS[path]))
     r = orc.build_graph(P.indptr, P.indices, P.n, P.m, tab, b, cap, k, THREADS)
     for g, w in zip(got, (r.knn_id, r.knn_I, r.knn_U)):
         assert np.array_equal(u32(g), w)
@@ -233,13 +257,15 @@ def test_validate_rejects_bad_profiles():
         assert e.value.status == -2
 
 
-def test_graph_replays_match_eager(orc):
+@pytest.mark.parametrize("path", list(CPATHS))
+def test_graph_replays_match_eager(orc, path):
+    say("graph replays", path)
     P = synth.random_profiles(44, 600, 300, 2, 30, 1.0)
     tab = synth.hash_tables(4, 45)
     dP, dtab = gpu_inputs(P, tab)
     p = c2.params(4, 16, 40, 10)
     eager = [u32(x) for x in c2.build(dP, dtab, p, c2.FORM_PLAIN)]
-    g = c2.Graph(dP, dtab, p)
+    g = c2.Graph(dP, dtab, p, c2.tuning(cluster_path=CPATHS[path]))
     for rep in range(3):
         out = g.launch()
         torch.cuda.synchronize()
