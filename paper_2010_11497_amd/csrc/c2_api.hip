@@ -151,6 +151,10 @@ KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
     k.hist = u32(w.hist);
     k.htmp = u32(w.htmp);
     k.ctr = u32(w.ctr);
+    k.bmax = u32(w.bmax);
+    k.pc = u32(w.pc);
+    k.ccls = u32(w.ccls);
+    k.cpos = u32(w.cpos);
     return k;
 }
 

@@ -73,7 +73,8 @@ struct KnnArgs {
 };
 struct KnnWs {
     size_t rows, rlen, cnt, items_m, items_b, slots, sbase, rb_done, skeys, csort_key,
-        csort_key_alt, csort_val, csort_val_alt, hist, htmp, ctmp, ctr, total;
+        csort_key_alt, csort_val, csort_val_alt, hist, htmp, ctmp, ctr, bmax, pc, ccls, cpos,
+        total;
 };
 struct KnnPtrs {
     uint32_t *rows, *rlen;
@@ -83,7 +84,7 @@ struct KnnPtrs {
     uint64_t *csort_key, *csort_key_alt;
     uint32_t *csort_val, *csort_val_alt, *hist, *htmp;
     uint64_t *ctmp;
-    uint32_t *ctr;
+    uint32_t *ctr, *bmax, *pc, *ccls, *cpos;
 };
 size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w);
 uint32_t knn_wmax(uint32_t m);

@@ -63,9 +63,18 @@ __global__ __launch_bounds__(256) void k_signature(const int64_t *__restrict__ i
     for (int i = 0; i < kSigD; ++i) s[i] = kNoValue;
     uint64_t a, e;
     row_range(indptr, u, nnz, a, e);
-    for (uint64_t p = a + gl; p < e; p += kSigLanes) {
-        const uint32_t it = indices[p];
-        sig_insert(s, it < m ? bj[it] : kNoValue);
+    // four index -> bucket gathers in flight per lane
+    for (uint64_t p = a + gl; p < e; p += 4 * kSigLanes) {
+        uint32_t it[4], x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t pq = p + (uint64_t)q * kSigLanes;
+            it[q] = pq < e ? indices[pq] : m;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = it[q] < m ? bj[it[q]] : kNoValue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sig_insert(s, x[q]);
     }
     uint32_t *out = sig + g * kSigD;
 #pragma unroll

@@ -30,6 +30,13 @@ constexpr uint32_t kDefaultMfmaMin = 2;
 constexpr uint32_t kPf = 8;          // chunks of bit rows prefetched ahead (MFMA path)
 constexpr uint32_t kGroupTiles = 4;  // column tiles per work item before a row block is split
 constexpr uint32_t kMaxGroups = 4;   // column groups a row block is split into at most
+constexpr uint32_t kUserBitsGrid = 512;  // blocks of k_user_bits at most
+constexpr uint32_t kBitmapPersistent = 256;  // persistent bitmap-path workgroups (batched form)
+// batched planning counters: kCostClasses item counts, then scratch slots and
+// bitmap items
+constexpr uint32_t kCostClasses = 64;
+constexpr uint32_t kSlotCtr = kCostClasses, kBitmapCtr = kCostClasses + 1;
+constexpr uint32_t kPlanCtr = kCostClasses + 2;
 
 // Words per bit row: the item universe padded to a multiple of 64 * kPf items,
 // so the MFMA K loop runs whole unrolled groups.
@@ -58,7 +65,8 @@ __global__ __launch_bounds__(kStageThreads) void k_user_bits(const int64_t *__re
                                                              uint32_t Wg,
                                                              uint32_t *__restrict__ ubits,
                                                              uint32_t *__restrict__ ulen,
-                                                             uint32_t *maxlen) {
+                                                             uint32_t *bmax_out,
+                                                             uint32_t *plan_ctr) {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t *rb = lds + wid * Wg;
@@ -81,13 +89,27 @@ __global__ __launch_bounds__(kStageThreads) void k_user_bits(const int64_t *__re
         if (p1 - p0 > longest) longest = (uint32_t)(p1 - p0);
         wave_sync();
     }
-    // one atomic per block (the grid is capped), not per user
+    // the longest profile of this block (the grid is capped); the planning
+    // kernels reduce the per-block values
     __shared__ uint32_t bmax;
     if (threadIdx.x == 0) bmax = 0;
     __syncthreads();
     if (lane == 0 && longest) atomicMax(&bmax, longest);
     __syncthreads();
-    if (threadIdx.x == 0 && bmax) atomicMax(maxlen, bmax);
+    if (threadIdx.x == 0) bmax_out[blockIdx.x] = bmax;
+    if (plan_ctr && blockIdx.x == 0 && threadIdx.x < kPlanCtr) plan_ctr[threadIdx.x] = 0;
+}
+
+// Longest profile, from the per-block values of k_user_bits (block-wide).
+C2_DEV uint32_t block_max_len(const uint32_t *bmax, uint32_t nb) {
+    __shared__ uint32_t red;
+    if (threadIdx.x == 0) red = 0;
+    __syncthreads();
+    uint32_t v = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) v = bmax[i] > v ? bmax[i] : v;
+    if (v) atomicMax(&red, v);
+    __syncthreads();
+    return red;
 }
 
 // --------------------------------------------------------------- selection
@@ -787,11 +809,11 @@ C2_DEV uint32_t mfma_groups(uint32_t s, uint32_t group_tiles) {
 // clusters of one member get padded lists here.
 __global__ __launch_bounds__(256) void k_plan_count(KnnArgs a, const uint32_t *order,
                                                     uint32_t mfma_min, uint32_t group_tiles,
-                                                    const uint32_t *maxlen, uint64_t *cnt,
-                                                    uint32_t *slots) {
+                                                    const uint32_t *bmax, uint32_t nbmax,
+                                                    uint64_t *cnt, uint32_t *slots) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t ncl = a.cl_cfg_off[a.t];
-    if (*maxlen >= kMfmaMaxLen) mfma_min = 0xFFFFFFFFu;
+    if (block_max_len(bmax, nbmax) >= kMfmaMaxLen) mfma_min = 0xFFFFFFFFu;
     if (q >= a.NE) return;
     if (q >= ncl) { cnt[q] = 0; slots[q] = 0; return; }
     const uint32_t c = order ? order[q] : q;
@@ -848,16 +870,85 @@ __global__ __launch_bounds__(256) void k_plan_fill(KnnArgs a, const uint32_t *or
     for (uint32_t r = 0; r < nbm; ++r) items_b[bb + r] = ((uint64_t)c << 32) | r;
 }
 
-// Sort keys for the largest-first order: (NE - size) so that ascending order
-// is descending size, ties by cluster index (stable sort).
-__global__ __launch_bounds__(256) void k_plan_keys(const uint32_t *cl_off,
-                                                   const uint32_t *cl_cfg_off, uint32_t t,
-                                                   uint32_t NE, uint64_t *key, uint32_t *val) {
+// Batched planning without a sort.  The work items of the MFMA path fall into
+// cost classes by the number of column tiles an item covers (more tiles =
+// lower class index = taken first: the size-ordered queue of Section II-F).
+// Each cluster takes a contiguous range inside its class by an atomic on the
+// class counter, and scratch slots (split row blocks) and bitmap items by
+// atomics on their counters; k_user_bits cleared the counters.  The order of
+// clusters inside a class changes only the schedule, never a result.
+__global__ __launch_bounds__(256) void k_plan_classes(KnnArgs a, uint32_t mfma_min,
+                                                      uint32_t group_tiles,
+                                                      const uint32_t *bmax, uint32_t nbmax,
+                                                      uint32_t *pc, uint32_t *ccls,
+                                                      uint32_t *cpos, uint32_t *sbase) {
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= NE || c >= cl_cfg_off[t]) return;
-    const uint32_t s = cl_off[c + 1] - cl_off[c];
-    key[c] = (uint64_t)(NE - s);
-    val[c] = c;
+    if (block_max_len(bmax, nbmax) >= kMfmaMaxLen) mfma_min = 0xFFFFFFFFu;
+    if (c >= a.NE || c >= a.cl_cfg_off[a.t]) return;
+    const ClusterView cv = view(a, c);
+    uint32_t cls = 0xFFFFFFFFu, pos = 0;
+    if (cv.s >= mfma_min && cv.s >= 2) {
+        const uint32_t ng = mfma_groups(cv.s, group_tiles);
+        const uint32_t tiles = (cv.s + kMC - 1) / kMC, per = (tiles + ng - 1) / ng;
+        const uint32_t nit = ((cv.s + kMR - 1) / kMR) * ng;
+        cls = kCostClasses - 1 - (per < kCostClasses - 1 ? per : kCostClasses - 1);
+        pos = atomicAdd(&pc[cls], nit);
+        if (ng > 1) sbase[c] = atomicAdd(&pc[kSlotCtr], nit);
+    } else if (cv.s >= 2) {
+        cls = kCostClasses;
+        pos = atomicAdd(&pc[kBitmapCtr], (cv.s + kRowBlock - 1) / kRowBlock);
+    } else if (cv.s == 1) {
+        const uint32_t u = member(a, cv, 0);
+        if (u < a.n && cv.j < a.t) {
+            const size_t base = ((size_t)u * a.t + cv.j) * a.k;
+            for (uint32_t r = 0; r < a.k; ++r) {
+                a.part_id[base + r] = kPad;
+                a.part_I[base + r] = 0;
+            }
+        }
+    }
+    ccls[c] = cls;
+    cpos[c] = pos;
+}
+
+__global__ __launch_bounds__(256) void k_plan_items(KnnArgs a, uint32_t group_tiles,
+                                                    const uint32_t *pc, const uint32_t *ccls,
+                                                    const uint32_t *cpos, const uint32_t *sbase,
+                                                    uint64_t *items_m, uint64_t *items_b,
+                                                    uint32_t *rb_done, uint32_t *nitems,
+                                                    uint32_t *cursors) {
+    __shared__ uint32_t cbase[kCostClasses + 1];
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t q = 0; q < kCostClasses; ++q) {
+            cbase[q] = run;
+            run += pc[q];
+        }
+        cbase[kCostClasses] = run;
+    }
+    __syncthreads();
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) {
+        nitems[0] = cbase[kCostClasses];
+        nitems[1] = pc[kBitmapCtr];
+        cursors[0] = 0;
+        cursors[1] = 0;
+    }
+    if (c >= a.NE || c >= a.cl_cfg_off[a.t]) return;
+    const uint32_t cls = ccls[c];
+    if (cls < kCostClasses) {
+        const uint32_t s = a.cl_off[c + 1] - a.cl_off[c];
+        const uint32_t ng = mfma_groups(s, group_tiles), nrb = (s + kMR - 1) / kMR;
+        const uint32_t b0 = cbase[cls] + cpos[c];
+        for (uint32_t r = 0; r < nrb; ++r) {
+            for (uint32_t g = 0; g < ng; ++g) items_m[b0 + r * ng + g] = mfma_item_code(c, r, g, ng);
+            if (ng > 1) rb_done[sbase[c] + r * ng] = 0;
+        }
+    } else if (cls == kCostClasses) {
+        const uint32_t s = a.cl_off[c + 1] - a.cl_off[c];
+        const uint32_t nrb = (s + kRowBlock - 1) / kRowBlock;
+        for (uint32_t r = 0; r < nrb; ++r) items_b[cpos[c] + r] = ((uint64_t)c << 32) | r;
+    }
 }
 
 // --------------------------------------------------------------- host side
@@ -894,9 +985,18 @@ size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w) {
     x.htmp = take(4 * scan_tmp_elems((uint32_t)(hist > NE + 1 ? hist : NE + 1)));
     x.ctmp = take(8 * scan_tmp_elems(NE + 1));
     x.ctr = take(4 * 8);
+    x.bmax = take(4 * kUserBitsGrid);
+    x.pc = take(4 * kPlanCtr);
+    x.ccls = take(4 * (size_t)NE);
+    x.cpos = take(4 * (size_t)NE);
     x.total = off;
     if (w) *w = x;
     return off;
+}
+
+static uint32_t user_bits_grid(const KnnArgs &a) {
+    const uint32_t grid = (uint32_t)div_up((uint64_t)a.n + 1, kStageWaves);
+    return grid < kUserBitsGrid ? grid : kUserBitsGrid;
 }
 
 static hipError_t user_bits(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
@@ -904,10 +1004,8 @@ static hipError_t user_bits(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
     hipError_t e = hipFuncSetAttribute((const void *)k_user_bits,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    if ((e = launch_fill_u32(w.ctr + 4, 0, 1, s)) != hipSuccess) return e;
-    const uint32_t grid = (uint32_t)div_up((uint64_t)a.n + 1, kStageWaves);
-    hipLaunchKernelGGL(k_user_bits, dim3(grid < 512 ? grid : 512), dim3(kStageThreads), lds, s,
-                       a.indptr, a.indices, a.nnz, a.n, a.m, a.wmax, w.rows, w.rlen, w.ctr + 4);
+    hipLaunchKernelGGL(k_user_bits, dim3(user_bits_grid(a)), dim3(kStageThreads), lds, s,
+                       a.indptr, a.indices, a.nnz, a.n, a.m, a.wmax, w.rows, w.rlen, w.bmax, w.pc);
     return hipGetLastError();
 }
 
@@ -916,8 +1014,8 @@ static hipError_t plan(const KnnArgs &a, const KnnPtrs &w, const uint32_t *order
     const uint32_t mfma_min = o.mfma_min ? o.mfma_min : kDefaultMfmaMin;
     const uint32_t gt = o.group_tiles ? o.group_tiles : kGroupTiles;  // >= 1
     const dim3 g((uint32_t)div_up(a.NE, 256));
-    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a, order, mfma_min, gt, w.ctr + 4, w.cnt,
-                       w.slots);
+    hipLaunchKernelGGL(k_plan_count, g, dim3(256), 0, s, a, order, mfma_min, gt, w.bmax,
+                       user_bits_grid(a), w.cnt, w.slots);
     hipError_t e = scan_u64(w.cnt, w.cnt, a.NE, w.ctmp, s);
     if (e != hipSuccess) return e;
     if ((e = scan_u32(w.slots, w.slots, a.NE, w.htmp, s)) != hipSuccess) return e;
@@ -960,18 +1058,18 @@ hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipSt
 hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
     hipError_t e = user_bits(a, w, s);
     if (e != hipSuccess) return e;
+    // items by cost class, costliest first (the size-ordered queue of
+    // Section II-F), without a sort
     const dim3 g((uint32_t)div_up(a.NE, 256));
-    // largest clusters first (the size-ordered queue of Section II-F)
-    hipLaunchKernelGGL(k_plan_keys, g, dim3(256), 0, s, a.cl_off, a.cl_cfg_off, a.t, a.NE,
-                       w.csort_key, w.csort_val);
-    bool in_alt = false;
-    e = radix_sort(w.csort_key, w.csort_val, w.csort_key_alt, w.csort_val_alt, a.cl_cfg_off + a.t,
-                   a.NE, bit_width(a.NE), w.hist, w.htmp, &in_alt, s);
-    if (e != hipSuccess) return e;
-    const uint32_t *order = in_alt ? w.csort_val_alt : w.csort_val;
-    if ((e = plan(a, w, order, o, true, s)) != hipSuccess) return e;
+    const uint32_t mfma_min = o.mfma_min ? o.mfma_min : kDefaultMfmaMin;
+    const uint32_t gt = o.group_tiles ? o.group_tiles : kGroupTiles;
+    hipLaunchKernelGGL(k_plan_classes, g, dim3(256), 0, s, a, mfma_min, gt, w.bmax,
+                       user_bits_grid(a), w.pc, w.ccls, w.cpos, w.sbase);
+    hipLaunchKernelGGL(k_plan_items, g, dim3(256), 0, s, a, gt, w.pc, w.ccls, w.cpos, w.sbase,
+                       w.items_m, w.items_b, w.rb_done, w.ctr, w.ctr + 2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const uint32_t gm = o.persistent_wgs ? o.persistent_wgs : 512;
-    return launch_paths(a, w, o, gm, 2048, true, s);
+    return launch_paths(a, w, o, gm, kBitmapPersistent, true, s);
 }
 
 }  // namespace c2
