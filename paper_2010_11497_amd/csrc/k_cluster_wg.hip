@@ -26,6 +26,8 @@ constexpr int kWgWaves = kWgThreads / 64;
 constexpr uint32_t kWgPer = kWgMaxN / kWgThreads;  // slots per thread in scans
 constexpr uint32_t kNoValue = 0xFFFFFFFFu;
 constexpr uint32_t kRankTab = kWgMaxN / 2;          // active segments hold >= 2 users
+constexpr uint32_t kWideBits = 10;                  // keys this short sort in one pass
+constexpr uint32_t kWideBins = 1u << kWideBits;
 
 // Insert x into the ascending list s of distinct values (kNoValue = empty),
 // keeping the kSigD smallest.
@@ -40,57 +42,76 @@ C2_DEV void sig_insert(uint32_t (&s)[kSigD], uint32_t x) {
 }
 
 // sig[(j*n + u)*kSigD + r] = the (r+1)-th smallest distinct value of
-// h_j over P_u, or kNoValue.  kSigLanes lanes per (j, u); the first thread
-// also clears the status word and the round counter of the workgroup pass.
+// h_j over P_u, or kNoValue.  Block (x, j) takes kSigUsers users of
+// configuration j, kSigLanes lanes per user; with STAGE the configuration's
+// bucket table is first copied to LDS, so the per-item lookups are LDS reads.
+// The first thread also clears the status word and the round counter of the
+// workgroup pass.
+constexpr uint32_t kSigUsers = 32;  // one user per lane group: many blocks in flight
+static_assert(kSigD == kSigLanes, "lane r of a group writes signature value r");
+constexpr uint32_t kSigTableMax = 8192;  // items whose bucket table is staged in LDS
+
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_signature(const int64_t *__restrict__ indptr,
                                                    const uint32_t *__restrict__ indices,
                                                    uint64_t nnz, uint32_t n, uint32_t m,
                                                    const uint32_t *__restrict__ bucket,
-                                                   uint32_t t, uint32_t *__restrict__ sig,
+                                                   uint32_t *__restrict__ sig,
                                                    uint32_t *status, uint32_t *rctr) {
-    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid == 0) {
+    extern __shared__ uint32_t tbl[];  // m entries when STAGE
+    const uint32_t j = blockIdx.y;
+    if (blockIdx.x == 0 && j == 0 && threadIdx.x == 0) {
         if (status) *status = 0;
         *rctr = 0;
     }
-    const uint64_t g = gid / kSigLanes;
-    const uint32_t gl = threadIdx.x % kSigLanes;
-    if (g >= (uint64_t)t * n) return;  // whole groups leave together
-    const uint32_t j = (uint32_t)(g / n), u = (uint32_t)(g % n);
     const uint32_t *bj = bucket + (size_t)j * m;
-    uint32_t s[kSigD];
-#pragma unroll
-    for (int i = 0; i < kSigD; ++i) s[i] = kNoValue;
-    uint64_t a, e;
-    row_range(indptr, u, nnz, a, e);
-    // four index -> bucket gathers in flight per lane
-    for (uint64_t p = a + gl; p < e; p += 4 * kSigLanes) {
-        uint32_t it[4], x[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint64_t pq = p + (uint64_t)q * kSigLanes;
-            it[q] = pq < e ? indices[pq] : m;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = it[q] < m ? bj[it[q]] : kNoValue;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sig_insert(s, x[q]);
+    if (STAGE) {
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) tbl[i] = bj[i];
+        __syncthreads();
     }
-    uint32_t *out = sig + g * kSigD;
+    const uint32_t *look = STAGE ? tbl : bj;
+    const uint32_t gl = threadIdx.x % kSigLanes;
+    const uint32_t u0 = blockIdx.x * kSigUsers;
+    for (uint32_t ub = threadIdx.x / kSigLanes; ub < kSigUsers; ub += blockDim.x / kSigLanes) {
+        const uint32_t u = u0 + ub;
+        if (u >= n) break;  // whole groups leave together
+        uint32_t s[kSigD];
 #pragma unroll
-    for (int r = 0; r < kSigD; ++r) {
-        uint32_t mn = s[0];
+        for (int i = 0; i < kSigD; ++i) s[i] = kNoValue;
+        uint64_t a, e;
+        row_range(indptr, u, nnz, a, e);
+        // four index -> bucket lookups in flight per lane
+        for (uint64_t p = a + gl; p < e; p += 4 * kSigLanes) {
+            uint32_t it[4], x[4];
 #pragma unroll
-        for (int d = kSigLanes / 2; d > 0; d >>= 1) {
-            const uint32_t o = __shfl_xor(mn, d, kSigLanes);
-            mn = o < mn ? o : mn;
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t pq = p + (uint64_t)q * kSigLanes;
+                it[q] = pq < e ? indices[pq] : m;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = it[q] < m ? look[it[q]] : kNoValue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sig_insert(s, x[q]);
         }
-        if (gl == 0) out[r] = mn;
-        if (s[0] == mn && mn != kNoValue) {
+        // merge the lanes' lists: kSigD times the group minimum of the heads;
+        // lane r keeps the r-th value and the group writes them together
+        uint32_t mine = kNoValue;
 #pragma unroll
-            for (int i = 0; i + 1 < kSigD; ++i) s[i] = s[i + 1];
-            s[kSigD - 1] = kNoValue;
+        for (int r = 0; r < kSigD; ++r) {
+            uint32_t mn = s[0];
+#pragma unroll
+            for (int d = kSigLanes / 2; d > 0; d >>= 1) {
+                const uint32_t o = __shfl_xor(mn, d, kSigLanes);
+                mn = o < mn ? o : mn;
+            }
+            if ((uint32_t)r == gl) mine = mn;
+            if (s[0] == mn && mn != kNoValue) {
+#pragma unroll
+                for (int i = 0; i + 1 < kSigD; ++i) s[i] = s[i + 1];
+                s[kSigD - 1] = kNoValue;
+            }
         }
+        sig[((size_t)j * n + u) * kSigD + gl] = mine;
     }
 }
 
@@ -103,8 +124,8 @@ struct WgLds {
     uint8_t st[kWgMaxN];        // state of the segment starting at this slot
     uint8_t rflag[kWgMaxN];     // active slot that stays behind this round
     uint16_t tab[4][kRankTab];  // radix tables, then per-rank bookkeeping
-    uint32_t hist[256];
-    uint32_t base[256];
+    uint32_t hist[kWideBins];
+    uint32_t base[kWideBins];
     uint32_t wsum[kWgWaves + 1];
 };
 
@@ -126,54 +147,63 @@ C2_DEV uint32_t wg_scan(uint32_t (&v)[kWgPer], uint32_t *wsum) {
 }
 
 // Stable LSD radix sort of the A slot indices in L.idx[0] by L.key[slot] over
-// nbits bits, 8 bits per pass.  Returns the buffer holding the result.
+// nbits bits: one pass of up to kWideBits bits if the key is that short, else
+// passes of 8 bits.  Inside a pass, elements are taken in index order 1024 at
+// a time; a wave ranks equal digits by ballots and per-wave digit counts give
+// the offsets.  Returns the buffer holding the result.
 C2_DEV int wg_sort(WgLds &L, uint32_t A, uint32_t nbits) {
     const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    uint16_t(*wcnt)[256] = reinterpret_cast<uint16_t(*)[256]>(&L.tab[0][0]);
-    uint16_t(*woff)[256] = reinterpret_cast<uint16_t(*)[256]>(&L.tab[2][0]);
+    const uint32_t width = nbits <= kWideBits ? kWideBits : 8;
+    const uint32_t nbins = 1u << width;
+    // per-wave digit counts, turned into offsets in place: [kWgWaves][nbins]
+    uint16_t *wtab = &L.tab[0][0];
+    static_assert(kWgWaves * kWideBins <= 4 * kRankTab, "radix table fits the bookkeeping area");
     int in = 0;
-    for (uint32_t sh = 0; sh < nbits; sh += 8) {
-        if (tid < 256) L.hist[tid] = 0;
-        for (uint32_t w = tid; w < kWgWaves * 256; w += kWgThreads) (&wcnt[0][0])[w] = 0;
+    for (uint32_t sh = 0; sh < nbits; sh += width) {
+        const uint32_t dmask = nbins - 1;
+        for (uint32_t d = tid; d < nbins; d += kWgThreads) L.hist[d] = 0;
+        for (uint32_t w = tid; w < kWgWaves * nbins; w += kWgThreads) wtab[w] = 0;
         __syncthreads();
         for (uint32_t i = tid; i < A; i += kWgThreads)
-            atomicAdd(&L.hist[(L.key[L.idx[in][i]] >> sh) & 255u], 1u);
+            atomicAdd(&L.hist[(L.key[L.idx[in][i]] >> sh) & dmask], 1u);
         __syncthreads();
         {
             uint32_t total;
-            const uint32_t h = tid < 256 ? L.hist[tid] : 0u;
+            const uint32_t h = tid < nbins ? L.hist[tid] : 0u;
             const uint32_t ex = block_excl_scan<uint32_t, kWgThreads>(h, L.wsum, &total);
-            if (tid < 256) L.base[tid] = ex;
+            if (tid < nbins) L.base[tid] = ex;
         }
         __syncthreads();
         for (uint32_t i0 = 0; i0 < A; i0 += kWgThreads) {
             const uint32_t i = i0 + tid;
             const bool valid = i < A;
             const uint32_t s = valid ? L.idx[in][i] : 0u;
-            const uint32_t d = valid ? (L.key[s] >> sh) & 255u : 0u;
+            const uint32_t d = valid ? (L.key[s] >> sh) & dmask : 0u;
             uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int bit = 0; bit < 8; ++bit) {
+            for (uint32_t bit = 0; bit < width; ++bit) {
                 const bool on = (d >> bit) & 1u;
                 const uint64_t bb = __ballot(on);
                 peers &= on ? bb : ~bb;
             }
             const uint32_t wrank = (uint32_t)__popcll(peers & lt_mask);
-            if (valid && wrank == 0) wcnt[wid][d] = (uint16_t)__popcll(peers);
+            if (valid && wrank == 0) wtab[wid * nbins + d] = (uint16_t)__popcll(peers);
             __syncthreads();
-            if (tid < 256) {
-                uint32_t run = L.base[tid];
+            for (uint32_t dd = tid; dd < nbins; dd += kWgThreads) {
+                uint32_t run = L.base[dd];
 #pragma unroll
                 for (int w = 0; w < kWgWaves; ++w) {
-                    woff[w][tid] = (uint16_t)run;
-                    run += wcnt[w][tid];
-                    wcnt[w][tid] = 0;
+                    const uint32_t c = wtab[w * nbins + dd];
+                    wtab[w * nbins + dd] = (uint16_t)run;
+                    run += c;
                 }
-                L.base[tid] = run;
+                L.base[dd] = run;
             }
             __syncthreads();
-            if (valid) L.idx[in ^ 1][woff[wid][d] + wrank] = (uint16_t)s;
+            if (valid) L.idx[in ^ 1][wtab[wid * nbins + d] + wrank] = (uint16_t)s;
+            __syncthreads();
+            for (uint32_t w = tid; w < kWgWaves * nbins; w += kWgThreads) wtab[w] = 0;
+            __syncthreads();
         }
         __syncthreads();
         in ^= 1;
@@ -255,18 +285,34 @@ __global__ __launch_bounds__(kWgThreads) void k_clu_wg(
         }
         __syncthreads();
         // (2) sort keys: rank of the segment, then the next hash value
-        for (uint32_t i = tid; i < A; i += kWgThreads) {
-            const uint32_t p = L.idx[0][i];
-            const uint32_t u = L.uid[p];
-            uint32_t e;
-            if (round < (uint32_t)kSigD) e = sj[(size_t)u * kSigD + round];
-            else e = min_above(indptr, indices, nnz, bj, m, b, u, L.key[p]);
-            if (e >= b) e = b;  // no value above eta
-            L.key[p] = ((uint32_t)L.idx[1][L.seg[p]] << bb) | e;
+        if (round < (uint32_t)kSigD) {
+            uint32_t e[kWgPer];  // all lookups in flight first
+#pragma unroll
+            for (uint32_t i = 0; i < kWgPer; ++i) {
+                const uint32_t q = tid + i * kWgThreads;
+                e[i] = q < A ? sj[(size_t)L.uid[L.idx[0][q]] * kSigD + round] : 0u;
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < kWgPer; ++i) {
+                const uint32_t q = tid + i * kWgThreads;
+                if (q < A) {
+                    const uint32_t p = L.idx[0][q];
+                    const uint32_t ev = e[i] >= b ? b : e[i];  // b: no value above eta
+                    L.key[p] = ((uint32_t)L.idx[1][L.seg[p]] << bb) | ev;
+                }
+            }
+        } else {
+            for (uint32_t q = tid; q < A; q += kWgThreads) {
+                const uint32_t p = L.idx[0][q];
+                uint32_t ev = min_above(indptr, indices, nnz, bj, m, b, L.uid[p], L.key[p]);
+                if (ev >= b) ev = b;
+                L.key[p] = ((uint32_t)L.idx[1][L.seg[p]] << bb) | ev;
+            }
         }
         __syncthreads();
         // (3) stable sort of the active slots by key
-        const uint32_t nbits = bb + bit_width_dev(nseg - 1);
+        // at the top level every user has a value below b
+        const uint32_t nbits = round == 0 ? bit_width_dev(b - 1) : bb + bit_width_dev(nseg - 1);
         const int res = wg_sort(L, A, nbits);
         uint16_t *sorted = L.idx[res];
         uint16_t *runs = L.idx[res ^ 1];
@@ -458,9 +504,13 @@ hipError_t cluster_wg_run(const ClusterArgs &a, uint32_t *members, uint32_t *cl_
     uint32_t *ccount = cstart + NE;
     uint32_t *rctr = ccount + 64;
     if (rctr_out) *rctr_out = rctr;
-    const uint64_t threads = NE * kSigLanes;
-    hipLaunchKernelGGL(k_signature, dim3((uint32_t)div_up(threads, 256)), dim3(256), 0, s,
-                       a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket, a.t, sig, status, rctr);
+    const dim3 sg((uint32_t)div_up(a.n, kSigUsers), a.t);
+    if (a.m <= kSigTableMax)
+        hipLaunchKernelGGL(k_signature<true>, sg, dim3(256), 4 * (size_t)a.m, s, a.indptr,
+                           a.indices, a.nnz, a.n, a.m, a.bucket, sig, status, rctr);
+    else
+        hipLaunchKernelGGL(k_signature<false>, sg, dim3(256), 0, s, a.indptr, a.indices, a.nnz,
+                           a.n, a.m, a.bucket, sig, status, rctr);
     hipLaunchKernelGGL(k_clu_wg, dim3(a.t), dim3(kWgThreads), 0, s, a.indptr, a.indices, a.nnz,
                        a.n, a.m, a.bucket, sig, a.b, a.bb, a.cap, max_rounds, members, cstart,
                        ccount, status, rctr);
