@@ -51,7 +51,8 @@ def source_hash():
 
 def traffic_from_profiles(workload):
     """HBM bytes per launch of the local-KNN kernel from the committed PMC
-    summary, only if it was taken on the current kernel source."""
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a device copy of known size),
+    only if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (KNN_KERNEL, workload))
     if not os.path.exists(path):
         return None
