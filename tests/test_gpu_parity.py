@@ -306,11 +306,53 @@ def test_workload_full_parity(orc, name):
         got = c2.build(dP, dtab, p, form)
         for g, want in zip(got, (r.knn_id, r.knn_I, r.knn_U)):
             assert np.array_equal(u32(g), want)
+    # the launch configuration the benchmark times: graph replays of the
+    # batched build with the autotuner's schedule for this workload
+    from paper_2010_11497_amd import autotune
+    g = c2.Graph(dP, dtab, p, c2.tuning(**(autotune.load_table(name) or {})))
+    for _ in range(2):
+        out = g.launch()
+        torch.cuda.synchronize()
+        g.check()
+        for a, want in zip(out, (r.knn_id, r.knn_I, r.knn_U)):
+            assert np.array_equal(u32(a), want)
+    g.close()
     bf = c2.brute_force(dP, w.k)
     rows = np.random.Generator(np.random.PCG64(1)).choice(P.n, size=200, replace=False)
     want = orc.brute_force(P.indptr, P.indices, P.n, P.m, w.k, rows=rows, threads=THREADS)
     for g, ww in zip(bf, want):
         assert np.array_equal(u32(g)[rows], ww)
+
+
+def test_workload_sampled_parity_n70k(orc):
+    # 70,000 users: the whole partition against the oracle's, and the graph
+    # on sampled users against the definition (top-k over the users that
+    # share a final cluster), both from the graph form the benchmark times
+    from paper_2010_11497_amd import autotune
+    name = "n70k_m10k"
+    w = synth.WORKLOADS[name]
+    say("workload sampled", name)
+    P = synth.make_profiles(w)
+    tab = synth.hash_tables(w.t, w.hash_seed)
+    dP, dtab = gpu_inputs(P, tab)
+    p = c2.params(w.t, w.b, w.cap, w.k)
+    bucket = orc.hash_items(tab, w.b, w.m)
+    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, w.cap)
+    gm, goff, gcfg, _ = c2.cluster(dP, c2.hash_items(dtab, w.b, w.m), p, c2.FORM_PLAIN)
+    gcfg = u32(gcfg)
+    assert np.array_equal(gcfg, ocfg)
+    assert np.array_equal(u32(goff)[: gcfg[-1] + 1], ooff)
+    assert np.array_equal(u32(gm), om)
+    g = c2.Graph(dP, dtab, p, c2.tuning(**(autotune.load_table(name) or {})))
+    out = [u32(x) for x in g.launch()]
+    torch.cuda.synchronize()
+    g.check()
+    g.close()
+    rows = np.random.Generator(np.random.PCG64(7)).choice(P.n, size=300, replace=False)
+    want = orc.candidate_topk(P.indptr, P.indices, P.n, P.m, w.t, w.k, om, ooff, ocfg,
+                              rows=rows, threads=THREADS)
+    for a, ww in zip(out, want):
+        assert np.array_equal(a[rows], ww)
 
 
 def test_long_profiles_take_exact_fallback(orc):
