@@ -430,15 +430,19 @@ struct KeyHeap {
     // 4-ary min-heap: the children of p are 4p+1 .. 4p+4.  The four child
     // slots are read together (an index past the end reads the last entry
     // again, which never wins the strict comparisons), so each level costs one
-    // LDS round trip.  Returns the entry that ends up at pos.
+    // LDS round trip.  A heap of at most 85 entries is at most three levels
+    // below any node, so the descent is unrolled three times with no loop.
+    // Returns the entry that ends up at pos.
     C2_DEV uint64_t sift_down(uint32_t pos, uint64_t v, uint32_t size) {
         uint64_t top = v;
-        bool moved = false;
-        for (;;) {
+        bool done = false;
+        const uint32_t last = size - 1;
+#pragma unroll
+        for (int lvl = 0; lvl < 3; ++lvl) {
             const uint32_t c0 = 4 * pos + 1;
-            if (c0 >= size) break;
-            const uint32_t last = size - 1;
-            const uint64_t x0 = get(c0);
+            done |= c0 >= size;
+            const uint32_t i0 = c0 < last ? c0 : last;
+            const uint64_t x0 = get(i0);
             const uint64_t x1 = get(c0 + 1 < last ? c0 + 1 : last);
             const uint64_t x2 = get(c0 + 2 < last ? c0 + 2 : last);
             const uint64_t x3 = get(c0 + 3 < last ? c0 + 3 : last);
@@ -447,11 +451,13 @@ struct KeyHeap {
             if (x1 < best) { best = x1; bi = c0 + 1; }
             if (x2 < best) { best = x2; bi = c0 + 2; }
             if (x3 < best) { best = x3; bi = c0 + 3; }
-            if (v <= best) break;
-            if (!moved) top = best;
-            moved = true;
-            put(pos, best);
-            pos = bi;
+            const bool mv = !done && v > best;
+            if (mv) {
+                put(pos, best);
+                if (lvl == 0) top = best;
+                pos = bi;
+            }
+            done |= !mv;
         }
         put(pos, v);
         return top;
@@ -679,6 +685,38 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
                     }
                     m0 &= k0;
                     m1 &= k1;
+                }
+            }
+            // While a row's heap holds fewer than k entries, both threads of the
+            // pair append passing candidates in parallel (the owner's first,
+            // then its helper's, up to k in all); the owner heapifies once the
+            // heap is full.  Candidates beyond k go through the insert loop.
+            const uint32_t cnt0 = __shfl(h.cnt, lane & ~1u);
+            if (__any(active && cnt0 < a.k)) {
+                const uint32_t pmine = __popc(m0) + __popc(m1);
+                const uint32_t pown = __shfl(pmine, lane & ~1u);
+                const uint32_t room = active && cnt0 < a.k ? a.k - cnt0 : 0u;
+                const uint32_t aown = pown < room ? pown : room;
+                const uint32_t quota = half == 0 ? aown
+                                                 : (pmine < room - aown ? pmine : room - aown);
+                uint32_t slot = cnt0 + (half == 0 ? 0u : aown);
+                for (uint32_t i = 0; i < quota; ++i) {
+                    const bool lo = m0 != 0u;
+                    const uint32_t bit = __ffs(lo ? m0 : m1) - 1;
+                    if (lo) m0 &= m0 - 1;
+                    else m1 &= m1 - 1;
+                    const uint32_t q = q0 + (lo ? 0u : 32u) + bit;
+                    const uint32_t I = L.u.itile[r][q];
+                    const uint32_t U = Lr + L.clen[q] - I, uid = L.cuid[q];
+                    h.put(slot++, ((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid));
+                }
+                const uint32_t ahelp = __shfl(quota, lane | 1u);
+                if (owner && cnt0 < a.k) {
+                    h.cnt = cnt0 + aown + ahelp;
+                    if (h.cnt == a.k) {
+                        h.heapify(a.k);
+                        h.root = h.get(0);
+                    }
                 }
             }
             // the owner takes its helper's masks (adjacent lane)
