@@ -20,7 +20,7 @@
 
 namespace c2 {
 
-constexpr int kSigLanes = 8;
+constexpr int kSigLanes = 16;  // lanes per user: the longest profile sets the kernel's time
 constexpr int kWgThreads = 1024;
 constexpr int kWgWaves = kWgThreads / 64;
 constexpr uint32_t kWgPer = kWgMaxN / kWgThreads;  // slots per thread in scans
@@ -47,8 +47,8 @@ C2_DEV void sig_insert(uint32_t (&s)[kSigD], uint32_t x) {
 // bucket table is first copied to LDS, so the per-item lookups are LDS reads.
 // The first thread also clears the status word and the round counter of the
 // workgroup pass.
-constexpr uint32_t kSigUsers = 32;  // one user per lane group: many blocks in flight
-static_assert(kSigD == kSigLanes, "lane r of a group writes signature value r");
+constexpr uint32_t kSigUsers = 16;  // one user per lane group: many blocks in flight
+static_assert(kSigD <= kSigLanes, "lane r < kSigD of a group writes signature value r");
 constexpr uint32_t kSigTableMax = 8192;  // items whose bucket table is staged in LDS
 
 template <bool STAGE>
@@ -80,18 +80,18 @@ __global__ __launch_bounds__(256) void k_signature(const int64_t *__restrict__ i
         for (int i = 0; i < kSigD; ++i) s[i] = kNoValue;
         uint64_t a, e;
         row_range(indptr, u, nnz, a, e);
-        // four index -> bucket lookups in flight per lane
-        for (uint64_t p = a + gl; p < e; p += 4 * kSigLanes) {
-            uint32_t it[4], x[4];
+        // eight index -> bucket lookups in flight per lane
+        for (uint64_t p = a + gl; p < e; p += 8 * kSigLanes) {
+            uint32_t it[8], x[8];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 const uint64_t pq = p + (uint64_t)q * kSigLanes;
                 it[q] = pq < e ? indices[pq] : m;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = it[q] < m ? look[it[q]] : kNoValue;
+            for (int q = 0; q < 8; ++q) x[q] = it[q] < m ? look[it[q]] : kNoValue;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sig_insert(s, x[q]);
+            for (int q = 0; q < 8; ++q) sig_insert(s, x[q]);
         }
         // merge the lanes' lists: kSigD times the group minimum of the heads;
         // lane r keeps the r-th value and the group writes them together
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_signature(const int64_t *__restrict__ i
                 s[kSigD - 1] = kNoValue;
             }
         }
-        sig[((size_t)j * n + u) * kSigD + gl] = mine;
+        if (gl < (uint32_t)kSigD) sig[((size_t)j * n + u) * kSigD + gl] = mine;
     }
 }
 
@@ -187,6 +187,10 @@ C2_DEV int wg_sort(WgLds &L, uint32_t A, uint32_t nbits) {
                 peers &= on ? bb : ~bb;
             }
             const uint32_t wrank = (uint32_t)__popcll(peers & lt_mask);
+            // a wave writes and reads only its own row of the table outside the
+            // conversion, which turns the counts into offsets where the count
+            // is not zero; the leader of each digit clears its entry after use,
+            // so the table is all zero again for the next 1024 elements
             if (valid && wrank == 0) wtab[wid * nbins + d] = (uint16_t)__popcll(peers);
             __syncthreads();
             for (uint32_t dd = tid; dd < nbins; dd += kWgThreads) {
@@ -194,16 +198,15 @@ C2_DEV int wg_sort(WgLds &L, uint32_t A, uint32_t nbits) {
 #pragma unroll
                 for (int w = 0; w < kWgWaves; ++w) {
                     const uint32_t c = wtab[w * nbins + dd];
-                    wtab[w * nbins + dd] = (uint16_t)run;
+                    if (c) wtab[w * nbins + dd] = (uint16_t)run;
                     run += c;
                 }
                 L.base[dd] = run;
             }
             __syncthreads();
-            if (valid) L.idx[in ^ 1][wtab[wid * nbins + d] + wrank] = (uint16_t)s;
-            __syncthreads();
-            for (uint32_t w = tid; w < kWgWaves * nbins; w += kWgThreads) wtab[w] = 0;
-            __syncthreads();
+            const uint32_t off = valid ? wtab[wid * nbins + d] : 0u;
+            if (valid) L.idx[in ^ 1][off + wrank] = (uint16_t)s;
+            if (valid && wrank == 0) wtab[wid * nbins + d] = 0;
         }
         __syncthreads();
         in ^= 1;
