@@ -30,42 +30,51 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
     __shared__ uint32_t sv[UPW * G * kMaxK], sI[UPW * G * kMaxK], sU[UPW * G * kMaxK];
     const uint32_t lane = threadIdx.x;
     const uint64_t u0 = (uint64_t)blockIdx.x * UPW;
-    // stage: entries of users u0 .. u0+UPW-1, list j, slot r at ((ul*G + j)*k + r);
-    // four entries per lane per step so that their dependent loads overlap
+    // stage: entries of users u0 .. u0+UPW-1, list j, slot r at ((ul*G + j)*k + r).
+    // The profile lengths of the block's users first; then, per lane, up to
+    // 16 entries with all their loads (entry, then the neighbour's row
+    // bounds) in flight before any is used.
+    __shared__ uint32_t ulen_s[UPW];
+    const uint32_t nu = (uint32_t)(u0 + UPW <= n ? UPW : (u0 < n ? n - u0 : 0));
+    if (lane < nu) {
+        uint64_t a0, a1;
+        row_range(indptr, (uint32_t)(u0 + lane), nnz, a0, a1);
+        ulen_s[lane] = (uint32_t)(a1 - a0);
+    }
+    __syncthreads();
     {
-        const uint32_t nu = (uint32_t)(u0 + UPW <= n ? UPW : (u0 < n ? n - u0 : 0));
-        const uint32_t total = nu * t * k;
-        const size_t base = (size_t)u0 * t * k;
-        for (uint32_t e0 = 0; e0 < total; e0 += 4 * kMergeThreads) {
-            uint32_t v[4], I[4], lu[4], lv[4];
+        const uint32_t tk = t * k;
+        const uint32_t total = nu * tk;
+        const size_t base = (size_t)u0 * tk;
+        for (uint32_t e0 = 0; e0 < total; e0 += 16 * kMergeThreads) {
+            uint32_t v[16], I[16];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 16; ++q) {
                 const uint32_t e = e0 + q * kMergeThreads + lane;
                 v[q] = e < total ? part_id[base + e] : kPad;
                 I[q] = e < total ? part_I[base + e] : 0;
             }
+            int64_t b0[16], b1[16];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t e = e0 + q * kMergeThreads + lane;
-                lu[q] = lv[q] = 0;
-                if (e < total && v[q] < n) {
-                    uint64_t a0, a1, b0, b1;
-                    row_range(indptr, (uint32_t)(u0 + e / (t * k)), nnz, a0, a1);
-                    row_range(indptr, v[q], nnz, b0, b1);
-                    lu[q] = (uint32_t)(a1 - a0);
-                    lv[q] = (uint32_t)(b1 - b0);
-                }
+            for (int q = 0; q < 16; ++q) {
+                const bool ok = v[q] < n;
+                b0[q] = ok ? indptr[v[q]] : 0;
+                b1[q] = ok ? indptr[v[q] + 1] : 0;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 16; ++q) {
                 const uint32_t e = e0 + q * kMergeThreads + lane;
                 if (e >= total) continue;
-                const uint32_t ul = e / (t * k), rem = e % (t * k);
+                const uint32_t ul = e / tk, rem = e % tk;
                 const uint32_t d = (ul * G + rem / k) * k + rem % k;
-                const bool ok = v[q] != kPad && v[q] < n;
+                const bool ok = v[q] < n;
+                // the row bounds clamped as row_range does
+                const int64_t lb = b0[q] < 0 ? 0 : b0[q];
+                const int64_t hb = b1[q] < (int64_t)nnz ? b1[q] : (int64_t)nnz;
+                const uint32_t lv = ok && hb > lb ? (uint32_t)(hb - lb) : 0u;
                 sv[d] = ok ? v[q] : kPad;
                 sI[d] = ok ? I[q] : 0;
-                sU[d] = ok ? lu[q] + lv[q] - I[q] : 0;
+                sU[d] = ok ? ulen_s[ul] + lv - I[q] : 0;
             }
         }
     }
