@@ -327,10 +327,12 @@ __global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *ub
 // which preserves the order of I/U exactly when U < 2^16 (two different
 // fractions with denominators below 2^16 differ by more than 1/(2^32 - 1)),
 // so the path is taken only when every profile has fewer than 2^15 items.
-// A heap entry is the u64 (key << 32) | (0xFFFFFFFF - id): larger is better.
-// Each tile is first filtered against the heap root (exactly, without a
-// division: key(I, U) > key_T  <=>  I * (2^32 - 1) >= (key_T + 1) * U), then
-// the candidates that passed are inserted in a wave-uniform loop.
+// A heap entry is the u64 (key << 32) | (0xFFFFFFFF - id): larger is better,
+// and entries are distinct, so an entry beats the root iff it compares
+// greater.  Each tile is first filtered against the heap root with a
+// necessary fp32 test (and, when many pass, against the k best of the tile);
+// the candidates that pass are inserted in a wave-uniform loop, where the
+// exact comparison is made.
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
@@ -392,15 +394,24 @@ C2_DEV uint64_t load_bits(const uint64_t *row, uint32_t chunk, uint32_t nchunks)
     return row[chunk < nchunks ? chunk : nchunks - 1];
 }
 
-// floor(I * (2^32 - 1) / U) for 0 <= I <= U < 2^16, U >= 1: a double
-// estimate (absolute error < 2^-20) and one exact integer correction.
+// floor(I * (2^32 - 1) / U) for 0 <= I <= U < 2^16, U >= 1, without a
+// division: an fp32 estimate from the reciprocal of U (within 2^10 of the
+// quotient), one correction from the exact 32-bit remainder scaled by the
+// same reciprocal (within 1), and a final step on the sign and size of the
+// remainder.  Every remainder is below 2^31 in magnitude, so 32-bit integer
+// arithmetic is exact.  Checked against 64-bit division for all (I, U) with
+// the reciprocal exact, and on a sample with it 1 and 2 ulp off.
 C2_DEV uint32_t jkey(uint32_t I, uint32_t U) {
-    const uint64_t N = ((uint64_t)I << 32) - I;
-    uint64_t q = (uint64_t)((double)N / (double)U);
-    const uint64_t p = q * U;
-    if (p > N) q -= 1;
-    else if (p + U <= N) q += 1;
-    return (uint32_t)q;
+    const float r = __builtin_amdgcn_rcpf((float)U);
+    const float qf = (float)I * r * 4294967296.0f;
+    const uint32_t q0 = qf >= 4294967295.0f ? 0xFFFFFFFFu : (uint32_t)qf;
+    const int32_t rem = (int32_t)((0u - I) - q0 * U);  // I * 2^32 - I - q0 * U
+    const int32_t c = (int32_t)floorf((float)rem * r);
+    uint32_t q = q0 + (uint32_t)c;
+    const int32_t rem1 = rem - c * (int32_t)U;
+    if (rem1 < 0) q -= 1;
+    else if (rem1 >= (int32_t)U) q += 1;
+    return q;
 }
 
 // I from key(I, U) and S = |P_u| + |P_v| (U = S - I): I/(S - I) is strictly
@@ -408,16 +419,6 @@ C2_DEV uint32_t jkey(uint32_t I, uint32_t U) {
 C2_DEV uint32_t key_to_I(uint32_t key, uint32_t S) {
     const double x = (double)S * (double)key / (4294967295.0 + (double)key);
     return (uint32_t)(x + 0.5);
-}
-
-// Is (I, U, uid) better than the heap root hk?  Exact.
-C2_DEV bool beats(uint32_t I, uint32_t U, uint32_t uid, uint64_t hk) {
-    const uint32_t kt = (uint32_t)(hk >> 32);
-    const uint64_t A = ((uint64_t)I << 32) - I;   // I * (2^32 - 1)
-    const uint64_t B = (uint64_t)kt * U;          // key_T * U
-    const bool gt = A >= B + U;                   // key > key_T
-    const bool eq = (A >= B) & !gt;               // equal keys: smaller id wins
-    return gt | (eq & (uid < 0xFFFFFFFFu - (uint32_t)hk));
 }
 
 struct KeyHeap {
@@ -732,8 +733,10 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
                     const uint32_t q = wsel * 32 + bit;
                     const uint32_t I = L.u.itile[r][q];
                     const uint32_t U = Lr + L.clen[q] - I, uid = L.cuid[q];
-                    if (!h.full() || beats(I, U, uid, h.root))
-                        h.insert(((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid));
+                    // keys are exact and distinct (the id is in the low word),
+                    // so beating the root is one comparison
+                    const uint64_t v = ((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid);
+                    if (!h.full() || v > h.root) h.insert(v);
                 }
             }
         }
