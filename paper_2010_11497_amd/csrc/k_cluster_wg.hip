@@ -148,65 +148,71 @@ C2_DEV uint32_t wg_scan(uint32_t (&v)[kWgPer], uint32_t *wsum) {
 
 // Stable LSD radix sort of the A slot indices in L.idx[0] by L.key[slot] over
 // nbits bits: one pass of up to kWideBits bits if the key is that short, else
-// passes of 8 bits.  Inside a pass, elements are taken in index order 1024 at
-// a time; a wave ranks equal digits by ballots and per-wave digit counts give
-// the offsets.  Returns the buffer holding the result.
+// passes of 8 bits.  Each wave owns a contiguous range of the elements: it
+// counts its digits into its own row of the table, one conversion turns the
+// rows into output offsets (digit-major, waves in order), and the wave then
+// places its range in index order with its row as running cursors.  Inside a
+// wave, 64 elements at a time, equal digits are ranked by ballots.  Returns
+// the buffer holding the result.
 C2_DEV int wg_sort(WgLds &L, uint32_t A, uint32_t nbits) {
     const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t width = nbits <= kWideBits ? kWideBits : 8;
     const uint32_t nbins = 1u << width;
-    // per-wave digit counts, turned into offsets in place: [kWgWaves][nbins]
-    uint16_t *wtab = &L.tab[0][0];
+    uint16_t *tab = &L.tab[0][0];  // [kWgWaves][nbins] over the whole bookkeeping area
+    uint16_t *row = tab + wid * nbins;  // this wave's row
     static_assert(kWgWaves * kWideBins <= 4 * kRankTab, "radix table fits the bookkeeping area");
+    const uint32_t per = (A + kWgWaves - 1) / kWgWaves;
+    const uint32_t begin = wid * per < A ? wid * per : A;
+    const uint32_t end = begin + per < A ? begin + per : A;
     int in = 0;
     for (uint32_t sh = 0; sh < nbits; sh += width) {
         const uint32_t dmask = nbins - 1;
-        for (uint32_t d = tid; d < nbins; d += kWgThreads) L.hist[d] = 0;
-        for (uint32_t w = tid; w < kWgWaves * nbins; w += kWgThreads) wtab[w] = 0;
-        __syncthreads();
-        for (uint32_t i = tid; i < A; i += kWgThreads)
-            atomicAdd(&L.hist[(L.key[L.idx[in][i]] >> sh) & dmask], 1u);
-        __syncthreads();
-        {
-            uint32_t total;
-            const uint32_t h = tid < nbins ? L.hist[tid] : 0u;
-            const uint32_t ex = block_excl_scan<uint32_t, kWgThreads>(h, L.wsum, &total);
-            if (tid < nbins) L.base[tid] = ex;
-        }
-        __syncthreads();
-        for (uint32_t i0 = 0; i0 < A; i0 += kWgThreads) {
-            const uint32_t i = i0 + tid;
-            const bool valid = i < A;
-            const uint32_t s = valid ? L.idx[in][i] : 0u;
-            const uint32_t d = valid ? (L.key[s] >> sh) & dmask : 0u;
-            uint64_t peers = __ballot(valid);
+        for (uint32_t d = lane; d < nbins; d += 64) row[d] = 0;
+        // ranking of equal digits among the 64 elements at i0 .. i0+63
+        auto rank = [&](uint32_t i0, uint32_t &s, uint32_t &d, uint64_t &peers, bool &valid) {
+            const uint32_t i = i0 + lane;
+            valid = i < end;
+            s = valid ? L.idx[in][i] : 0u;
+            d = valid ? (L.key[s] >> sh) & dmask : 0u;
+            peers = __ballot(valid);
             for (uint32_t bit = 0; bit < width; ++bit) {
                 const bool on = (d >> bit) & 1u;
                 const uint64_t bb = __ballot(on);
                 peers &= on ? bb : ~bb;
             }
-            const uint32_t wrank = (uint32_t)__popcll(peers & lt_mask);
-            // a wave writes and reads only its own row of the table outside the
-            // conversion, which turns the counts into offsets where the count
-            // is not zero; the leader of each digit clears its entry after use,
-            // so the table is all zero again for the next 1024 elements
-            if (valid && wrank == 0) wtab[wid * nbins + d] = (uint16_t)__popcll(peers);
-            __syncthreads();
-            for (uint32_t dd = tid; dd < nbins; dd += kWgThreads) {
-                uint32_t run = L.base[dd];
-#pragma unroll
+        };
+        for (uint32_t i0 = begin; i0 < end; i0 += 64) {
+            uint32_t s, d;
+            uint64_t peers;
+            bool valid;
+            rank(i0, s, d, peers, valid);
+            if (valid && (peers & lt_mask) == 0) row[d] = (uint16_t)(row[d] + __popcll(peers));
+        }
+        __syncthreads();
+        {   // digit tid: its total, the offsets of all digits before it, then
+            // each wave's start inside the digit
+            uint32_t tot = 0;
+            if (tid < nbins)
+                for (int w = 0; w < kWgWaves; ++w) tot += tab[w * nbins + tid];
+            uint32_t all;
+            uint32_t run = block_excl_scan<uint32_t, kWgThreads>(tid < nbins ? tot : 0u, L.wsum, &all);
+            if (tid < nbins)
                 for (int w = 0; w < kWgWaves; ++w) {
-                    const uint32_t c = wtab[w * nbins + dd];
-                    if (c) wtab[w * nbins + dd] = (uint16_t)run;
+                    const uint32_t c = tab[w * nbins + tid];
+                    tab[w * nbins + tid] = (uint16_t)run;
                     run += c;
                 }
-                L.base[dd] = run;
-            }
-            __syncthreads();
-            const uint32_t off = valid ? wtab[wid * nbins + d] : 0u;
-            if (valid) L.idx[in ^ 1][off + wrank] = (uint16_t)s;
-            if (valid && wrank == 0) wtab[wid * nbins + d] = 0;
+        }
+        __syncthreads();
+        for (uint32_t i0 = begin; i0 < end; i0 += 64) {
+            uint32_t s, d;
+            uint64_t peers;
+            bool valid;
+            rank(i0, s, d, peers, valid);
+            const uint32_t cur = valid ? row[d] : 0u;  // read by all lanes of the digit first
+            if (valid) L.idx[in ^ 1][cur + __popcll(peers & lt_mask)] = (uint16_t)s;
+            if (valid && (peers & lt_mask) == 0) row[d] = (uint16_t)(cur + __popcll(peers));
         }
         __syncthreads();
         in ^= 1;
