@@ -20,9 +20,9 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_DIR = os.path.join(HERE, "tuning")
 GRID = {
-    "persistent_wgs": [256, 512, 1024],
-    "mfma_min_rows": [2, 48],
-    "group_tiles": [2, 4, 8, 16],
+    "persistent_wgs": [256, 384, 512, 768, 1024],
+    "mfma_min_rows": [2],
+    "group_tiles": [1, 2, 4, 8, 16, 32],
 }
 
 
