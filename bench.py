@@ -98,6 +98,38 @@ def upload_ms(P, torch, reps=5):
     return sorted(ts)[len(ts) // 2]
 
 
+def minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np, bf):
+    """The paper's MinHash variant of the clustering (Section IV, Table 4): t
+    min-wise permutations of the items as bucket tables (b = m), no split,
+    then the same local KNN and merge.  Timed in the plain eager form, beside
+    which the FastRandomHash build's plain form is reported."""
+    tab = synth.minhash_tables(w.t, w.m, w.hash_seed + 1)
+    dtab = torch.as_tensor(tab.view(np.int32)).cuda()
+    p = c2.params(w.t, w.m, w.n, w.k)
+    members, cl_off, cfg, _ = c2.cluster(dP, dtab, p, c2.FORM_PLAIN)
+    ncl = int(c2.to_u32(cfg)[-1])
+    work = metrics.cluster_work(c2.to_u32(members), c2.to_u32(cl_off)[: ncl + 1], P.indptr,
+                                P.indices, P.m)
+    out = None
+    for _ in range(args.warmup):
+        out = c2.build_from_buckets(dP, dtab, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = c2.build_from_buckets(dP, dtab, p)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    q = None
+    if bf is not None:
+        q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
+                            c2.to_u32(bf[2]))
+    log("MinHash clustering: %d clusters, max %d, %d evals, plain build %.3f ms, quality %s"
+        % (ncl, int(work["sizes"].max()), work["pairs"], ms, q))
+    return {"build_ms_plain": ms, "quality": q, "jaccard_evals": int(work["pairs"]),
+            "clusters": ncl, "max_cluster": int(work["sizes"].max()),
+            "tables": "t seeded permutations of the m items (b = m), cap = n"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +139,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the MinHash-clustering comparison (Table 4 of the paper)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -210,6 +244,11 @@ def main():
         quality = metrics.quality(out_graph[1], out_graph[2], c2.to_u32(bf[1]), c2.to_u32(bf[2]))
         log("quality %.4f" % quality)
 
+    ablation = None
+    if not args.no_ablation:
+        ablation = minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np,
+                                    bf if quality is not None else None)
+
     mfma_min = int(tuned.get("mfma_min_rows", MFMA_MIN_DEFAULT))
     big = work["sizes"] >= mfma_min
     ops = int((2 * work["sizes"][big].astype(np.int64) ** 2 * work["dict"][big]).sum())
@@ -233,6 +272,7 @@ def main():
                    "tuning": tuned or "defaults"},
         "build_ms": {"graph": graph_ms, "batched": batched_ms, "plain": plain_ms},
         "quality": quality, "jaccard_evals": E, "clusters": ncl,
+        "minhash_ablation": ablation,
         "h2d_csr_ms": h2d_ms, "evals_per_s_incl_h2d": E / ((graph_ms + h2d_ms) * 1e-3),
         "local_knn_ms": knn_ms, "local_knn_evals_per_s": E / (knn_ms * 1e-3),
         "roofline": roof,

@@ -238,6 +238,19 @@ def build(P: DeviceProfiles, tab: torch.Tensor, p: Params, form=FORM_PLAIN,
     return out
 
 
+def build_from_buckets(P: DeviceProfiles, bucket: torch.Tensor, p: Params,
+                       tune: Optional[Tuning] = None):
+    """The three stages on an explicit bucket table (int32 view of
+    uint32[t][m], values < p.b) instead of hashed items: clustering, local
+    KNN and merge in the plain form.  With p.b = m and per-item permutation
+    ranks as the table, and p.cap >= n, this is the MinHash clustering the
+    paper compares FastRandomHash against (Section IV, Table 4): one cluster
+    per item that is some user's minimum, no splitting."""
+    members, cl_off, cfg, _ = cluster(P, bucket, p, FORM_PLAIN, tune)
+    part = local_knn(P, members, cl_off, cfg, p, FORM_PLAIN, tune)
+    return merge(P, part[0], part[1], p)
+
+
 def brute_force(P: DeviceProfiles, k: int, ws=None, out=None):
     if out is None:
         out = tuple(_u32((P.n, k), P.device) for _ in range(3))

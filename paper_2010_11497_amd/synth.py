@@ -175,6 +175,18 @@ def hash_tables(t: int, seed: int) -> np.ndarray:
     return g.random_raw(t * 4 * 256).astype(np.uint64).reshape(t, 4, 256)
 
 
+def minhash_tables(t: int, m: int, seed: int) -> np.ndarray:
+    """uint32[t][m]: t seeded random permutations of the item ids, entry i of
+    row j being the rank of item i.  Used as bucket tables with b = m they are
+    the min-wise hash functions of MinHash (the paper's MinHash variant of its
+    clustering, Section IV, "Impact of FastRandomHash")."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty((t, m), dtype=np.uint32)
+    for j in range(t):
+        out[j] = rng.permutation(m).astype(np.uint32)
+    return out
+
+
 def random_profiles(seed: int, n: int, m: int, lo: int, hi: int,
                     zipf_s: float = 0.0) -> Profiles:
     """Small random instance for tests: sizes uniform in [lo, hi], items Zipf

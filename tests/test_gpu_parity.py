@@ -376,3 +376,27 @@ def test_long_profiles_take_exact_fallback(orc):
     r = orc.build_graph(P.indptr, P.indices, P.n, P.m, tab, 4, 60, k, THREADS)
     for g, w in zip(got, (r.knn_id, r.knn_I, r.knn_U)):
         assert np.array_equal(u32(g), w)
+
+
+# ------------------------------------------------- MinHash clustering ----
+
+@pytest.mark.parametrize("path", list(CPATHS))
+@pytest.mark.parametrize("n,m,lo,hi,zipf,t,k", [(600, 250, 1, 25, 1.1, 4, 10),
+                                               (2000, 1000, 5, 60, 1.0, 8, 30),
+                                               (300, 40, 1, 6, 0.0, 2, 5)])
+def test_minhash_build(orc, n, m, lo, hi, zipf, t, k, path):
+    """MinHash clustering (b = m, per-item permutation ranks, no split) through
+    the same three stages, against the oracle's stages on the same table."""
+    say("minhash", n, m, t, k, path)
+    P = synth.random_profiles(7000 + n, n, m, lo, hi, zipf)
+    tab = synth.minhash_tables(t, m, 7100 + n)
+    dP = c2.DeviceProfiles.from_synth(P)
+    p = c2.params(t, m, n, k)
+    got = c2.build_from_buckets(dP, torch.as_tensor(tab.view(np.int32)).cuda(), p,
+                                c2.tuning(cluster_path=CPATHS[path]))
+    om, ooff, ocfg, depth = orc.cluster(P.indptr, P.indices, n, m, tab, n)
+    assert depth == 0
+    pid, pI = orc.local_knn(P.indptr, P.indices, n, m, t, k, om, ooff, ocfg, THREADS)
+    want = orc.merge(P.indptr, n, t, k, pid, pI)
+    for g, w in zip(got, want):
+        assert np.array_equal(u32(g), w)

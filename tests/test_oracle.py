@@ -346,6 +346,53 @@ def test_minhash_limit(orc):
     assert abs(hits / S - J) < 4 * sd + 0.01
 
 
+def test_minhash_permutations_exact(orc):
+    """MinHash clustering (Section IV, Table 4) keys a user by the smallest
+    permutation rank among its items.  Over all m! permutations the two users'
+    keys agree in exactly J * m! of them (min-wise independence of a uniform
+    permutation), so the oracle's key must reproduce that count exactly."""
+    import itertools
+    m = 6
+    perms = np.array(list(itertools.permutations(range(m))), dtype=np.uint32)   # 720 x 6
+    for A, B in [({0, 1, 2, 3}, {2, 3, 4}), ({5}, {5}), ({0}, {1}), ({0, 1, 2, 3, 4, 5}, {1})]:
+        P = synth.profiles_from_sets([A, B], m)
+        keys = orc.frh_keys(P.indptr, P.indices, 2, m, perms)
+        same = int((keys[:, 0] == keys[:, 1]).sum())
+        assert Fraction(same, len(perms)) == Fraction(len(A & B), len(A | B))
+        # the key is the rank of the user's first item under the permutation
+        assert all(keys[j, 0] == min(perms[j, i] for i in A) for j in range(0, 720, 37))
+
+
+def test_minhash_tables_are_permutations():
+    tab = synth.minhash_tables(5, 1000, 3)
+    assert tab.shape == (5, 1000) and tab.dtype == np.uint32
+    for row in tab:
+        assert np.array_equal(np.sort(row), np.arange(1000, dtype=np.uint32))
+    assert not np.array_equal(tab[0], tab[1])
+    assert np.array_equal(tab, synth.minhash_tables(5, 1000, 3))
+
+
+def test_minhash_clusters_are_min_items(orc):
+    """With b = m and cap >= n nothing splits: there is one cluster per item
+    that is some user's minimum, t*m clusters at most, and each cluster is
+    exactly the users whose minimum rank is that item's."""
+    P = synth.random_profiles(11, 400, 150, 1, 15, 1.0)
+    t = 3
+    tab = synth.minhash_tables(t, P.m, 12)
+    members, off, cfg, depth = orc.cluster(P.indptr, P.indices, P.n, P.m, tab, P.n)
+    keys = orc.frh_keys(P.indptr, P.indices, P.n, P.m, tab)
+    assert depth == 0 and int(cfg[-1]) <= t * P.m
+    for j in range(t):
+        want = {}
+        for u in range(P.n):
+            row = P.indices[P.indptr[u]:P.indptr[u + 1]]
+            if len(row):
+                assert keys[j, u] == tab[j, row].min()
+            want.setdefault(int(keys[j, u]), []).append(u)
+        got = [members[off[c]:off[c + 1]].tolist() for c in range(cfg[j], cfg[j + 1])]
+        assert got == [want[v] for v in sorted(want)]
+
+
 # ------------------------------------------------------------ Theorem 2 --
 
 def test_theorem2_example_constant():
