@@ -99,7 +99,7 @@ def upload_ms(P, torch, reps=5):
 
 
 def minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np, bf):
-    """The paper's MinHash variant of the clustering (Section IV, Table 4): t
+    """The paper's MinHash variant of the clustering (Section V-C, Table 4): t
     min-wise permutations of the items as bucket tables (b = m), no split,
     then the same local KNN and merge.  Timed in the plain eager form, beside
     which the FastRandomHash build's plain form is reported."""
@@ -130,6 +130,42 @@ def minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np, bf):
             "tables": "t seeded permutations of the m items (b = m), cap = n"}
 
 
+def goldfinger_variant(args, w, P, dP, c2, metrics, synth, torch, np, bf, B=1024):
+    """The paper's default local similarity (Section II-F, Section V-D and
+    Table 5): the same clusters, local KNN and merge on B-bit GoldFinger
+    fingerprints.  The fingerprints are computed once (timed apart); the
+    graph is scored by the exact similarity of the edges it chose."""
+    gtab = c2.tables_to_device(synth.hash_tables(1, w.hash_seed + 2))
+    dtab = c2.tables_to_device(synth.hash_tables(w.t, w.hash_seed))
+    g = c2.hash_items(gtab, B, w.m)[0]
+    p = c2.params(w.t, w.b, w.cap, w.k)
+    ws = c2.workspace(dP, c2.params(1, B, 1, 1), c2.OP_FINGERPRINT)
+    FP = c2.fingerprint(dP, g, B, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        FP = c2.fingerprint(dP, g, B, ws)
+    fp_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out = None
+    for _ in range(args.warmup):
+        out = c2.build_goldfinger(dP, FP, dtab, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = c2.build_goldfinger(dP, FP, dtab, p)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    q = None
+    if bf is not None:
+        I, U = metrics.edge_jaccard(P.indptr, P.indices, P.m, c2.to_u32(out[0]))
+        q = metrics.quality(I, U, c2.to_u32(bf[1]), c2.to_u32(bf[2]))
+    log("GoldFinger %d bits: fingerprints %.3f ms (nnz %d -> %d), plain build %.3f ms, "
+        "quality %s" % (B, fp_ms, P.nnz, FP.nnz, ms, q))
+    return {"bits": B, "fingerprint_ms": fp_ms, "fingerprint_nnz": FP.nnz,
+            "build_ms_plain": ms, "quality": q,
+            "quality_def": "exact similarity of the chosen edges over the exact graph's"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,7 +176,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-ablation", action="store_true",
-                    help="skip the MinHash-clustering comparison (Table 4 of the paper)")
+                    help="skip the MinHash-clustering (Table 4) and GoldFinger (Table 5) "
+                         "variants")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -244,10 +281,12 @@ def main():
         quality = metrics.quality(out_graph[1], out_graph[2], c2.to_u32(bf[1]), c2.to_u32(bf[2]))
         log("quality %.4f" % quality)
 
-    ablation = None
+    ablation = gold = None
     if not args.no_ablation:
         ablation = minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np,
                                     bf if quality is not None else None)
+        gold = goldfinger_variant(args, w, P, dP, c2, metrics, synth, torch, np,
+                                  bf if quality is not None else None)
 
     mfma_min = int(tuned.get("mfma_min_rows", MFMA_MIN_DEFAULT))
     big = work["sizes"] >= mfma_min
@@ -272,7 +311,7 @@ def main():
                    "tuning": tuned or "defaults"},
         "build_ms": {"graph": graph_ms, "batched": batched_ms, "plain": plain_ms},
         "quality": quality, "jaccard_evals": E, "clusters": ncl,
-        "minhash_ablation": ablation,
+        "minhash_ablation": ablation, "goldfinger": gold,
         "h2d_csr_ms": h2d_ms, "evals_per_s_incl_h2d": E / ((graph_ms + h2d_ms) * 1e-3),
         "local_knn_ms": knn_ms, "local_knn_evals_per_s": E / (knn_ms * 1e-3),
         "roofline": roof,

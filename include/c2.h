@@ -111,6 +111,7 @@ typedef struct c2_tuning {
 #define C2_OP_LOCAL_KNN 2
 #define C2_OP_BUILD 3
 #define C2_OP_BRUTE_FORCE 4
+#define C2_OP_FINGERPRINT 5
 
 /* Message for the last non-OK status returned on this thread (host string,
  * valid until the next call on this thread). */
@@ -213,6 +214,27 @@ c2_status c2_build(const c2_profiles *P, const uint64_t *tab, const c2_params *p
  * holding all users.  Outputs as c2_merge.  ws: C2_OP_BRUTE_FORCE bytes. */
 c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uint32_t *knn_I,
                          uint32_t *knn_U, void *ws, size_t ws_bytes, void *stream);
+
+/* GoldFinger fingerprints (Section II-F; 1024 bits in Section IV-C; their
+ * effect in Section V-D, Table 5): the local similarities may be computed on
+ * a compact B-bit vector per user instead of the profile.  The fingerprint of
+ * user u is the set F_u = { g(i) : i in P_u } of bit positions, g an item hash
+ * into [0, B) (c2_hash_items with t = 1, b = B and tables of its own), and
+ * the Jaccard index of F_u and F_v is the estimate of the users' similarity.
+ * The fingerprints are written as CSR profiles over B items, so that
+ * c2_local_knn, c2_merge and c2_brute_force run on them unchanged (then
+ * knn_I = |F_u & F_v| and knn_U = |F_u | F_v|).
+ *   g           device, [m], every value < B
+ *   B           bits, 1..8192
+ *   fp_indptr   device int64 [n+1]; fp_indices device u32 with room for
+ *               P->nnz entries (|F_u| <= |P_u|); each row strictly increasing
+ *   fp_nnz      host; receives fp_indptr[n]
+ * Synchronous.  C2_E_PROFILE if a row holds an item >= m, C2_E_ARG if g
+ * holds a value >= B (outputs then undefined).  ws: C2_OP_FINGERPRINT bytes,
+ * queried with p->b = B (the other fields of p are not used). */
+c2_status c2_fingerprint(const c2_profiles *P, const uint32_t *g, uint32_t B, int64_t *fp_indptr,
+                         uint32_t *fp_indices, uint64_t *fp_nnz, void *ws, size_t ws_bytes,
+                         void *stream);
 
 /* HIP-graph form of c2_build (C2_FORM_BATCHED) on fixed buffers.  Create
  * runs one plain clustering synchronously to learn how many split rounds the

@@ -173,6 +173,20 @@ def build_graph(indptr, indices, n, m, tab, b, cap, k, threads=1) -> Result:
                   depth=depth, part_id=pid, part_I=pI, knn_id=kid, knn_I=kI, knn_U=kU)
 
 
+def fingerprints(indptr, indices, n, g):
+    """GoldFinger fingerprints (Section II-F): row u is the set of positions
+    g[i] over the items i of P_u, as CSR (indptr int64[n+1], ascending rows).
+    Written from the definition with numpy, independent of the C oracle."""
+    ip = np.asarray(indptr, dtype=np.int64)
+    ix = np.asarray(indices, dtype=np.int64)
+    g = np.asarray(g, dtype=np.uint32)
+    rows = [np.unique(g[ix[ip[u]:ip[u + 1]]]) for u in range(n)]
+    fp_ip = np.zeros(n + 1, dtype=np.int64)
+    fp_ip[1:] = np.cumsum([len(r) for r in rows])
+    fp_ix = np.concatenate(rows).astype(np.uint32) if n else np.zeros(0, np.uint32)
+    return fp_ip, fp_ix
+
+
 def avg_sim(knn_I, knn_U, n_users: Optional[int] = None) -> float:
     """Eq. 1: sum of J over all edge slots divided by k*n; empty slots add 0."""
     kI = np.asarray(knn_I, dtype=np.int64)

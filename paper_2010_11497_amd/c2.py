@@ -24,12 +24,13 @@ C2_OK = 0
 C2_PAD = 0xFFFFFFFF
 FORM_PLAIN = 0
 FORM_BATCHED = 1
-OP_VALIDATE, OP_CLUSTER, OP_LOCAL_KNN, OP_BUILD, OP_BRUTE_FORCE = range(5)
+OP_VALIDATE, OP_CLUSTER, OP_LOCAL_KNN, OP_BUILD, OP_BRUTE_FORCE, OP_FINGERPRINT = range(6)
 
 # every entry point of include/c2.h
 SYMBOLS = ["c2_last_error", "c2_workspace_bytes", "c2_validate", "c2_hash_items", "c2_frh_keys",
            "c2_cluster", "c2_check_complete", "c2_local_knn", "c2_merge", "c2_build",
-           "c2_brute_force", "c2_graph_create", "c2_graph_launch", "c2_graph_destroy"]
+           "c2_brute_force", "c2_fingerprint", "c2_graph_create", "c2_graph_launch",
+           "c2_graph_destroy"]
 
 
 class C2Error(RuntimeError):
@@ -82,6 +83,7 @@ def load(path: str = LIB_PATH):
     L.c2_merge.argtypes = [PP, P, P, PA, P, P, P, P]
     L.c2_build.argtypes = [PP, P, PA, i32, PT, P, P, P, P, sz, P]
     L.c2_brute_force.argtypes = [PP, u32, P, P, P, P, sz, P]
+    L.c2_fingerprint.argtypes = [PP, P, u32, P, P, ctypes.POINTER(u64), P, sz, P]
     L.c2_graph_create.argtypes = [PP, P, PA, PT, P, P, P, P, sz, P, ctypes.POINTER(P)]
     L.c2_graph_launch.argtypes = [P, P]
     L.c2_graph_destroy.argtypes = [P]
@@ -132,6 +134,19 @@ class DeviceProfiles:
     @classmethod
     def from_synth(cls, P, device="cuda"):
         return cls(P.indptr, P.indices, P.n, P.m, device)
+
+    @classmethod
+    def from_device(cls, indptr: torch.Tensor, indices: torch.Tensor, n: int, m: int):
+        """Wraps CSR tensors already on the GPU (indptr int64[n+1], indices
+        int32[nnz]) without copying."""
+        self = cls.__new__(cls)
+        self.n, self.m = int(n), int(m)
+        self.indptr, self.indices = indptr, indices
+        self.nnz = int(indices.numel())
+        self.device = indptr.device
+        self.c = Profiles(self.n, self.m, self.nnz, indptr.data_ptr(),
+                          indices.data_ptr() if self.nnz else 0)
+        return self
 
 
 def params(t, b, cap, k) -> Params:
@@ -238,13 +253,40 @@ def build(P: DeviceProfiles, tab: torch.Tensor, p: Params, form=FORM_PLAIN,
     return out
 
 
+def fingerprint(P: DeviceProfiles, g: torch.Tensor, B: int, ws=None) -> DeviceProfiles:
+    """GoldFinger fingerprints of the profiles as CSR profiles over B items
+    (synchronous).  g: int32 view of uint32[m], positions < B, e.g.
+    hash_items(tables, B, m)[0]."""
+    L = load()
+    indptr = torch.empty(P.n + 1, dtype=torch.int64, device=P.device)
+    indices = _u32(max(P.nnz, 1), P.device)
+    if ws is None:
+        ws = workspace(P, params(1, B, 1, 1), OP_FINGERPRINT)
+    nnz = ctypes.c_uint64()
+    _check(L.c2_fingerprint(ctypes.byref(P.c), _ptr(g), int(B), _ptr(indptr), _ptr(indices),
+                            ctypes.byref(nnz), _ptr(ws), ws.numel(), _stream()))
+    return DeviceProfiles.from_device(indptr, indices[: nnz.value], P.n, B)
+
+
+def build_goldfinger(P: DeviceProfiles, FP: DeviceProfiles, tab: torch.Tensor, p: Params,
+                     tune: Optional[Tuning] = None):
+    """C2 with GoldFinger local similarities (Section II-F): the clusters come
+    from FastRandomHash on the profiles, the local KNN graphs and the merge
+    from the fingerprints FP (see fingerprint()).  knn_I / knn_U are the
+    fingerprints' intersection and union sizes."""
+    bucket = hash_items(tab, p.b, P.m)
+    members, cl_off, cfg, _ = cluster(P, bucket, p, FORM_PLAIN, tune)
+    part = local_knn(FP, members, cl_off, cfg, p, FORM_PLAIN, tune)
+    return merge(FP, part[0], part[1], p)
+
+
 def build_from_buckets(P: DeviceProfiles, bucket: torch.Tensor, p: Params,
                        tune: Optional[Tuning] = None):
     """The three stages on an explicit bucket table (int32 view of
     uint32[t][m], values < p.b) instead of hashed items: clustering, local
     KNN and merge in the plain form.  With p.b = m and per-item permutation
     ranks as the table, and p.cap >= n, this is the MinHash clustering the
-    paper compares FastRandomHash against (Section IV, Table 4): one cluster
+    paper compares FastRandomHash against (Section V-C, Table 4): one cluster
     per item that is some user's minimum, no splitting."""
     members, cl_off, cfg, _ = cluster(P, bucket, p, FORM_PLAIN, tune)
     part = local_knn(P, members, cl_off, cfg, p, FORM_PLAIN, tune)

@@ -297,6 +297,13 @@ size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params 
                             2 * al(4 * (size_t)n * one.k);
         return head + knn_ws_bytes(n, n, knn_wmax(m), nullptr);
     }
+    case C2_OP_FINGERPRINT:
+        if (check_sizes(n, m, nnz, nullptr, false) != C2_OK) return 0;
+        if (!p || p->b < 1 || p->b > kFpMaxBits) {
+            fail(C2_E_ARG, "fingerprint bits (p->b) out of range [1, %u]", kFpMaxBits);
+            return 0;
+        }
+        return kHeader + fingerprint_ws_bytes(n, p->b);
     default:
         fail(C2_E_ARG, "unknown op %d", op);
         return 0;
@@ -320,6 +327,34 @@ c2_status c2_validate(const c2_profiles *P, void *ws, size_t ws_bytes, void *str
                     (h & 2) ? " empty row" : "", (h & 4) ? " item >= m" : "",
                     (h & 8) ? " items not strictly increasing" : "");
     }
+    return C2_OK;
+}
+
+c2_status c2_fingerprint(const c2_profiles *P, const uint32_t *g, uint32_t B, int64_t *fp_indptr,
+                         uint32_t *fp_indices, uint64_t *fp_nnz, void *ws, size_t ws_bytes,
+                         void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, nullptr, false)) != C2_OK) return st;
+    if (!g || !fp_indptr || (!fp_indices && P->nnz) || !fp_nnz) return fail(C2_E_ARG, "NULL pointer");
+    if (B < 1 || B > kFpMaxBits) return fail(C2_E_ARG, "B = %u out of range [1, %u]", B, kFpMaxBits);
+    const c2_params q = {1, B, 1, 1};
+    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, &q, C2_OP_FINGERPRINT))) != C2_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *err = reinterpret_cast<uint32_t *>(ws);
+    C2_TRY(launch_fill_u32(err, 0, 1, s), "fingerprint");
+    C2_TRY(launch_fingerprint(P->indptr, P->indices, P->nnz, P->n, P->m, g, B, fp_indptr,
+                              fp_indices, reinterpret_cast<char *>(ws) + kHeader, err, s),
+           "fingerprint");
+    uint32_t h = 0;
+    int64_t total = 0;
+    C2_TRY(hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, s), "fingerprint copy");
+    C2_TRY(hipMemcpyAsync(&total, fp_indptr + P->n, 8, hipMemcpyDeviceToHost, s), "fingerprint copy");
+    C2_TRY(hipStreamSynchronize(s), "fingerprint sync");
+    if (h & 1) return fail(C2_E_PROFILE, "a profile holds an item >= m");
+    if (h & 2) return fail(C2_E_ARG, "g holds a position >= B = %u", B);
+    *fp_nnz = (uint64_t)total;
     return C2_OK;
 }
 

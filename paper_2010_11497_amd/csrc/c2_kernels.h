@@ -18,6 +18,14 @@ hipError_t launch_validate(const int64_t *indptr, const uint32_t *indices, uint6
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint32_t n, hipStream_t s);
 hipError_t launch_iota(uint32_t *p, uint32_t n, hipStream_t s);
 
+// ---- GoldFinger fingerprints
+constexpr uint32_t kFpMaxBits = 8192;
+size_t fingerprint_ws_bytes(uint32_t n, uint32_t B);
+hipError_t launch_fingerprint(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                              uint32_t n, uint32_t m, const uint32_t *g, uint32_t B,
+                              int64_t *fp_indptr, uint32_t *fp_indices, void *ws, uint32_t *err,
+                              hipStream_t s);
+
 // ---- clustering
 struct ClusterDims {
     size_t NE;  // t*n slots

@@ -5,7 +5,9 @@ similarity over the k*n edge slots, empty slots counting 0; quality is the
 ratio to the exact graph).  Sums use math.fsum, so they do not depend on
 summation order.  cluster_work counts the work units the benchmark's roofline
 uses: same-cluster pairs (the paper's similarity computations) and each
-cluster's local dictionary size.
+cluster's local dictionary size.  edge_jaccard gives the exact intersection and
+union of chosen edges, so that a graph built on estimated similarities
+(GoldFinger fingerprints) is scored by the users' true similarities.
 """
 
 from __future__ import annotations
@@ -67,3 +69,32 @@ def cluster_work(members: np.ndarray, cl_off: np.ndarray, indptr: np.ndarray,
         "sizes": s,
         "dict": D,
     }
+
+
+def edge_jaccard(indptr: np.ndarray, indices: np.ndarray, m: int, knn_id: np.ndarray,
+                 pad: int = 0xFFFFFFFF, chunk: int = 1 << 16):
+    """Exact |P_u & P_v| and |P_u | P_v| for every edge u -> knn_id[u, j]
+    (0 and 0 for padded slots), from the profiles packed as bit rows."""
+    indptr = np.asarray(indptr, dtype=np.int64)
+    n = len(indptr) - 1
+    words = (m + 63) // 64
+    lens = np.diff(indptr)
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    cols = np.asarray(indices, dtype=np.int64)
+    bits = np.zeros((n, words), dtype=np.uint64)
+    np.bitwise_or.at(bits, (rows, cols >> 6), np.left_shift(np.uint64(1),
+                                                           (cols & 63).astype(np.uint64)))
+    ids = np.asarray(knn_id, dtype=np.int64)
+    shape = ids.shape
+    u = np.repeat(np.arange(n, dtype=np.int64), shape[1])
+    v = ids.ravel()
+    ok = v != pad
+    I = np.zeros(v.shape, dtype=np.int64)
+    U = np.zeros(v.shape, dtype=np.int64)
+    sel = np.nonzero(ok)[0]
+    for c0 in range(0, len(sel), chunk):
+        e = sel[c0:c0 + chunk]
+        inter = np.bitwise_count(bits[u[e]] & bits[v[e]]).sum(axis=1, dtype=np.int64)
+        I[e] = inter
+        U[e] = lens[u[e]] + lens[v[e]] - inter
+    return I.reshape(shape), U.reshape(shape)

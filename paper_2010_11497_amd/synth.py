@@ -179,7 +179,7 @@ def minhash_tables(t: int, m: int, seed: int) -> np.ndarray:
     """uint32[t][m]: t seeded random permutations of the item ids, entry i of
     row j being the rank of item i.  Used as bucket tables with b = m they are
     the min-wise hash functions of MinHash (the paper's MinHash variant of its
-    clustering, Section IV, "Impact of FastRandomHash")."""
+    clustering, Section V-C and Table 4)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = np.empty((t, m), dtype=np.uint32)
     for j in range(t):

@@ -29,7 +29,7 @@ def test_header_lists_entry_points():
     names = declared()
     from paper_2010_11497_amd import c2
     assert names == sorted(c2.SYMBOLS)
-    assert len(names) == 14
+    assert len(names) == 15
 
 
 def test_library_exports_every_symbol(lib):
@@ -50,6 +50,10 @@ def test_workspace_queries_host_only(lib):
     assert b"k = 33" in lib.c2_last_error()
     assert lib.c2_workspace_bytes(n, 200000, nnz, ctypes.byref(p), c2.OP_BUILD) == 0   # m too big
     assert lib.c2_workspace_bytes(n, m, nnz, ctypes.byref(p), 99) == 0
+    fp = c2.params(1, 1024, 1, 1)                # fingerprint: p->b is the width in bits
+    assert lib.c2_workspace_bytes(n, m, nnz, ctypes.byref(fp), c2.OP_FINGERPRINT) >= n * 128
+    assert lib.c2_workspace_bytes(n, m, nnz, ctypes.byref(c2.params(1, 8193, 1, 1)),
+                                  c2.OP_FINGERPRINT) == 0
 
 
 def test_argument_errors_before_enqueue(lib):
@@ -74,3 +78,11 @@ def test_argument_errors_before_enqueue(lib):
                             ctypes.c_void_p(1), ctypes.byref(ok), 7, None, ctypes.c_void_p(1),
                             ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 30, None) == -1  # form
     assert lib.c2_graph_destroy(None) == 0
+    nnz = ctypes.c_uint64()
+    for B in (0, 8193):                         # fingerprint width out of range
+        assert lib.c2_fingerprint(ctypes.byref(q), ctypes.c_void_p(1), B, ctypes.c_void_p(1),
+                                  ctypes.c_void_p(1), ctypes.byref(nnz), ctypes.c_void_p(1),
+                                  1 << 30, None) == -1
+    assert lib.c2_fingerprint(ctypes.byref(q), ctypes.c_void_p(1), 1024, ctypes.c_void_p(1),
+                              ctypes.c_void_p(1), ctypes.byref(nnz), ctypes.c_void_p(1), 16,
+                              None) == -3          # workspace too small

@@ -400,3 +400,58 @@ def test_minhash_build(orc, n, m, lo, hi, zipf, t, k, path):
     want = orc.merge(P.indptr, n, t, k, pid, pI)
     for g, w in zip(got, want):
         assert np.array_equal(u32(g), w)
+
+
+# ------------------------------------------------ GoldFinger (II-F) ----
+
+def check_fingerprint(orc, P, g, B):
+    dP = c2.DeviceProfiles.from_synth(P)
+    FP = c2.fingerprint(dP, torch.as_tensor(g.view(np.int32)).cuda(), B)
+    ip, ix = orc.fingerprints(P.indptr, P.indices, P.n, g)
+    assert FP.n == P.n and FP.m == B and FP.nnz == len(ix)
+    assert np.array_equal(FP.indptr.cpu().numpy(), ip)
+    assert np.array_equal(u32(FP.indices), ix)
+    return dP, FP, ip, ix
+
+
+@pytest.mark.parametrize("B", [1, 31, 64, 1000, 1024, 8192])
+@pytest.mark.parametrize("n,m,lo,hi", [(1, 10, 1, 10), (257, 500, 1, 40), (1003, 20000, 50, 3000)])
+def test_fingerprint(orc, n, m, lo, hi, B):
+    say("fingerprint", n, m, B)
+    P = synth.random_profiles(8000 + n, n, m, lo, hi, 1.0)
+    g = orc.hash_items(synth.hash_tables(1, 8100 + B), B, m)[0]
+    check_fingerprint(orc, P, g, B)
+
+
+def test_fingerprint_rejects_bad_positions():
+    P = synth.random_profiles(8200, 50, 100, 1, 10, 0.0)
+    dP = c2.DeviceProfiles.from_synth(P)
+    g = torch.zeros(P.m, dtype=torch.int32, device="cuda")
+    g[int(P.indices[0])] = 64                 # >= B: detected on the device
+    with pytest.raises(c2.C2Error):
+        c2.fingerprint(dP, g, 64)
+    for B in (0, 8193):
+        with pytest.raises(c2.C2Error):
+            c2.fingerprint(dP, g, B)
+
+
+@pytest.mark.parametrize("name", ["n2k_m1k", "n6k_m3.7k"])
+def test_goldfinger_build(orc, name):
+    """Clusters from FastRandomHash on the profiles, local KNN and merge on
+    1024-bit fingerprints, against the oracle's stages on the oracle's
+    fingerprints."""
+    w = synth.WORKLOADS[name]
+    say("goldfinger", name)
+    P = synth.make_profiles(w)
+    tab = synth.hash_tables(w.t, w.hash_seed)
+    B = 1024
+    g = orc.hash_items(synth.hash_tables(1, w.hash_seed + 2), B, P.m)[0]
+    dP, FP, ip, ix = check_fingerprint(orc, P, g, B)
+    p = c2.params(w.t, w.b, w.cap, w.k)
+    got = c2.build_goldfinger(dP, FP, c2.tables_to_device(tab), p)
+    bucket = orc.hash_items(tab, w.b, P.m)
+    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, w.cap)
+    pid, pI = orc.local_knn(ip, ix, P.n, B, w.t, w.k, om, ooff, ocfg, THREADS)
+    want = orc.merge(ip, P.n, w.t, w.k, pid, pI)
+    for a, b in zip(got, want):
+        assert np.array_equal(u32(a), b)

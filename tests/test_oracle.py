@@ -347,7 +347,7 @@ def test_minhash_limit(orc):
 
 
 def test_minhash_permutations_exact(orc):
-    """MinHash clustering (Section IV, Table 4) keys a user by the smallest
+    """MinHash clustering (Section V-C, Table 4) keys a user by the smallest
     permutation rank among its items.  Over all m! permutations the two users'
     keys agree in exactly J * m! of them (min-wise independence of a uniform
     permutation), so the oracle's key must reproduce that count exactly."""
@@ -391,6 +391,72 @@ def test_minhash_clusters_are_min_items(orc):
             want.setdefault(int(keys[j, u]), []).append(u)
         got = [members[off[c]:off[c + 1]].tolist() for c in range(cfg[j], cfg[j + 1])]
         assert got == [want[v] for v in sorted(want)]
+
+
+# ------------------------------------------------- GoldFinger (II-F) ----
+
+def test_fingerprints_brute_force(orc):
+    """The fingerprint of a profile is the set of its items' positions."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    for B in (1, 7, 64, 1000):
+        P = synth.random_profiles(22 + B, 60, 300, 1, 80, 1.0)
+        g = rng.integers(0, B, size=P.m, dtype=np.uint32)
+        ip, ix = orc.fingerprints(P.indptr, P.indices, P.n, g)
+        assert ip[0] == 0 and ip[-1] == len(ix)
+        for u in range(P.n):
+            want = sorted({int(g[i]) for i in P.indices[P.indptr[u]:P.indptr[u + 1]]})
+            assert ix[ip[u]:ip[u + 1]].tolist() == want
+
+
+def test_fingerprints_injective_position_is_identity(orc):
+    """With B = m and g(i) = i nothing collides: the fingerprint is the
+    profile and the GoldFinger estimate is the exact Jaccard index."""
+    P = synth.random_profiles(23, 200, 90, 1, 30, 1.2)
+    ip, ix = orc.fingerprints(P.indptr, P.indices, P.n, np.arange(P.m, dtype=np.uint32))
+    assert np.array_equal(ip, P.indptr) and np.array_equal(ix, P.indices)
+
+
+def test_fingerprints_of_union_and_fill(orc):
+    """F(A | B) = F(A) | F(B), F(A & B) is inside F(A) & F(B), and with the
+    seeded item hash into B positions a profile of s items fills
+    B(1 - (1 - 1/B)^s) positions on average (a uniform hash)."""
+    B, m = 1024, 20000
+    g = orc.hash_items(synth.hash_tables(1, 24), B, m)[0]
+    rng = np.random.Generator(np.random.PCG64(25))
+    sets = []
+    for _ in range(200):
+        base = rng.choice(m, size=500, replace=False)
+        sets += [set(base[:300].tolist()), set(base[150:450].tolist())]
+    P = synth.profiles_from_sets(sets + [a | b for a, b in zip(sets[::2], sets[1::2])] +
+                                 [a & b for a, b in zip(sets[::2], sets[1::2])], m)
+    ip, ix = orc.fingerprints(P.indptr, P.indices, P.n, g)
+    F = [set(ix[ip[u]:ip[u + 1]].tolist()) for u in range(P.n)]
+    npair = len(sets) // 2
+    for q in range(npair):
+        Fa, Fb = F[2 * q], F[2 * q + 1]
+        assert F[len(sets) + q] == Fa | Fb
+        assert F[len(sets) + npair + q] <= Fa & Fb
+    fill = np.mean([len(F[u]) for u in range(len(sets))])
+    want = B * (1 - (1 - 1 / B) ** 300)
+    sd = math.sqrt(B * math.exp(-300 / B) * (1 - (1 + 300 / B) * math.exp(-300 / B)))
+    assert abs(fill - want) < 4 * sd / math.sqrt(len(sets)) + 0.5
+
+
+def test_edge_jaccard_matches_sets():
+    from paper_2010_11497_amd import metrics
+    P = synth.random_profiles(26, 80, 150, 1, 40, 1.0)
+    rng = np.random.Generator(np.random.PCG64(27))
+    ids = rng.integers(0, P.n, size=(P.n, 5)).astype(np.uint32)
+    ids[::7, 4] = 0xFFFFFFFF
+    I, U = metrics.edge_jaccard(P.indptr, P.indices, P.m, ids)
+    rows = [set(P.indices[P.indptr[u]:P.indptr[u + 1]].tolist()) for u in range(P.n)]
+    for u in range(P.n):
+        for j in range(5):
+            v = int(ids[u, j])
+            if v == 0xFFFFFFFF:
+                assert I[u, j] == 0 and U[u, j] == 0
+            else:
+                assert I[u, j] == len(rows[u] & rows[v]) and U[u, j] == len(rows[u] | rows[v])
 
 
 # ------------------------------------------------------------ Theorem 2 --
