@@ -167,6 +167,19 @@ c2_status c2_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_para
                      int form, const c2_tuning *tune, uint32_t *members, uint32_t *cl_off,
                      uint32_t *cl_cfg_off, void *ws, size_t ws_bytes, void *stream);
 
+/* Step 1 with the top-level buckets given per user instead of computed by
+ * FastRandomHash: keys[j*n + u] < p->b is user u's bucket in configuration j
+ * (e.g. from a learned assigner, c2_assign_keys).  Users with equal keys form
+ * a cluster; a cluster larger than p->cap is split by FastRandomHash on
+ * `bucket` (as c2_hash_items writes it, values < p->b), starting from H_j(u)
+ * and then recursively as in c2_cluster.  Cluster order: ascending key, a
+ * split cluster replaced as in c2_cluster.  Always runs the grid rounds
+ * (tune->cluster_path is not used).  Outputs, forms and ws as c2_cluster. */
+c2_status c2_cluster_keys(const c2_profiles *P, const uint32_t *keys, const uint32_t *bucket,
+                          const c2_params *p, int form, const c2_tuning *tune, uint32_t *members,
+                          uint32_t *cl_off, uint32_t *cl_cfg_off, void *ws, size_t ws_bytes,
+                          void *stream);
+
 /* Synchronous: C2_OK if the last batched c2_cluster / c2_build that used this
  * workspace split every oversized cluster, C2_E_INCOMPLETE otherwise. */
 c2_status c2_check_complete(const void *ws, void *stream);
@@ -235,6 +248,49 @@ c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uin
 c2_status c2_fingerprint(const c2_profiles *P, const uint32_t *g, uint32_t B, int64_t *fp_indptr,
                          uint32_t *fp_indices, uint64_t *fp_nnz, void *ws, size_t ws_bytes,
                          void *stream);
+
+/* Learned cluster assigner: a per-user bucket in each of the t configurations
+ * from a small network over the user's items, in place of FastRandomHash's
+ * top-level grouping (then c2_cluster_keys, c2_local_knn and c2_merge, whose
+ * exact arithmetic is unchanged).  FastRandomHash remains the fallback: for
+ * users whose best logit does not clear the second by min_gap, and for the
+ * split of groups larger than the cap.  The paper has no such component;
+ * model and fallback rules are this library's own.
+ *   e_u = mean over i in P_u of E[i]      (fp32 sum, rounded to bf16)
+ *   h_u = ReLU(W1 e_u + b1)               (fp32, rounded to bf16)
+ *   z_u = W2 h_u + b2                     (bf16 products, fp32 sums)
+ *   key_j(u) = argmax over c < b of z_u[j*b + c], lowest c on ties.
+ * Weights (device, row-major, caller-owned): E bf16 [m][C2_ASSIGN_DIM],
+ * W1 bf16 [C2_ASSIGN_HIDDEN][C2_ASSIGN_DIM], b1 fp32 [C2_ASSIGN_HIDDEN],
+ * W2 bf16 [t*b][C2_ASSIGN_HIDDEN], b2 fp32 [t*b].  bf16 is passed as its
+ * 16-bit pattern (uint16_t). */
+#define C2_ASSIGN_DIM 64
+#define C2_ASSIGN_HIDDEN 256
+
+/* h [n][C2_ASSIGN_HIDDEN] bf16 (device) = h_u for every user. */
+c2_status c2_assign_hidden(const c2_profiles *P, const uint16_t *E, const uint16_t *W1,
+                           const float *b1, uint16_t *h, void *stream);
+
+/* keys [t][n] (device u32): key_j(u), or b + frh_keys[j*n + u] when frh_keys
+ * (device [t][n], values < b, e.g. c2_frh_keys) is not NULL and the gap
+ * z(top 1) - z(top 2) of head j is below min_gap.  gap [t][n] (device fp32,
+ * may be NULL) receives that gap.  Cluster the keys with p->b >= 2b when the
+ * fallback is on (b otherwise).  b: a multiple of 32.  The n x t*b logits are
+ * never written: the argmax runs in the product's epilogue. */
+c2_status c2_assign_keys(const uint16_t *h, uint32_t n, const uint16_t *W2, const float *b2,
+                         uint32_t t, uint32_t b, const uint32_t *frh_keys, float min_gap,
+                         uint32_t *keys, float *gap, void *stream);
+
+/* Training support.  out [nrows][C2_ASSIGN_DIM] fp32 (device) = e_u in fp32
+ * (not rounded) for u = rows[r] (device u32 [nrows]; NULL = rows 0..nrows-1). */
+c2_status c2_embag(const c2_profiles *P, const uint32_t *rows, uint32_t nrows, const uint16_t *E,
+                   float *out, void *stream);
+
+/* dE [m][C2_ASSIGN_DIM] fp32 (device) += the gradient of the mean bag
+ * through out, given grad [nrows][C2_ASSIGN_DIM] fp32: each item of row r gets
+ * grad[r] / |P_u|.  Atomic fp32 adds: the summation order is not fixed. */
+c2_status c2_embag_backward(const c2_profiles *P, const uint32_t *rows, uint32_t nrows,
+                            const float *grad, float *dE, void *stream);
 
 /* HIP-graph form of c2_build (C2_FORM_BATCHED) on fixed buffers.  Create
  * runs one plain clustering synchronously to learn how many split rounds the

@@ -162,13 +162,15 @@ static void emit(split_ctx *c, const uint32_t *users, uint32_t cnt,
     if (depth > c->max_depth) c->max_depth = depth;
 }
 
-/* H\eta(u) = min{ h(i) : i in P_u, h(i) > eta }, or ORC_NONE. */
+/* H\eta(u) = min{ h(i) : i in P_u, h(i) > eta }, or ORC_NONE.  eta = ORC_ALL
+ * stands for "below every hash value": then the result is H(u) itself. */
+#define ORC_ALL (ORC_NONE - 1)
 static uint64_t next_hash(const split_ctx *c, uint32_t u, uint64_t eta)
 {
     uint64_t best = ORC_NONE;
     for (int64_t p = c->indptr[u]; p < c->indptr[u + 1]; ++p) {
         uint64_t h = c->h[c->indices[p]];
-        if (h > eta && h < best) best = h;
+        if ((eta == ORC_ALL || h > eta) && h < best) best = h;
     }
     return best;
 }
@@ -208,18 +210,15 @@ static void split(split_ctx *c, const uint32_t *users, uint32_t cnt,
     free(kv);
 }
 
-/* Step 1 (Algorithm 1 + recursive splitting) for all t configurations.
- * members[j*n .. j*n+n) receives configuration j's users grouped by final
- * cluster, each cluster's members ascending.  cl_off[c] is the start slot of
- * cluster c (global over configurations, cl_off[total] = t*n), and clusters of
- * configuration j are [cl_cfg_off[j], cl_cfg_off[j+1]).  Cluster order: top-level
- * clusters by ascending hash value; a split cluster is replaced by its
- * sub-clusters (ascending new hash value, each recursively) followed by the
- * users that stayed behind.  Returns the deepest split level reached. */
-int orc_cluster(uint32_t n, uint32_t m, const int64_t *indptr,
-                const uint32_t *indices, const uint32_t *bucket, uint32_t t,
-                uint32_t cap, uint32_t *members, uint32_t *cl_off,
-                uint32_t *cl_cfg_off)
+/* Top-level grouping of configuration j followed by the recursive split.
+ * keys0 == NULL: the group key is H_j(u) (Eq. 3) and an oversized group is
+ * split from its own hash value.  Otherwise keys0[j*n + u] is an externally
+ * assigned bucket (a learned assignment); an oversized group of such users is
+ * split by FastRandomHash from the start, i.e. by H_j(u), then recursively. */
+static int cluster_impl(uint32_t n, uint32_t m, const int64_t *indptr,
+                        const uint32_t *indices, const uint32_t *keys0,
+                        const uint32_t *bucket, uint32_t t, uint32_t cap,
+                        uint32_t *members, uint32_t *cl_off, uint32_t *cl_cfg_off)
 {
     split_ctx c;
     memset(&c, 0, sizeof(c));
@@ -238,9 +237,13 @@ int orc_cluster(uint32_t n, uint32_t m, const int64_t *indptr,
         /* B_j[H_j(u)] <- B_j[H_j(u)] + {u} */
         for (uint32_t u = 0; u < n; ++u) {
             uint64_t best = ORC_NONE;
-            for (int64_t p = indptr[u]; p < indptr[u + 1]; ++p) {
-                uint64_t h = c.h[indices[p]];
-                if (h < best) best = h;
+            if (keys0) {
+                best = keys0[(size_t)j * n + u];
+            } else {
+                for (int64_t p = indptr[u]; p < indptr[u + 1]; ++p) {
+                    uint64_t h = c.h[indices[p]];
+                    if (h < best) best = h;
+                }
             }
             kv[u].key = best;
             kv[u].uid = u;
@@ -250,7 +253,7 @@ int orc_cluster(uint32_t n, uint32_t m, const int64_t *indptr,
             uint32_t e = a;
             while (e < n && kv[e].key == kv[a].key) ++e;
             for (uint32_t q = a; q < e; ++q) grp[q - a] = kv[q].uid;
-            split(&c, grp, e - a, kv[a].key, 0);
+            split(&c, grp, e - a, keys0 ? ORC_ALL : kv[a].key, 0);
             a = e;
         }
     }
@@ -259,6 +262,34 @@ int orc_cluster(uint32_t n, uint32_t m, const int64_t *indptr,
     free(grp);
     free(kv);
     return (int)c.max_depth;
+}
+
+/* Step 1 (Algorithm 1 + recursive splitting) for all t configurations.
+ * members[j*n .. j*n+n) receives configuration j's users grouped by final
+ * cluster, each cluster's members ascending.  cl_off[c] is the start slot of
+ * cluster c (global over configurations, cl_off[total] = t*n), and clusters of
+ * configuration j are [cl_cfg_off[j], cl_cfg_off[j+1]).  Cluster order: top-level
+ * clusters by ascending hash value; a split cluster is replaced by its
+ * sub-clusters (ascending new hash value, each recursively) followed by the
+ * users that stayed behind.  Returns the deepest split level reached. */
+int orc_cluster(uint32_t n, uint32_t m, const int64_t *indptr,
+                const uint32_t *indices, const uint32_t *bucket, uint32_t t,
+                uint32_t cap, uint32_t *members, uint32_t *cl_off,
+                uint32_t *cl_cfg_off)
+{
+    return cluster_impl(n, m, indptr, indices, NULL, bucket, t, cap, members,
+                        cl_off, cl_cfg_off);
+}
+
+/* The same with top-level groups given by keys0[t][n] (ascending key order),
+ * FastRandomHash on `bucket` splitting the oversized ones. */
+int orc_cluster_keys(uint32_t n, uint32_t m, const int64_t *indptr,
+                     const uint32_t *indices, const uint32_t *keys0,
+                     const uint32_t *bucket, uint32_t t, uint32_t cap,
+                     uint32_t *members, uint32_t *cl_off, uint32_t *cl_cfg_off)
+{
+    return cluster_impl(n, m, indptr, indices, keys0, bucket, t, cap, members,
+                        cl_off, cl_cfg_off);
 }
 
 /* ----------------------------------------------------- local KNN (Alg.2) -- */

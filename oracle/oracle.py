@@ -50,6 +50,8 @@ def lib():
         L.orc_frh_keys.argtypes = [u32, u32, P, P, P, u32, P]
         L.orc_cluster.argtypes = [u32, u32, P, P, P, u32, u32, P, P, P]
         L.orc_cluster.restype = i32
+        L.orc_cluster_keys.argtypes = [u32, u32, P, P, P, P, u32, u32, P, P, P]
+        L.orc_cluster_keys.restype = i32
         L.orc_local_knn.argtypes = [u32, u32, P, P, u32, u32, P, P, P, P, P, i32]
         L.orc_merge.argtypes = [u32, P, u32, u32, P, P, P, P, P]
         L.orc_brute_force.argtypes = [u32, u32, P, P, u32, P, u32, P, P, P, i32]
@@ -107,6 +109,22 @@ def cluster(indptr, indices, n, m, bucket, cap):
     cfg = np.empty(t + 1, dtype=np.uint32)
     depth = lib().orc_cluster(n, m, _p(ip), _p(ix), _p(bk), t, cap, _p(members),
                               _p(cl_off), _p(cfg))
+    ncl = int(cfg[t])
+    return members, cl_off[: ncl + 1].copy(), cfg, depth
+
+
+def cluster_keys(indptr, indices, n, m, keys0, bucket, cap):
+    """Step 1 with the top-level groups given per user (keys0[t][n], e.g. a
+    learned assignment) and FastRandomHash on `bucket` splitting every group
+    larger than cap, starting from H_j(u).  Returns as cluster()."""
+    ip, ix = _c(indptr, np.int64), _c(indices, np.uint32)
+    k0, bk = _c(keys0, np.uint32), _c(bucket, np.uint32)
+    t = bk.shape[0]
+    members = np.empty(t * n, dtype=np.uint32)
+    cl_off = np.empty(t * n + 1, dtype=np.uint32)
+    cfg = np.empty(t + 1, dtype=np.uint32)
+    depth = lib().orc_cluster_keys(n, m, _p(ip), _p(ix), _p(k0), _p(bk), t, cap, _p(members),
+                                   _p(cl_off), _p(cfg))
     ncl = int(cfg[t])
     return members, cl_off[: ncl + 1].copy(), cfg, depth
 

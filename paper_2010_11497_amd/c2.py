@@ -28,9 +28,11 @@ OP_VALIDATE, OP_CLUSTER, OP_LOCAL_KNN, OP_BUILD, OP_BRUTE_FORCE, OP_FINGERPRINT 
 
 # every entry point of include/c2.h
 SYMBOLS = ["c2_last_error", "c2_workspace_bytes", "c2_validate", "c2_hash_items", "c2_frh_keys",
-           "c2_cluster", "c2_check_complete", "c2_local_knn", "c2_merge", "c2_build",
-           "c2_brute_force", "c2_fingerprint", "c2_graph_create", "c2_graph_launch",
+           "c2_cluster", "c2_cluster_keys", "c2_check_complete", "c2_local_knn", "c2_merge", "c2_build",
+           "c2_brute_force", "c2_fingerprint", "c2_assign_hidden", "c2_assign_keys",
+           "c2_embag", "c2_embag_backward", "c2_graph_create", "c2_graph_launch",
            "c2_graph_destroy"]
+ASSIGN_DIM, ASSIGN_HIDDEN = 64, 256
 
 
 class C2Error(RuntimeError):
@@ -78,12 +80,17 @@ def load(path: str = LIB_PATH):
     L.c2_hash_items.argtypes = [P, u32, u32, u32, P, P]
     L.c2_frh_keys.argtypes = [PP, P, u32, P, P]
     L.c2_cluster.argtypes = [PP, P, PA, i32, PT, P, P, P, P, sz, P]
+    L.c2_cluster_keys.argtypes = [PP, P, P, PA, i32, PT, P, P, P, P, sz, P]
     L.c2_check_complete.argtypes = [P, P]
     L.c2_local_knn.argtypes = [PP, P, P, P, PA, i32, PT, P, P, P, sz, P]
     L.c2_merge.argtypes = [PP, P, P, PA, P, P, P, P]
     L.c2_build.argtypes = [PP, P, PA, i32, PT, P, P, P, P, sz, P]
     L.c2_brute_force.argtypes = [PP, u32, P, P, P, P, sz, P]
     L.c2_fingerprint.argtypes = [PP, P, u32, P, P, ctypes.POINTER(u64), P, sz, P]
+    L.c2_assign_hidden.argtypes = [PP, P, P, P, P, P]
+    L.c2_assign_keys.argtypes = [P, u32, P, P, u32, u32, P, ctypes.c_float, P, P, P]
+    L.c2_embag.argtypes = [PP, P, u32, P, P, P]
+    L.c2_embag_backward.argtypes = [PP, P, u32, P, P, P]
     L.c2_graph_create.argtypes = [PP, P, PA, PT, P, P, P, P, sz, P, ctypes.POINTER(P)]
     L.c2_graph_launch.argtypes = [P, P]
     L.c2_graph_destroy.argtypes = [P]
@@ -217,6 +224,20 @@ def cluster(P: DeviceProfiles, bucket: torch.Tensor, p: Params, form=FORM_PLAIN,
     return members, cl_off, cfg, ws
 
 
+def cluster_keys(P: DeviceProfiles, keys: torch.Tensor, bucket: torch.Tensor, p: Params,
+                 form=FORM_PLAIN, tune: Optional[Tuning] = None, ws=None):
+    """Step 1 from per-user top-level keys (int32 view of uint32[t][n], < p.b),
+    FastRandomHash on `bucket` splitting the clusters larger than p.cap.
+    Returns as cluster()."""
+    NE = p.t * P.n
+    members, cl_off, cfg = _u32(NE, P.device), _u32(NE + 1, P.device), _u32(p.t + 1, P.device)
+    ws = workspace(P, p, OP_CLUSTER) if ws is None else ws
+    _check(load().c2_cluster_keys(ctypes.byref(P.c), _ptr(keys), _ptr(bucket), ctypes.byref(p),
+                                  form, ctypes.byref(tune) if tune else None, _ptr(members),
+                                  _ptr(cl_off), _ptr(cfg), _ptr(ws), ws.numel(), _stream()))
+    return members, cl_off, cfg, ws
+
+
 def check_complete(ws: torch.Tensor) -> None:
     _check(load().c2_check_complete(_ptr(ws), _stream()))
 
@@ -278,6 +299,50 @@ def build_goldfinger(P: DeviceProfiles, FP: DeviceProfiles, tab: torch.Tensor, p
     members, cl_off, cfg, _ = cluster(P, bucket, p, FORM_PLAIN, tune)
     part = local_knn(FP, members, cl_off, cfg, p, FORM_PLAIN, tune)
     return merge(FP, part[0], part[1], p)
+
+
+def assign_hidden(P: DeviceProfiles, E: torch.Tensor, W1: torch.Tensor, b1: torch.Tensor,
+                  out=None) -> torch.Tensor:
+    """h = ReLU(W1 mean(E[P_u]) + b1) for every user, bf16 [n][256].  E, W1
+    bfloat16 tensors, b1 float32."""
+    out = torch.empty((P.n, ASSIGN_HIDDEN), dtype=torch.bfloat16, device=P.device) \
+        if out is None else out
+    _check(load().c2_assign_hidden(ctypes.byref(P.c), _ptr(E), _ptr(W1), _ptr(b1), _ptr(out),
+                                   _stream()))
+    return out
+
+
+def assign_keys(h: torch.Tensor, W2: torch.Tensor, b2: torch.Tensor, t: int, b: int,
+                frh_keys: Optional[torch.Tensor] = None, min_gap: float = 0.0,
+                with_gap: bool = False):
+    """Per-head argmax of W2 h + b2: keys int32 view of uint32[t][n] (b + FRH
+    key where the gap is below min_gap and frh_keys is given), and the gaps
+    (float32 [t][n]) if with_gap."""
+    n = h.shape[0]
+    keys = _u32((t, n), h.device)
+    gap = torch.empty((t, n), dtype=torch.float32, device=h.device) if with_gap else None
+    _check(load().c2_assign_keys(_ptr(h), n, _ptr(W2), _ptr(b2), int(t), int(b),
+                                 _ptr(frh_keys), float(min_gap), _ptr(keys), _ptr(gap),
+                                 _stream()))
+    return (keys, gap) if with_gap else keys
+
+
+def embag(P: DeviceProfiles, E: torch.Tensor, rows: Optional[torch.Tensor] = None,
+          nrows: Optional[int] = None) -> torch.Tensor:
+    """fp32 mean of E rows over each listed user's items, [nrows][64]."""
+    nrows = (rows.numel() if rows is not None else P.n) if nrows is None else nrows
+    out = torch.empty((nrows, ASSIGN_DIM), dtype=torch.float32, device=P.device)
+    _check(load().c2_embag(ctypes.byref(P.c), _ptr(rows), int(nrows), _ptr(E), _ptr(out),
+                           _stream()))
+    return out
+
+
+def embag_backward(P: DeviceProfiles, grad: torch.Tensor, dE: torch.Tensor,
+                   rows: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dE += gradient of embag() through grad (fp32, [nrows][64])."""
+    _check(load().c2_embag_backward(ctypes.byref(P.c), _ptr(rows), int(grad.shape[0]),
+                                    _ptr(grad), _ptr(dE), _stream()))
+    return dE
 
 
 def build_from_buckets(P: DeviceProfiles, bucket: torch.Tensor, p: Params,

@@ -167,7 +167,7 @@ uint32_t rounds_from(const c2_tuning *tune) {
 c2_status run_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_params *p, int form,
                       const c2_tuning *tune, uint32_t rounds_batched, uint32_t *members, uint32_t *cl_off,
                       uint32_t *cl_cfg_off, char *scratch, uint32_t *status, hipStream_t s,
-                      uint32_t *rounds_used) {
+                      uint32_t *rounds_used, const uint32_t *keys_in = nullptr) {
     ClusterWs w;
     const ClusterDims d = cdims(P->n, p);
     cluster_ws_elems(d, &w);
@@ -185,8 +185,9 @@ c2_status run_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_par
     a.bucket = bucket;
     a.NE = (uint32_t)d.NE;
     a.NP = (uint32_t)d.NP;
+    a.keys_in = keys_in;
     const uint32_t path = tune ? tune->cluster_path : 0;
-    if (path != 1 && cluster_wg_fits(a.n, a.b)) {
+    if (!keys_in && path != 1 && cluster_wg_fits(a.n, a.b)) {
         uint32_t *rctr = nullptr;
         const uint32_t maxr = form == C2_FORM_PLAIN ? kMaxRounds : rounds_batched;
         C2_TRY(cluster_wg_run(a, members, cl_off, cl_cfg_off, scratch, status, maxr, &rctr, s),
@@ -358,6 +359,58 @@ c2_status c2_fingerprint(const c2_profiles *P, const uint32_t *g, uint32_t B, in
     return C2_OK;
 }
 
+c2_status c2_assign_hidden(const c2_profiles *P, const uint16_t *E, const uint16_t *W1,
+                           const float *b1, uint16_t *h, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, nullptr, false)) != C2_OK) return st;
+    if (!E || !W1 || !b1 || !h) return fail(C2_E_ARG, "NULL pointer");
+    C2_TRY(launch_assign_hidden(P->indptr, P->indices, P->nnz, P->n, P->m, E, W1, b1, h,
+                                (hipStream_t)stream),
+           "assign hidden");
+    return C2_OK;
+}
+
+c2_status c2_assign_keys(const uint16_t *h, uint32_t n, const uint16_t *W2, const float *b2,
+                         uint32_t t, uint32_t b, const uint32_t *frh_keys, float min_gap,
+                         uint32_t *keys, float *gap, void *stream) {
+    if (!h || !W2 || !b2 || !keys) return fail(C2_E_ARG, "NULL pointer");
+    if (n == 0 || n > 0x7FFFFFFFu) return fail(C2_E_ARG, "n = %u out of range [1, 2^31)", n);
+    if (t < 1 || t > 64) return fail(C2_E_ARG, "t = %u out of range [1, 64]", t);
+    if (b < 32 || b % 32 || b > (1u << 23)) return fail(C2_E_ARG, "b = %u: a multiple of 32 in [32, 2^23]", b);
+    if ((uint64_t)t * n >= 0xFFFFFFFFull) return fail(C2_E_UNSUPPORTED, "t*n >= 2^32");
+    C2_TRY(launch_assign_keys(h, n, W2, b2, t, b, frh_keys, min_gap, keys, gap,
+                              (hipStream_t)stream),
+           "assign keys");
+    return C2_OK;
+}
+
+c2_status c2_embag(const c2_profiles *P, const uint32_t *rows, uint32_t nrows, const uint16_t *E,
+                   float *out, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, nullptr, false)) != C2_OK) return st;
+    if (!E || !out) return fail(C2_E_ARG, "NULL pointer");
+    if (nrows == 0) return C2_OK;
+    C2_TRY(launch_embag(P->indptr, P->indices, P->nnz, P->n, P->m, rows, nrows, E, out,
+                        (hipStream_t)stream),
+           "embedding bag");
+    return C2_OK;
+}
+
+c2_status c2_embag_backward(const c2_profiles *P, const uint32_t *rows, uint32_t nrows,
+                            const float *grad, float *dE, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, nullptr, false)) != C2_OK) return st;
+    if (!grad || !dE) return fail(C2_E_ARG, "NULL pointer");
+    if (nrows == 0) return C2_OK;
+    C2_TRY(launch_embag_backward(P->indptr, P->indices, P->nnz, P->n, P->m, rows, nrows, grad, dE,
+                                 (hipStream_t)stream),
+           "embedding bag backward");
+    return C2_OK;
+}
+
 c2_status c2_hash_items(const uint64_t *tab, uint32_t t, uint32_t b, uint32_t m, uint32_t *bucket,
                         void *stream) {
     if (!tab || !bucket) return fail(C2_E_ARG, "NULL pointer");
@@ -393,6 +446,23 @@ c2_status c2_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_para
     return run_cluster(P, bucket, p, form, tune, rounds_from(tune), members, cl_off, cl_cfg_off,
                        base + kHeader, reinterpret_cast<uint32_t *>(base), (hipStream_t)stream,
                        nullptr);
+}
+
+c2_status c2_cluster_keys(const c2_profiles *P, const uint32_t *keys, const uint32_t *bucket,
+                          const c2_params *p, int form, const c2_tuning *tune, uint32_t *members,
+                          uint32_t *cl_off, uint32_t *cl_cfg_off, void *ws, size_t ws_bytes,
+                          void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
+    if ((st = check_form(form)) != C2_OK) return st;
+    if (!keys || !bucket || !members || !cl_off || !cl_cfg_off) return fail(C2_E_ARG, "NULL pointer");
+    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_CLUSTER))) != C2_OK)
+        return st;
+    char *base = reinterpret_cast<char *>(ws);
+    return run_cluster(P, bucket, p, form, tune, rounds_from(tune), members, cl_off, cl_cfg_off,
+                       base + kHeader, reinterpret_cast<uint32_t *>(base), (hipStream_t)stream,
+                       nullptr, keys);
 }
 
 c2_status c2_check_complete(const void *ws, void *stream) {

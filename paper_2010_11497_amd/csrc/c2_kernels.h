@@ -26,6 +26,22 @@ hipError_t launch_fingerprint(const int64_t *indptr, const uint32_t *indices, ui
                               int64_t *fp_indptr, uint32_t *fp_indices, void *ws, uint32_t *err,
                               hipStream_t s);
 
+// ---- learned assigner (embedding bag dim 64, hidden 256)
+constexpr int kAsgDim = 64;
+constexpr int kAsgHidden = 256;
+hipError_t launch_assign_hidden(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                                uint32_t n, uint32_t m, const uint16_t *E, const uint16_t *W1,
+                                const float *b1, uint16_t *h, hipStream_t s);
+hipError_t launch_assign_keys(const uint16_t *h, uint32_t n, const uint16_t *W2, const float *b2,
+                              uint32_t t, uint32_t b, const uint32_t *frh, float min_gap,
+                              uint32_t *keys, float *gap, hipStream_t s);
+hipError_t launch_embag(const int64_t *indptr, const uint32_t *indices, uint64_t nnz, uint32_t n,
+                        uint32_t m, const uint32_t *rows, uint32_t nrows, const uint16_t *E,
+                        float *out, hipStream_t s);
+hipError_t launch_embag_backward(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                                 uint32_t n, uint32_t m, const uint32_t *rows, uint32_t nrows,
+                                 const float *grad, float *dE, hipStream_t s);
+
 // ---- clustering
 struct ClusterDims {
     size_t NE;  // t*n slots
@@ -52,6 +68,9 @@ struct ClusterArgs {
     uint32_t n, m, t, b, bb, cap;
     const uint32_t *bucket;
     uint32_t NE, NP;
+    // top-level keys given per user ([t][n], < b) instead of H_j(u); the
+    // oversized top-level groups are then split by FastRandomHash from H_j(u)
+    const uint32_t *keys_in = nullptr;
 };
 size_t cluster_ws_elems(const ClusterDims &d, ClusterWs *w);
 // one workgroup per configuration (n <= kWgMaxN), all split rounds in LDS

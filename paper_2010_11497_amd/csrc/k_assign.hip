@@ -1,0 +1,302 @@
+// Learned cluster assigner: an embedding bag over the user's items and a
+// two-layer MLP whose output is one bucket per hash configuration.  It takes
+// the place of FastRandomHash's top-level grouping; FastRandomHash stays the
+// fallback (low-confidence users, and the split of oversized groups).
+//
+//   e_u   = mean_{i in P_u} E[i]             E bf16 [m][64], fp32 sum, -> bf16
+//   h_u   = ReLU(W1 e_u + b1)                W1 bf16 [256][64], b1 fp32, -> bf16
+//   z_u   = W2 h_u + b2                      W2 bf16 [t*b][256], b2 fp32, fp32
+//   key_j = argmax_{c < b} z_u[j*b + c]      lowest index on ties
+//   gap_j = top-1 minus top-2 logit of head j
+//
+// k_assign_hidden: one wave per user, W1 staged (transposed, fp32) in LDS.
+// k_assign_keys:   the logits as a bf16 MFMA product (32x32x16), buckets as
+//                  the M dimension and users as N, the per-head argmax fused
+//                  into the epilogue, so the n x t*b logits never reach HBM.
+// k_embag_fwd/bwd: the embedding bag alone in fp32, for training.
+#include "c2_internal.h"
+#include "c2_kernels.h"
+
+namespace c2 {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+C2_DEV float bf16_to_f32(uint16_t x) { return __uint_as_float((uint32_t)x << 16); }
+
+// round to nearest even (finite inputs)
+C2_DEV uint16_t f32_to_bf16(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Sum of E rows over the items of row u, lane = dimension; returns the count.
+C2_DEV uint32_t bag_sum(const int64_t *indptr, const uint32_t *indices, uint64_t nnz, uint32_t m,
+                        const uint16_t *E, uint32_t u, int lane, float &sum) {
+    uint64_t a, e;
+    row_range(indptr, u, nnz, a, e);
+    float s = 0.f;
+    for (uint64_t c = a; c < e; c += 64) {
+        const uint32_t cnt = (uint32_t)(e - c < 64 ? e - c : 64);
+        const uint32_t mine = (uint32_t)lane < cnt ? indices[c + lane] : 0u;
+#pragma unroll 8
+        for (uint32_t q = 0; q < cnt; ++q) {
+            const uint32_t i = __builtin_amdgcn_readlane(mine, q);
+            if (i < m) s += bf16_to_f32(E[(size_t)i * kAsgDim + lane]);
+        }
+    }
+    sum = s;
+    return (uint32_t)(e - a);
+}
+
+constexpr int kHidWaves = 4;
+
+__global__ __launch_bounds__(64 * kHidWaves) void k_assign_hidden(
+    const int64_t *__restrict__ indptr, const uint32_t *__restrict__ indices, uint64_t nnz,
+    uint32_t n, uint32_t m, const uint16_t *__restrict__ E, const uint16_t *__restrict__ W1,
+    const float *__restrict__ b1, uint16_t *__restrict__ h) {
+    __shared__ float w1t[kAsgDim][kAsgHidden];
+    for (uint32_t x = threadIdx.x; x < kAsgDim * kAsgHidden; x += 64 * kHidWaves) {
+        const uint32_t o = x / kAsgDim, k = x % kAsgDim;
+        w1t[k][o] = bf16_to_f32(W1[x]);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    float bias[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bias[q] = b1[lane + 64 * q];
+    for (uint32_t u = blockIdx.x * kHidWaves + wid; u < n; u += gridDim.x * kHidWaves) {
+        float s;
+        const uint32_t len = bag_sum(indptr, indices, nnz, m, E, u, lane, s);
+        const float eu = bf16_to_f32(f32_to_bf16(len ? s / (float)len : 0.f));
+        float acc[4] = {bias[0], bias[1], bias[2], bias[3]};
+#pragma unroll 16
+        for (int k = 0; k < kAsgDim; ++k) {
+            const float ek = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(eu), k));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = fmaf(w1t[k][lane + 64 * q], ek, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            h[(size_t)u * kAsgHidden + lane + 64 * q] = f32_to_bf16(acc[q] > 0.f ? acc[q] : 0.f);
+    }
+}
+
+// ---------------------------------------------------------------- logits
+
+constexpr int kKeyWaves = 8;
+constexpr int kKeyUsers = 64 * kKeyWaves;  // 64 users (two 32-column blocks) per wave
+constexpr int kTileB = 32;                 // buckets per tile (one MFMA row block)
+constexpr int kRowPad = kAsgHidden + 8;    // bf16 per LDS row (breaks bank aliasing)
+constexpr int kSteps = kAsgHidden / 16;    // MFMA k-steps per tile
+
+struct Best {
+    float v1, v2;
+    uint32_t idx;
+};
+
+C2_DEV void best_reset(Best &b) {
+    b.v1 = -__builtin_huge_valf();
+    b.v2 = -__builtin_huge_valf();
+    b.idx = 0xFFFFFFFFu;
+}
+
+// buckets arrive in ascending order per lane: strict '>' keeps the lowest
+C2_DEV void best_push(Best &b, float v, uint32_t c) {
+    if (v > b.v1) {
+        b.v2 = b.v1;
+        b.v1 = v;
+        b.idx = c;
+    } else if (v > b.v2) {
+        b.v2 = v;
+    }
+}
+
+// lanes l and l^32 hold the same user over disjoint bucket sets
+C2_DEV void best_combine(Best &b) {
+    const float o1 = __shfl_xor(b.v1, 32), o2 = __shfl_xor(b.v2, 32);
+    const uint32_t oi = __shfl_xor(b.idx, 32);
+    if (o1 > b.v1) {
+        b.v2 = fmaxf(o2, b.v1);
+        b.v1 = o1;
+        b.idx = oi;
+    } else if (o1 == b.v1) {
+        b.v2 = b.v1;
+        b.idx = oi < b.idx ? oi : b.idx;
+    } else {
+        b.v2 = fmaxf(b.v2, o1);
+    }
+}
+
+__global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
+    const uint16_t *__restrict__ h, uint32_t n, const uint16_t *__restrict__ W2,
+    const float *__restrict__ b2, uint32_t t, uint32_t b, const uint32_t *__restrict__ frh,
+    float min_gap, uint32_t *__restrict__ keys, float *__restrict__ gap) {
+    __shared__ __attribute__((aligned(16))) uint16_t wt[2][kTileB * kRowPad];
+    __shared__ float bt[2][kTileB];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t ubase = blockIdx.x * kKeyUsers + wid * 64;
+    const int half = lane >> 5, col = lane & 31;
+
+    // this wave's users as MFMA B fragments: B[k][j] = h[user j][k]
+    bf16x8 bf[2][kSteps];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t u = ubase + c * 32 + col;
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (u < n)
+                v = *reinterpret_cast<const uint4 *>(h + (size_t)u * kAsgHidden + 16 * s + 8 * half);
+            bf[c][s] = __builtin_bit_cast(bf16x8, v);
+        }
+    }
+
+    const uint32_t tiles_per_head = b / kTileB;
+    const uint32_t ntiles = t * tiles_per_head;
+    // cooperative tile load: 32 rows x 512 B = 1024 chunks of 16 B, two per thread
+    auto load_tile = [&](uint32_t T, uint4 (&r)[2], float &bias) {
+        const size_t row0 = (size_t)T * kTileB;
+#pragma unroll
+        for (int z = 0; z < 2; ++z) {
+            const uint32_t q = threadIdx.x + 64 * kKeyWaves * z;
+            r[z] = *reinterpret_cast<const uint4 *>(W2 + (row0 + q / 32) * kAsgHidden + (q % 32) * 8);
+        }
+        bias = threadIdx.x < kTileB ? b2[row0 + threadIdx.x] : 0.f;
+    };
+    auto store_tile = [&](int buf, const uint4 (&r)[2], float bias) {
+#pragma unroll
+        for (int z = 0; z < 2; ++z) {
+            const uint32_t q = threadIdx.x + 64 * kKeyWaves * z;
+            *reinterpret_cast<uint4 *>(&wt[buf][(q / 32) * kRowPad + (q % 32) * 8]) = r[z];
+        }
+        if (threadIdx.x < kTileB) bt[buf][threadIdx.x] = bias;
+    };
+
+    uint4 pre[2];
+    float pbias;
+    load_tile(0, pre, pbias);
+    store_tile(0, pre, pbias);
+    __syncthreads();
+
+    Best best[2];
+    best_reset(best[0]);
+    best_reset(best[1]);
+    for (uint32_t T = 0; T < ntiles; ++T) {
+        const int buf = T & 1;
+        if (T + 1 < ntiles) load_tile(T + 1, pre, pbias);
+        f32x16 acc[2] = {};
+        const uint16_t *arow = &wt[buf][col * kRowPad + 8 * half];
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(arow + 16 * s));
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[0][s], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[1][s], acc[1], 0, 0, 0);
+        }
+        const uint32_t tin = T % tiles_per_head;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r / 4) + 4 * half + (r % 4);
+            const float bias = bt[buf][row];
+            const uint32_t c = tin * kTileB + row;
+            best_push(best[0], acc[0][r] + bias, c);
+            best_push(best[1], acc[1][r] + bias, c);
+        }
+        if (tin == tiles_per_head - 1) {
+            const uint32_t j = T / tiles_per_head;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                best_combine(best[c]);
+                const uint32_t u = ubase + c * 32 + col;
+                if (half == 0 && u < n) {
+                    const float g = best[c].v1 - best[c].v2;
+                    uint32_t key = best[c].idx;
+                    if (frh && g < min_gap) key = b + frh[(size_t)j * n + u];
+                    keys[(size_t)j * n + u] = key;
+                    if (gap) gap[(size_t)j * n + u] = g;
+                }
+                best_reset(best[c]);
+            }
+        }
+        __syncthreads();
+        if (T + 1 < ntiles) store_tile(buf ^ 1, pre, pbias);
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------------- training
+
+__global__ __launch_bounds__(256) void k_embag_fwd(const int64_t *__restrict__ indptr,
+                                                   const uint32_t *__restrict__ indices,
+                                                   uint64_t nnz, uint32_t n, uint32_t m,
+                                                   const uint32_t *__restrict__ rows,
+                                                   uint32_t nrows, const uint16_t *__restrict__ E,
+                                                   float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nrows) return;
+    const uint32_t u = rows ? rows[r] : r;
+    float s = 0.f;
+    uint32_t len = 0;
+    if (u < n) len = bag_sum(indptr, indices, nnz, m, E, u, lane, s);
+    out[(size_t)r * kAsgDim + lane] = len ? s / (float)len : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_embag_bwd(const int64_t *__restrict__ indptr,
+                                                   const uint32_t *__restrict__ indices,
+                                                   uint64_t nnz, uint32_t n, uint32_t m,
+                                                   const uint32_t *__restrict__ rows,
+                                                   uint32_t nrows, const float *__restrict__ grad,
+                                                   float *__restrict__ dE) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nrows) return;
+    const uint32_t u = rows ? rows[r] : r;
+    if (u >= n) return;
+    uint64_t a, e;
+    row_range(indptr, u, nnz, a, e);
+    if (e == a) return;
+    const float g = grad[(size_t)r * kAsgDim + lane] / (float)(e - a);
+    for (uint64_t p = a; p < e; ++p) {
+        const uint32_t i = indices[p];
+        if (i < m) atomicAdd(&dE[(size_t)i * kAsgDim + lane], g);
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+hipError_t launch_assign_hidden(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                                uint32_t n, uint32_t m, const uint16_t *E, const uint16_t *W1,
+                                const float *b1, uint16_t *h, hipStream_t s) {
+    uint32_t blocks = (uint32_t)div_up(n, kHidWaves);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_assign_hidden, dim3(blocks), dim3(64 * kHidWaves), 0, s, indptr, indices,
+                       nnz, n, m, E, W1, b1, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_assign_keys(const uint16_t *h, uint32_t n, const uint16_t *W2, const float *b2,
+                              uint32_t t, uint32_t b, const uint32_t *frh, float min_gap,
+                              uint32_t *keys, float *gap, hipStream_t s) {
+    hipLaunchKernelGGL(k_assign_keys, dim3((uint32_t)div_up(n, kKeyUsers)), dim3(64 * kKeyWaves),
+                       0, s, h, n, W2, b2, t, b, frh, min_gap, keys, gap);
+    return hipGetLastError();
+}
+
+hipError_t launch_embag(const int64_t *indptr, const uint32_t *indices, uint64_t nnz, uint32_t n,
+                        uint32_t m, const uint32_t *rows, uint32_t nrows, const uint16_t *E,
+                        float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_embag_fwd, dim3((uint32_t)div_up(nrows, 4)), dim3(256), 0, s, indptr,
+                       indices, nnz, n, m, rows, nrows, E, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_embag_backward(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                                 uint32_t n, uint32_t m, const uint32_t *rows, uint32_t nrows,
+                                 const float *grad, float *dE, hipStream_t s) {
+    hipLaunchKernelGGL(k_embag_bwd, dim3((uint32_t)div_up(nrows, 4)), dim3(256), 0, s, indptr,
+                       indices, nnz, n, m, rows, nrows, grad, dE);
+    return hipGetLastError();
+}
+
+}  // namespace c2

@@ -18,6 +18,8 @@
 //   scatter: inside each parent segment, the groups in ascending e' first,
 //            then the users that stayed, in their previous order; new segments
 //            larger than cap become active, the others final.
+// With externally given top-level keys (a learned assignment) the root's
+// groups start their split from eta1 = 0, i.e. from H_j(u) itself.
 // Every step is a grid over all t*n slots whose work depends only on device
 // data, so the rounds can be enqueued without synchronising.
 #include "c2_internal.h"
@@ -137,8 +139,8 @@ __global__ __launch_bounds__(256) void k_clu_scatter(
     const uint64_t *skey, const uint32_t *sval, const uint32_t *n_act, uint32_t bb, uint32_t cap,
     const uint32_t *A_uid, const uint32_t *A_rank, const uint32_t *P_start, const uint32_t *P_len,
     const uint32_t *P_q0, const uint32_t *glb, const uint32_t *glen, const uint64_t *fs,
-    uint32_t *E_uid, uint32_t *E_seg, uint32_t *S_state, uint32_t *S_eta1, uint32_t *S_len,
-    uint32_t *new_active) {
+    const uint32_t *P_state, uint32_t given_keys, uint32_t *E_uid, uint32_t *E_seg,
+    uint32_t *S_state, uint32_t *S_eta1, uint32_t *S_len, uint32_t *new_active) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= *n_act) return;
     // (a) q as a sorted entry: place it inside its group
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(256) void k_clu_scatter(
             if (q == lb) {
                 const bool big = len > cap;
                 S_state[gs] = big ? kActive : kFinal;
-                S_eta1[gs] = e + 1;
+                S_eta1[gs] = (given_keys && P_state[r] == kRoot) ? 0u : e + 1;
                 S_len[gs] = len;
                 if (big) atomicAdd(new_active, 1u);
             }
@@ -265,7 +267,8 @@ hipError_t cluster_round(const ClusterArgs &a, const ClusterPtrs &c, uint32_t ro
     hipError_t e = scan_u64(c.mark, c.mark, NE, c.mtmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_clu_fill, grid_for((uint64_t)NE * kFillLanes), dim3(256), 0, s,
-                       a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket, c.keys0, a.b, a.bb,
+                       a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket,
+                       a.keys_in ? a.keys_in : c.keys0, a.b, a.bb,
                        c.E_uid, c.E_seg, c.S_state, c.S_eta1, c.S_len, c.mark, NE, c.A_uid,
                        c.A_rank, c.P_start, c.P_len, c.P_state, c.P_q0, c.key, c.val);
     const uint32_t *n_act = reinterpret_cast<const uint32_t *>(c.mark + NE);
@@ -282,7 +285,8 @@ hipError_t cluster_round(const ClusterArgs &a, const ClusterPtrs &c, uint32_t ro
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_clu_scatter, grid_for(NE), dim3(256), 0, s, skey, sval, n_act, a.bb,
                        a.cap, c.A_uid, c.A_rank, c.P_start, c.P_len, c.P_q0, c.glb, c.glen, c.flg,
-                       c.E_uid, c.E_seg, c.S_state, c.S_eta1, c.S_len, c.ctr + 1 + round);
+                       c.P_state, a.keys_in ? 1u : 0u, c.E_uid, c.E_seg, c.S_state, c.S_eta1,
+                       c.S_len, c.ctr + 1 + round);
     return hipGetLastError();
 }
 
@@ -290,6 +294,7 @@ hipError_t cluster_init(const ClusterArgs &a, const ClusterPtrs &c, hipStream_t 
     hipLaunchKernelGGL(k_clu_init, grid_for(a.NE > kMaxRounds + 2 ? a.NE : kMaxRounds + 2),
                        dim3(256), 0, s, c.E_uid, c.E_seg, c.S_state, c.S_eta1, c.S_len, a.n, a.NE,
                        c.ctr, (uint32_t)(kMaxRounds + 2));
+    if (a.keys_in) return hipGetLastError();
     return launch_frh_keys(a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket, a.t, a.b, c.keys0, s);
 }
 

@@ -204,3 +204,32 @@ def profiles_from_sets(sets, m: int) -> Profiles:
     indptr[1:] = np.cumsum([len(r) for r in rows])
     indices = np.concatenate(rows) if n else np.zeros(0, np.uint32)
     return Profiles(n=n, m=m, indptr=indptr, indices=indices.astype(np.uint32))
+
+
+def bf16_bits_from_normal(rng: np.random.Generator, shape, scale: float) -> np.ndarray:
+    """uint16 bfloat16 patterns of seeded normal draws (the float32 draw's high
+    half, i.e. truncated): random bf16 values, not a rounding of anything."""
+    f = (rng.standard_normal(shape) * scale).astype(np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def assigner_weights(m: int, t: int, b: int, seed: int, dim: int = 64, hidden: int = 256):
+    """Seeded random weights of the learned assigner: E [m][dim], W1
+    [hidden][dim], W2 [t*b][hidden] as bf16 patterns (uint16), b1 [hidden] and
+    b2 [t*b] float32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    E = bf16_bits_from_normal(rng, (m, dim), 1.0)
+    W1 = bf16_bits_from_normal(rng, (hidden, dim), 1.0 / np.sqrt(dim))
+    b1 = (rng.standard_normal(hidden) * 0.1).astype(np.float32)
+    W2 = bf16_bits_from_normal(rng, (t * b, hidden), 1.0 / np.sqrt(hidden))
+    b2 = (rng.standard_normal(t * b) * 0.1).astype(np.float32)
+    return E, W1, b1, W2, b2
+
+
+def hidden_inputs(n: int, seed: int, hidden: int = 256) -> np.ndarray:
+    """Seeded stand-in for the hidden layer (uint16 bf16 patterns [n][hidden]):
+    non-negative, about half exact zeros, as after a ReLU."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = np.abs(rng.standard_normal((n, hidden))).astype(np.float32)
+    f[rng.random((n, hidden)) < 0.5] = 0.0
+    return (f.view(np.uint32) >> 16).astype(np.uint16)

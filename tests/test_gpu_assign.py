@@ -1,0 +1,224 @@
+"""GPU parity of the learned cluster assigner and of clustering from given
+keys, through the C ABI, against the CPU oracle on the same seeded inputs.
+
+Floating-point decides an integer here (the argmax), so the comparison
+follows the arithmetic: the kernel sums bf16 products in fp32, whose error is
+bounded by eps = 2^-14 * (|h| |W2|^T + |b2|) (256 terms, unit roundoff 2^-24,
+with slack).  Where the oracle's top-2 gap exceeds 2*eps the keys must be
+equal; elsewhere the kernel's bucket must be within 2*eps of the maximum.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2010_11497_amd import c2, metrics, synth  # noqa: E402
+
+THREADS = 16
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    from oracle import assign
+    return assign
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def bf16_dev(bits):
+    return torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
+
+
+def bf16_host(t):
+    return t.view(torch.int16).cpu().numpy().view(np.uint16)
+
+
+@pytest.mark.parametrize("n,m,lo,hi", [(1, 5, 1, 5), (1500, 800, 1, 120), (777, 3000, 20, 900)])
+def test_assign_hidden(A, n, m, lo, hi):
+    say("assign hidden", n, m)
+    P = synth.random_profiles(9000 + n, n, m, lo, hi, 1.0)
+    E, W1, b1, _, _ = synth.assigner_weights(m, 1, 32, 9100 + n)
+    dP = c2.DeviceProfiles.from_synth(P)
+    h = c2.assign_hidden(dP, bf16_dev(E), bf16_dev(W1), torch.from_numpy(b1).cuda())
+    torch.cuda.synchronize()
+    got = A.from_bf16_bits(bf16_host(h))
+    Ev, W1v, b1v = A.from_bf16_bits(E), A.from_bf16_bits(W1), b1.astype(np.float64)
+    e, want = A.hidden(P.indptr, P.indices, Ev, W1v, b1v)
+    # one bf16 step of e moves W1 e by at most 2^-8 |W1| |e|; one of h is 2^-7 |h|
+    tol = 2.0 ** -8 * (np.abs(e) @ np.abs(W1v).T + np.abs(b1v)) + 2.0 ** -7 * np.abs(want)
+    assert np.all(np.abs(got - want) <= tol + 1e-30)
+    assert np.mean(got == want) > 0.99
+
+
+def check_keys(A, hb, W2, b2, t, b, keys, gap):
+    hv, W2v, b2v = A.from_bf16_bits(hb), A.from_bf16_bits(W2), b2.astype(np.float64)
+    wkey, wgap, z = A.keys(hv, W2v, b2v, t, b)
+    eps_all = 2.0 ** -14 * (np.abs(hv) @ np.abs(W2v).T + np.abs(b2v)) + 1e-6
+    n = hv.shape[0]
+    exact = 0
+    for j in range(t):
+        zj = z[:, j * b:(j + 1) * b]
+        eps = eps_all[:, j * b:(j + 1) * b].max(axis=1)
+        gk = keys[j].astype(np.int64)
+        assert np.all(gk < b)
+        chosen = zj[np.arange(n), gk]
+        assert np.all(chosen >= zj.max(axis=1) - 2 * eps)
+        clear = wgap[j] > 2 * eps
+        assert np.array_equal(gk[clear], wkey[j][clear].astype(np.int64))
+        exact += int(np.sum(gk == wkey[j]))
+        if gap is not None:
+            assert np.all(np.abs(gap[j] - wgap[j]) <= 4 * eps)
+    return exact / (t * n), wgap
+
+
+@pytest.mark.parametrize("n,t,b", [(1, 2, 32), (513, 3, 1024), (1500, 8, 256), (100, 1, 8192)])
+def test_assign_keys(A, n, t, b):
+    say("assign keys", n, t, b)
+    hb = synth.hidden_inputs(n, 9200 + n)
+    _, _, _, W2, b2 = synth.assigner_weights(10, t, b, 9300 + b)
+    keys, gap = c2.assign_keys(bf16_dev(hb), bf16_dev(W2), torch.from_numpy(b2).cuda(), t, b,
+                               with_gap=True)
+    torch.cuda.synchronize()
+    frac, wgap = check_keys(A, hb, W2, b2, t, b, c2.to_u32(keys).reshape(t, n),
+                            gap.cpu().numpy().astype(np.float64))
+    assert frac > 0.98
+    # the FastRandomHash fallback below a gap threshold
+    rng = np.random.Generator(np.random.PCG64(9400 + n))
+    frh = rng.integers(0, b, size=(t, n), dtype=np.uint32)
+    thr = float(np.median(wgap))
+    k2 = c2.assign_keys(bf16_dev(hb), bf16_dev(W2), torch.from_numpy(b2).cuda(), t, b,
+                        torch.from_numpy(frh.view(np.int32)).cuda(), thr)
+    torch.cuda.synchronize()
+    k2 = c2.to_u32(k2).reshape(t, n)
+    g = gap.cpu().numpy()
+    low = g < np.float32(thr)
+    assert np.array_equal(k2[low], frh[low] + b)
+    assert np.array_equal(k2[~low], c2.to_u32(keys).reshape(t, n)[~low])
+
+
+def test_embag_forward_backward(A):
+    P = synth.random_profiles(9500, 900, 700, 1, 200, 1.0)
+    E, _, _, _, _ = synth.assigner_weights(P.m, 1, 32, 9501)
+    dP = c2.DeviceProfiles.from_synth(P)
+    rows = np.random.Generator(np.random.PCG64(9502)).integers(0, P.n, 333).astype(np.uint32)
+    drows = torch.from_numpy(rows.view(np.int32)).cuda()
+    out = c2.embag(dP, bf16_dev(E), drows)
+    Ev = A.from_bf16_bits(E)
+    want = A.embag(P.indptr, P.indices, Ev, rows.astype(np.int64))
+    tol = 2.0 ** -20 * (A.embag(P.indptr, P.indices, np.abs(Ev), rows.astype(np.int64)) + 1)
+    assert np.all(np.abs(out.cpu().numpy() - want) <= tol)
+    g = np.random.Generator(np.random.PCG64(9503)).standard_normal((len(rows), 64)).astype(np.float32)
+    dE = torch.zeros((P.m, 64), dtype=torch.float32, device="cuda")
+    c2.embag_backward(dP, torch.from_numpy(g).cuda(), dE, drows)
+    wdE = A.embag_backward(P.indptr, P.indices, P.m, g.astype(np.float64), rows.astype(np.int64))
+    absd = A.embag_backward(P.indptr, P.indices, P.m, np.abs(g).astype(np.float64),
+                            rows.astype(np.int64))
+    assert np.all(np.abs(dE.cpu().numpy() - wdE) <= 2.0 ** -18 * (absd + 1e-3))
+
+
+@pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
+@pytest.mark.parametrize("n,m,t,b,nb,cap", [(600, 300, 3, 64, 40, 20), (3000, 1500, 8, 512, 300, 50),
+                                             (400, 100, 2, 16, 1, 30), (9000, 2000, 4, 1024, 32, 200)])
+def test_cluster_keys(orc, n, m, t, b, nb, cap, form):
+    """Given keys (seeded, values < nb <= b) grouped, oversized groups split by
+    FastRandomHash from H_j(u), against the oracle."""
+    say("cluster keys", n, m, t, b, nb, cap, form)
+    P = synth.random_profiles(9600 + n, n, m, 1, 40, 1.0)
+    tab = synth.hash_tables(t, 9700 + n)
+    bucket = orc.hash_items(tab, b, m)
+    keys = np.random.Generator(np.random.PCG64(9800 + n)).integers(0, nb, (t, n), dtype=np.uint32)
+    dP = c2.DeviceProfiles.from_synth(P)
+    p = c2.params(t, b, cap, 1)
+    tu = c2.tuning(split_rounds=64 if form else 0)
+    mem, off, cfg, ws = c2.cluster_keys(dP, torch.from_numpy(keys.view(np.int32)).cuda(),
+                                        torch.from_numpy(bucket.view(np.int32)).cuda(), p, form, tu)
+    torch.cuda.synchronize()
+    if form == c2.FORM_BATCHED:
+        c2.check_complete(ws)
+    om, ooff, ocfg, _ = orc.cluster_keys(P.indptr, P.indices, n, m, keys, bucket, cap)
+    gcfg = c2.to_u32(cfg)
+    assert np.array_equal(gcfg, ocfg)
+    assert np.array_equal(c2.to_u32(off)[: gcfg[-1] + 1], ooff)
+    assert np.array_equal(c2.to_u32(mem), om)
+
+
+def test_cluster_keys_from_frh_keys_equals_cluster(orc):
+    P = synth.random_profiles(9900, 2000, 800, 1, 50, 1.1)
+    t, b, cap = 4, 256, 60
+    dP = c2.DeviceProfiles.from_synth(P)
+    dtab = c2.tables_to_device(synth.hash_tables(t, 9901))
+    bucket = c2.hash_items(dtab, b, P.m)
+    keys = c2.frh_keys(dP, bucket)
+    p = c2.params(t, b, cap, 1)
+    a = c2.cluster(dP, bucket, p, c2.FORM_PLAIN, c2.tuning(cluster_path=c2.CLUSTER_GRID))
+    k = c2.cluster_keys(dP, keys, bucket, p)
+    torch.cuda.synchronize()
+    ncl = int(c2.to_u32(a[2])[-1])
+    assert torch.equal(a[0], k[0]) and torch.equal(a[2], k[2])
+    assert torch.equal(a[1][: ncl + 1], k[1][: ncl + 1])    # entries past ncl are unused
+
+
+def test_learned_pipeline_end_to_end(A, orc):
+    """Weights -> hidden -> keys (FRH fallback on) -> clustering -> local KNN ->
+    merge, all on the GPU.  Keys agree with the oracle wherever its gap is
+    clear of the rounding bound; the graph's similarities are the exact ones
+    of the edges it lists, in the exact order."""
+    w = synth.WORKLOADS["n2k_m1k"]
+    P = synth.make_profiles(w)
+    t, b = w.t, 256
+    E, W1, b1, W2, b2 = synth.assigner_weights(P.m, t, b, 9950)
+    dP = c2.DeviceProfiles.from_synth(P)
+    dtab = c2.tables_to_device(synth.hash_tables(t, w.hash_seed))
+    bucket = c2.hash_items(dtab, b, P.m)
+    frh = c2.frh_keys(dP, bucket)
+    h = c2.assign_hidden(dP, bf16_dev(E), bf16_dev(W1), torch.from_numpy(b1).cuda())
+    keys, gap = c2.assign_keys(h, bf16_dev(W2), torch.from_numpy(b2).cuda(), t, b, frh, 0.05,
+                               with_gap=True)
+    p = c2.params(t, 2 * b, w.cap, w.k)
+    mem, off, cfg, _ = c2.cluster_keys(dP, keys, bucket, p)
+    part = c2.local_knn(dP, mem, off, cfg, p)
+    kid, kI, kU = c2.merge(dP, part[0], part[1], p)
+    torch.cuda.synchronize()
+    # keys of the users whose hidden layer equals the oracle's
+    e, hw = A.hidden(P.indptr, P.indices, A.from_bf16_bits(E), A.from_bf16_bits(W1),
+                     b1.astype(np.float64))
+    hg = A.from_bf16_bits(bf16_host(h))
+    same = np.all(hg == hw, axis=1)
+    assert same.mean() > 0.9
+    hb = bf16_host(h)[same]
+    gk = c2.to_u32(keys).reshape(t, P.n)[:, same]
+    g = gap.cpu().numpy()[:, same]
+    learned = g >= np.float32(0.05)
+    hv, W2v, b2v = A.from_bf16_bits(hb), A.from_bf16_bits(W2), b2.astype(np.float64)
+    wkey, wgap, _ = A.keys(hv, W2v, b2v, t, b)
+    eps = 2.0 ** -14 * (np.abs(hv) @ np.abs(W2v).T + np.abs(b2v)) + 1e-6
+    eps = np.stack([eps[:, j * b:(j + 1) * b].max(axis=1) for j in range(t)])
+    fk = c2.to_u32(frh).reshape(t, P.n)[:, same]
+    assert np.array_equal(gk[~learned], fk[~learned] + b)
+    clear = learned & (wgap > 2 * eps) & (np.abs(g - 0.05) > 4 * eps)
+    assert np.array_equal(gk[clear], wkey[clear])
+    # the graph: exact integer similarities of the listed edges, exact order
+    ids, I, U = c2.to_u32(kid), c2.to_u32(kI), c2.to_u32(kU)
+    eI, eU = metrics.edge_jaccard(P.indptr, P.indices, P.m, ids)
+    assert np.array_equal(I.astype(np.int64), eI) and np.array_equal(U.astype(np.int64), eU)
+    for u in range(0, P.n, 7):
+        row = [(int(I[u, q]), int(U[u, q]), int(ids[u, q])) for q in range(w.k) if ids[u, q] != c2.C2_PAD]
+        for (i1, u1, v1), (i2, u2, v2) in zip(row, row[1:]):
+            assert i1 * u2 > i2 * u1 or (i1 * u2 == i2 * u1 and v1 < v2)
+        assert len({v for _, _, v in row}) == len(row) and u not in {v for _, _, v in row}

@@ -393,6 +393,57 @@ def test_minhash_clusters_are_min_items(orc):
         assert got == [want[v] for v in sorted(want)]
 
 
+# ------------------------------------- externally assigned top level ----
+
+def test_cluster_keys_with_frh_keys_is_frh(orc):
+    """Top-level groups given as the FastRandomHash keys themselves: the
+    oversized ones first split by H_j (one group, every member shares it), then
+    by H\\eta as usual, so the partition and its order equal Step 1's."""
+    for seed, (n, m, t, b, cap) in enumerate([(400, 150, 3, 16, 30), (300, 2000, 4, 128, 2),
+                                              (500, 100, 2, 4, 60)]):
+        P = synth.random_profiles(30 + seed, n, m, 1, 25, 1.0)
+        bucket = orc.hash_items(synth.hash_tables(t, 40 + seed), b, m)
+        keys = orc.frh_keys(P.indptr, P.indices, n, m, bucket)
+        a = orc.cluster(P.indptr, P.indices, n, m, bucket, cap)
+        k = orc.cluster_keys(P.indptr, P.indices, n, m, keys, bucket, cap)
+        for x, y in zip(a[:3], k[:3]):
+            assert np.array_equal(x, y)
+
+
+def test_cluster_keys_no_split_groups_by_key(orc):
+    """cap >= n: the clusters are the users grouped by key, ascending."""
+    P = synth.random_profiles(33, 300, 100, 1, 10, 1.0)
+    rng = np.random.Generator(np.random.PCG64(34))
+    keys = rng.integers(0, 40, size=(2, P.n), dtype=np.uint32)
+    bucket = orc.hash_items(synth.hash_tables(2, 35), 16, P.m)
+    mem, off, cfg, depth = orc.cluster_keys(P.indptr, P.indices, P.n, P.m, keys, bucket, P.n)
+    assert depth == 0
+    for j in range(2):
+        got = [mem[off[c]:off[c + 1]].tolist() for c in range(cfg[j], cfg[j + 1])]
+        want = [np.nonzero(keys[j] == v)[0].tolist() for v in np.unique(keys[j])]
+        assert got == want
+
+
+def test_cluster_keys_split_uses_frh_from_the_start(orc):
+    """One key for everybody and cap < n: the result is Step 1 on the same
+    users with a single top-level group, i.e. FRH with b = 1 bucket value
+    spread by the item hash: every final cluster is within cap or is the
+    users that stayed, and it is a partition of all users."""
+    P = synth.random_profiles(36, 400, 300, 2, 30, 1.1)
+    t, cap = 3, 25
+    bucket = orc.hash_items(synth.hash_tables(t, 37), 64, P.m)
+    keys = np.zeros((t, P.n), dtype=np.uint32)
+    mem, off, cfg, depth = orc.cluster_keys(P.indptr, P.indices, P.n, P.m, keys, bucket, cap)
+    assert depth >= 1
+    frh = orc.frh_keys(P.indptr, P.indices, P.n, P.m, bucket)
+    for j in range(t):
+        users = np.sort(mem[j * P.n:(j + 1) * P.n])
+        assert np.array_equal(users, np.arange(P.n))
+        # the first-level sub-clusters follow ascending H_j
+        first = [int(frh[j, mem[off[c]]]) for c in range(cfg[j], cfg[j + 1])]
+        assert first[0] == frh[j].min()
+
+
 # ------------------------------------------------- GoldFinger (II-F) ----
 
 def test_fingerprints_brute_force(orc):
