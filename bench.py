@@ -166,6 +166,71 @@ def goldfinger_variant(args, w, P, dP, c2, metrics, synth, torch, np, bf, B=1024
             "quality_def": "exact similarity of the chosen edges over the exact graph's"}
 
 
+def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_ms, batched_ms):
+    """The learned cluster assigner: trained here on exact KNN edges of a
+    100,000-user subsample, then the learned-assignment build (assignment,
+    clustering from keys with FastRandomHash splits, local KNN, merge) timed in
+    the plain eager form and scored against the exact graph."""
+    from paper_2010_11497_amd import learned
+    b = 8192 if w.n >= 100000 else w.b
+    t0 = time.perf_counter()
+    pairs = learned.exact_pairs(P, 100000, w.k, seed=1)
+    A = learned.Assigner(P.m, w.t, b, seed=2)
+    st = learned.train(A, dP, pairs, steps=args.learned_steps, batch=2048, w_bal=1.0, w_neg=1.0,
+                       w_ent=1.0, lr=3e-3, log=log)
+    train_s = time.perf_counter() - t0
+    W = A.inference_weights()
+    out = None
+    res = {"buckets": b, "train_s": train_s, "train_steps": st.steps, "train_pairs": st.pairs,
+           "loss": [st.first_loss, st.last_loss], "min_gap": {}}
+    for gap in (0.0, 0.5):
+        for _ in range(args.warmup):
+            out = learned.build(A, dP, dtab, p, gap, weights=W)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            out = learned.build(A, dP, dtab, p, gap, weights=W)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        q = None
+        if bf is not None:
+            q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
+                                c2.to_u32(bf[2]))
+        res["min_gap"][str(gap)] = {"build_ms_plain": ms, "quality": q}
+        log("learned assigner (min_gap %.1f): plain build %.3f ms, quality %s" % (gap, ms, q))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        A.keys(dP, None, 0.0, W)
+    torch.cuda.synchronize()
+    res["assign_ms"] = (time.perf_counter() - t1) * 1e3 / args.steps
+    res["frh_build_ms"] = {"plain": plain_ms, "batched": batched_ms}
+    # FastRandomHash's time to the same quality bar: more hash configurations
+    # until the graph reaches quality 0.95 (plain form)
+    if bf is not None:
+        from paper_2010_11497_amd import synth
+        sweep = []
+        for t in (w.t, w.t + 2, w.t + 4, w.t + 8):
+            tab_t = c2.tables_to_device(synth.hash_tables(t, w.hash_seed))
+            p_t = c2.params(t, w.b, w.cap, w.k)
+            out = c2.build(dP, tab_t, p_t, c2.FORM_PLAIN)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                out = c2.build(dP, tab_t, p_t, c2.FORM_PLAIN)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) * 1e3 / args.steps
+            q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
+                                c2.to_u32(bf[2]))
+            sweep.append({"t": t, "build_ms_plain": ms, "quality": q})
+            log("FastRandomHash t=%d: plain build %.3f ms, quality %.4f" % (t, ms, q))
+            if q >= 0.95:
+                break
+        res["frh_t_sweep"] = sweep
+    log("assignment (hidden layer + keys) %.3f ms; training %.1f s" % (res["assign_ms"], train_s))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +243,10 @@ def main():
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the MinHash-clustering (Table 4) and GoldFinger (Table 5) "
                          "variants")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the learned cluster assigner on this workload and time the "
+                         "learned-assignment build beside the FastRandomHash forms")
+    ap.add_argument("--learned-steps", type=int, default=1000)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -281,6 +350,10 @@ def main():
         quality = metrics.quality(out_graph[1], out_graph[2], c2.to_u32(bf[1]), c2.to_u32(bf[2]))
         log("quality %.4f" % quality)
 
+    learned_leg = None
+    if args.learned:
+        learned_leg = learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np,
+                                      bf if quality is not None else None, plain_ms, batched_ms)
     ablation = gold = None
     if not args.no_ablation:
         ablation = minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np,
@@ -311,7 +384,7 @@ def main():
                    "tuning": tuned or "defaults"},
         "build_ms": {"graph": graph_ms, "batched": batched_ms, "plain": plain_ms},
         "quality": quality, "jaccard_evals": E, "clusters": ncl,
-        "minhash_ablation": ablation, "goldfinger": gold,
+        "minhash_ablation": ablation, "goldfinger": gold, "learned": learned_leg,
         "h2d_csr_ms": h2d_ms, "evals_per_s_incl_h2d": E / ((graph_ms + h2d_ms) * 1e-3),
         "local_knn_ms": knn_ms, "local_knn_evals_per_s": E / (knn_ms * 1e-3),
         "roofline": roof,

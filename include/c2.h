@@ -275,7 +275,7 @@ c2_status c2_assign_hidden(const c2_profiles *P, const uint16_t *E, const uint16
  * (device [t][n], values < b, e.g. c2_frh_keys) is not NULL and the gap
  * z(top 1) - z(top 2) of head j is below min_gap.  gap [t][n] (device fp32,
  * may be NULL) receives that gap.  Cluster the keys with p->b >= 2b when the
- * fallback is on (b otherwise).  b: a multiple of 32.  The n x t*b logits are
+ * fallback is on (b otherwise).  b: a multiple of 64.  The n x t*b logits are
  * never written: the argmax runs in the product's epilogue. */
 c2_status c2_assign_keys(const uint16_t *h, uint32_t n, const uint16_t *W2, const float *b2,
                          uint32_t t, uint32_t b, const uint32_t *frh_keys, float min_gap,

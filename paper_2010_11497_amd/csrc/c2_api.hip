@@ -377,7 +377,7 @@ c2_status c2_assign_keys(const uint16_t *h, uint32_t n, const uint16_t *W2, cons
     if (!h || !W2 || !b2 || !keys) return fail(C2_E_ARG, "NULL pointer");
     if (n == 0 || n > 0x7FFFFFFFu) return fail(C2_E_ARG, "n = %u out of range [1, 2^31)", n);
     if (t < 1 || t > 64) return fail(C2_E_ARG, "t = %u out of range [1, 64]", t);
-    if (b < 32 || b % 32 || b > (1u << 23)) return fail(C2_E_ARG, "b = %u: a multiple of 32 in [32, 2^23]", b);
+    if (b < 64 || b % 64 || b > (1u << 23)) return fail(C2_E_ARG, "b = %u: a multiple of 64 in [64, 2^23]", b);
     if ((uint64_t)t * n >= 0xFFFFFFFFull) return fail(C2_E_UNSUPPORTED, "t*n >= 2^32");
     C2_TRY(launch_assign_keys(h, n, W2, b2, t, b, frh_keys, min_gap, keys, gap,
                               (hipStream_t)stream),

@@ -9,7 +9,8 @@
 //   key_j = argmax_{c < b} z_u[j*b + c]      lowest index on ties
 //   gap_j = top-1 minus top-2 logit of head j
 //
-// k_assign_hidden: one wave per user, W1 staged (transposed, fp32) in LDS.
+// k_assign_hidden: one wave per user (8 item rows per gather), W1 staged
+//                  (transposed, fp32) in LDS.
 // k_assign_keys:   the logits as a bf16 MFMA product (32x32x16), buckets as
 //                  the M dimension and users as N, the per-head argmax fused
 //                  into the epilogue, so the n x t*b logits never reach HBM.
@@ -30,26 +31,53 @@ C2_DEV uint16_t f32_to_bf16(float f) {
     return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// Sum of E rows over the items of row u, lane = dimension; returns the count.
-C2_DEV uint32_t bag_sum(const int64_t *indptr, const uint32_t *indices, uint64_t nnz, uint32_t m,
-                        const uint16_t *E, uint32_t u, int lane, float &sum) {
+// Sum of E rows over the items of row u with wide gathers: lane = 8 * g + d8
+// loads dimensions [8*d8, 8*d8+8) of every 8th item (g = 0..7), so one load
+// instruction brings in 8 item rows; the 8 partial sums per dimension are
+// then added across g.
+// Returns the count; lane l receives the sum of dimension l in `sum`.
+C2_DEV uint32_t bag_sum_wide(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                             uint32_t m, const uint16_t *E, uint32_t u, int lane, float &sum) {
     uint64_t a, e;
     row_range(indptr, u, nnz, a, e);
-    float s = 0.f;
+    const int g = lane >> 3, d8 = lane & 7;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (uint64_t c = a; c < e; c += 64) {
         const uint32_t cnt = (uint32_t)(e - c < 64 ? e - c : 64);
-        const uint32_t mine = (uint32_t)lane < cnt ? indices[c + lane] : 0u;
-#pragma unroll 8
-        for (uint32_t q = 0; q < cnt; ++q) {
-            const uint32_t i = __builtin_amdgcn_readlane(mine, q);
-            if (i < m) s += bf16_to_f32(E[(size_t)i * kAsgDim + lane]);
+        const uint32_t mine = (uint32_t)lane < cnt ? indices[c + lane] : 0xFFFFFFFFu;
+#pragma unroll 4
+        for (uint32_t q = 0; q < cnt; q += 8) {
+            const uint32_t i = __shfl(mine, (int)(q + g));
+            if (q + g < cnt && i < m) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(E + (size_t)i * kAsgDim + 8 * d8);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    acc[2 * x] += __uint_as_float(w[x] << 16);
+                    acc[2 * x + 1] += __uint_as_float(w[x] & 0xFFFF0000u);
+                }
+            }
         }
     }
-    sum = s;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        acc[x] += __shfl_xor(acc[x], 8);
+        acc[x] += __shfl_xor(acc[x], 16);
+        acc[x] += __shfl_xor(acc[x], 32);
+    }
+    // lane l wants dimension l = 8 * d8' + x': held (after the reduction) by
+    // every lane with d8 == l / 8, in acc[l % 8]
+    float r = 0.f;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const float y = __shfl(acc[x], lane >> 3);
+        r = (lane & 7) == x ? y : r;
+    }
+    sum = r;
     return (uint32_t)(e - a);
 }
 
-constexpr int kHidWaves = 4;
+constexpr int kHidWaves = 8;
 
 __global__ __launch_bounds__(64 * kHidWaves) void k_assign_hidden(
     const int64_t *__restrict__ indptr, const uint32_t *__restrict__ indices, uint64_t nnz,
@@ -67,7 +95,7 @@ __global__ __launch_bounds__(64 * kHidWaves) void k_assign_hidden(
     for (int q = 0; q < 4; ++q) bias[q] = b1[lane + 64 * q];
     for (uint32_t u = blockIdx.x * kHidWaves + wid; u < n; u += gridDim.x * kHidWaves) {
         float s;
-        const uint32_t len = bag_sum(indptr, indices, nnz, m, E, u, lane, s);
+        const uint32_t len = bag_sum_wide(indptr, indices, nnz, m, E, u, lane, s);
         const float eu = bf16_to_f32(f32_to_bf16(len ? s / (float)len : 0.f));
         float acc[4] = {bias[0], bias[1], bias[2], bias[3]};
 #pragma unroll 16
@@ -86,9 +114,11 @@ __global__ __launch_bounds__(64 * kHidWaves) void k_assign_hidden(
 
 constexpr int kKeyWaves = 8;
 constexpr int kKeyUsers = 64 * kKeyWaves;  // 64 users (two 32-column blocks) per wave
-constexpr int kTileB = 32;                 // buckets per tile (one MFMA row block)
+constexpr int kTileB = 64;                 // buckets per tile (two MFMA row blocks)
 constexpr int kRowPad = kAsgHidden + 8;    // bf16 per LDS row (breaks bank aliasing)
 constexpr int kSteps = kAsgHidden / 16;    // MFMA k-steps per tile
+constexpr int kTileChunks = kTileB * kAsgHidden / 8;             // 16-byte chunks per tile
+constexpr int kChunksPerThread = kTileChunks / (64 * kKeyWaves);  // 4
 
 struct Best {
     float v1, v2;
@@ -102,13 +132,20 @@ C2_DEV void best_reset(Best &b) {
 }
 
 // buckets arrive in ascending order per lane: strict '>' keeps the lowest
+template <bool kSecond>
 C2_DEV void best_push(Best &b, float v, uint32_t c) {
-    if (v > b.v1) {
-        b.v2 = b.v1;
-        b.v1 = v;
-        b.idx = c;
-    } else if (v > b.v2) {
-        b.v2 = v;
+    if constexpr (kSecond) {
+        if (v > b.v1) {
+            b.v2 = b.v1;
+            b.v1 = v;
+            b.idx = c;
+        } else if (v > b.v2) {
+            b.v2 = v;
+        }
+    } else {
+        const bool gt = v > b.v1;
+        b.v1 = gt ? v : b.v1;
+        b.idx = gt ? c : b.idx;
     }
 }
 
@@ -128,6 +165,8 @@ C2_DEV void best_combine(Best &b) {
     }
 }
 
+// kSecond: also track the runner-up (for the gap output or the fallback)
+template <bool kSecond>
 __global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
     const uint16_t *__restrict__ h, uint32_t n, const uint16_t *__restrict__ W2,
     const float *__restrict__ b2, uint32_t t, uint32_t b, const uint32_t *__restrict__ frh,
@@ -154,26 +193,26 @@ __global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
 
     const uint32_t tiles_per_head = b / kTileB;
     const uint32_t ntiles = t * tiles_per_head;
-    // cooperative tile load: 32 rows x 512 B = 1024 chunks of 16 B, two per thread
-    auto load_tile = [&](uint32_t T, uint4 (&r)[2], float &bias) {
+    // cooperative tile load: 64 rows x 512 B in 16-byte chunks
+    auto load_tile = [&](uint32_t T, uint4 (&r)[kChunksPerThread], float &bias) {
         const size_t row0 = (size_t)T * kTileB;
 #pragma unroll
-        for (int z = 0; z < 2; ++z) {
+        for (int z = 0; z < kChunksPerThread; ++z) {
             const uint32_t q = threadIdx.x + 64 * kKeyWaves * z;
             r[z] = *reinterpret_cast<const uint4 *>(W2 + (row0 + q / 32) * kAsgHidden + (q % 32) * 8);
         }
         bias = threadIdx.x < kTileB ? b2[row0 + threadIdx.x] : 0.f;
     };
-    auto store_tile = [&](int buf, const uint4 (&r)[2], float bias) {
+    auto store_tile = [&](int buf, const uint4 (&r)[kChunksPerThread], float bias) {
 #pragma unroll
-        for (int z = 0; z < 2; ++z) {
+        for (int z = 0; z < kChunksPerThread; ++z) {
             const uint32_t q = threadIdx.x + 64 * kKeyWaves * z;
             *reinterpret_cast<uint4 *>(&wt[buf][(q / 32) * kRowPad + (q % 32) * 8]) = r[z];
         }
         if (threadIdx.x < kTileB) bt[buf][threadIdx.x] = bias;
     };
 
-    uint4 pre[2];
+    uint4 pre[kChunksPerThread];
     float pbias;
     load_tile(0, pre, pbias);
     store_tile(0, pre, pbias);
@@ -185,23 +224,36 @@ __global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
     for (uint32_t T = 0; T < ntiles; ++T) {
         const int buf = T & 1;
         if (T + 1 < ntiles) load_tile(T + 1, pre, pbias);
-        f32x16 acc[2] = {};
-        const uint16_t *arow = &wt[buf][col * kRowPad + 8 * half];
+        // accumulators start at the bias of their bucket row
+        f32x16 acc[2][2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float bias = bt[buf][32 * rb + 8 * (r / 4) + 4 * half + (r % 4)];
+                acc[rb][0][r] = bias;
+                acc[rb][1][r] = bias;
+            }
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) {
-            const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(arow + 16 * s));
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[0][s], acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[1][s], acc[1], 0, 0, 0);
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const bf16x8 a = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(
+                                &wt[buf][(32 * rb + col) * kRowPad + 8 * half + 16 * s]));
+                acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[0][s], acc[rb][0], 0, 0, 0);
+                acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[1][s], acc[rb][1], 0, 0, 0);
+            }
         }
         const uint32_t tin = T % tiles_per_head;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r / 4) + 4 * half + (r % 4);
-            const float bias = bt[buf][row];
-            const uint32_t c = tin * kTileB + row;
-            best_push(best[0], acc[0][r] + bias, c);
-            best_push(best[1], acc[1][r] + bias, c);
-        }
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t c = tin * kTileB + 32 * rb + 8 * (r / 4) + 4 * half + (r % 4);
+                best_push<kSecond>(best[0], acc[rb][0][r], c);
+                best_push<kSecond>(best[1], acc[rb][1][r], c);
+            }
         if (tin == tiles_per_head - 1) {
             const uint32_t j = T / tiles_per_head;
 #pragma unroll
@@ -209,11 +261,13 @@ __global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
                 best_combine(best[c]);
                 const uint32_t u = ubase + c * 32 + col;
                 if (half == 0 && u < n) {
-                    const float g = best[c].v1 - best[c].v2;
                     uint32_t key = best[c].idx;
-                    if (frh && g < min_gap) key = b + frh[(size_t)j * n + u];
+                    if constexpr (kSecond) {
+                        const float g = best[c].v1 - best[c].v2;
+                        if (frh && g < min_gap) key = b + frh[(size_t)j * n + u];
+                        if (gap) gap[(size_t)j * n + u] = g;
+                    }
                     keys[(size_t)j * n + u] = key;
-                    if (gap) gap[(size_t)j * n + u] = g;
                 }
                 best_reset(best[c]);
             }
@@ -238,7 +292,7 @@ __global__ __launch_bounds__(256) void k_embag_fwd(const int64_t *__restrict__ i
     const uint32_t u = rows ? rows[r] : r;
     float s = 0.f;
     uint32_t len = 0;
-    if (u < n) len = bag_sum(indptr, indices, nnz, m, E, u, lane, s);
+    if (u < n) len = bag_sum_wide(indptr, indices, nnz, m, E, u, lane, s);
     out[(size_t)r * kAsgDim + lane] = len ? s / (float)len : 0.f;
 }
 
@@ -269,7 +323,7 @@ hipError_t launch_assign_hidden(const int64_t *indptr, const uint32_t *indices, 
                                 uint32_t n, uint32_t m, const uint16_t *E, const uint16_t *W1,
                                 const float *b1, uint16_t *h, hipStream_t s) {
     uint32_t blocks = (uint32_t)div_up(n, kHidWaves);
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_assign_hidden, dim3(blocks), dim3(64 * kHidWaves), 0, s, indptr, indices,
                        nnz, n, m, E, W1, b1, h);
     return hipGetLastError();
@@ -278,8 +332,13 @@ hipError_t launch_assign_hidden(const int64_t *indptr, const uint32_t *indices, 
 hipError_t launch_assign_keys(const uint16_t *h, uint32_t n, const uint16_t *W2, const float *b2,
                               uint32_t t, uint32_t b, const uint32_t *frh, float min_gap,
                               uint32_t *keys, float *gap, hipStream_t s) {
-    hipLaunchKernelGGL(k_assign_keys, dim3((uint32_t)div_up(n, kKeyUsers)), dim3(64 * kKeyWaves),
-                       0, s, h, n, W2, b2, t, b, frh, min_gap, keys, gap);
+    const dim3 grid((uint32_t)div_up(n, kKeyUsers)), block(64 * kKeyWaves);
+    if (frh || gap)
+        hipLaunchKernelGGL(k_assign_keys<true>, grid, block, 0, s, h, n, W2, b2, t, b, frh,
+                           min_gap, keys, gap);
+    else
+        hipLaunchKernelGGL(k_assign_keys<false>, grid, block, 0, s, h, n, W2, b2, t, b, frh,
+                           min_gap, keys, gap);
     return hipGetLastError();
 }
 

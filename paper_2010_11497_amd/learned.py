@@ -16,6 +16,7 @@ p_j(u) = softmax(z_u[j*b:(j+1)*b]) the loss is
     - log sum_c p_j(u,c) p_j(v,c)                 (collide with neighbours)
     - w_neg * log(1 - sum_c p_j(u,c) p_j(w,c))    (w: in-batch non-neighbour)
     + w_bal * KL(mean_u p_j(u) || uniform)        (use all buckets)
+    + w_ent * H(p_j(u))                           (be confident)
 averaged over heads and pairs.  The embedding bag runs through the library's
 HIP kernels (c2_embag, c2_embag_backward); the two dense layers and the
 softmax go through torch.  Weights are fp32 masters updated by Adam; the
@@ -100,8 +101,8 @@ def exact_pairs(P, n_sub: int, k: int, seed: int = 0):
 
 
 def train(A: Assigner, P: c2.DeviceProfiles, pairs: np.ndarray, steps: int = 400,
-          batch: int = 1024, lr: float = 3e-3, w_neg: float = 1.0, w_bal: float = 0.1,
-          seed: int = 0, log=None) -> TrainStats:
+          batch: int = 1024, lr: float = 3e-3, w_neg: float = 1.0, w_bal: float = 3.0,
+          w_ent: float = 1.0, seed: int = 0, log=None) -> TrainStats:
     dev = P.device
     pairs_d = torch.from_numpy(pairs.astype(np.int32)).to(dev)
     opt = torch.optim.Adam(A.params(), lr=lr)
@@ -118,12 +119,14 @@ def train(A: Assigner, P: c2.DeviceProfiles, pairs: np.ndarray, steps: int = 400
         h = torch.relu(e @ A.W1.t() + A.b1)
         z = (h @ A.W2.t() + A.b2).view(2 * batch, t, b)
         p = torch.softmax(z, dim=-1)
+        ent = -(p * torch.log_softmax(z, dim=-1)).sum(-1).mean()
         pu, pv = p[:batch], p[batch:]
         pos = (pu * pv).sum(-1).clamp_min(1e-12)
         neg = (pu * pv.roll(1, dims=0)).sum(-1).clamp(0.0, 1.0 - 1e-6)
         q = p.mean(0)
         bal = (q * torch.log(q * b + 1e-12)).sum(-1).mean()
-        loss = -torch.log(pos).mean() - w_neg * torch.log1p(-neg).mean() + w_bal * bal
+        loss = (-torch.log(pos).mean() - w_neg * torch.log1p(-neg).mean() + w_bal * bal
+                + w_ent * ent)
         opt.zero_grad(set_to_none=True)
         loss.backward()
         dE = torch.zeros_like(A.E)
@@ -133,9 +136,10 @@ def train(A: Assigner, P: c2.DeviceProfiles, pairs: np.ndarray, steps: int = 400
         if step == 0:
             first = float(loss.detach())
         if log and (step % 100 == 0 or step == steps - 1):
-            log("train step %d loss %.4f (pos %.4f neg %.4f bal %.4f)"
-                % (step, float(loss), float(-torch.log(pos).mean()),
-                   float(-torch.log1p(-neg).mean()), float(bal)))
+            log("train step %d loss %.4f (pos %.4f neg %.4f bal %.4f ent %.4f)"
+                % (step, float(loss.detach()), float(-torch.log(pos).mean().detach()),
+                   float(-torch.log1p(-neg).mean().detach()), float(bal.detach()),
+                   float(ent.detach())))
     last = float(loss.detach())
     torch.cuda.synchronize()
     return TrainStats(steps, time.perf_counter() - t0, int(pairs.shape[0]), first, last)

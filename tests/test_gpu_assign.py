@@ -87,7 +87,7 @@ def check_keys(A, hb, W2, b2, t, b, keys, gap):
     return exact / (t * n), wgap
 
 
-@pytest.mark.parametrize("n,t,b", [(1, 2, 32), (513, 3, 1024), (1500, 8, 256), (100, 1, 8192)])
+@pytest.mark.parametrize("n,t,b", [(1, 2, 64), (513, 3, 1024), (1500, 8, 256), (100, 1, 8192)])
 def test_assign_keys(A, n, t, b):
     say("assign keys", n, t, b)
     hb = synth.hidden_inputs(n, 9200 + n)
