@@ -112,6 +112,7 @@ typedef struct c2_tuning {
 #define C2_OP_BUILD 3
 #define C2_OP_BRUTE_FORCE 4
 #define C2_OP_FINGERPRINT 5
+#define C2_OP_LOCAL_KNN_ALG2 6
 
 /* Message for the last non-OK status returned on this thread (host string,
  * valid until the next call on this thread). */
@@ -207,6 +208,34 @@ c2_status c2_local_knn(const c2_profiles *P, const uint32_t *members, const uint
                        const uint32_t *cl_cfg_off, const c2_params *p, int form,
                        const c2_tuning *tune, uint32_t *part_id, uint32_t *part_I,
                        void *ws, size_t ws_bytes, void *stream);
+
+/* Parameters of Algorithm 2's Hyrec branch (Section II-F; Hyrec, delta and the
+ * iteration cap in Section IV-B and IV-C; rho = 5 in Section II-F). */
+typedef struct c2_hyrec {
+    uint32_t rho;       /* clusters of at least rho*k^2 members take Hyrec */
+    uint32_t max_iter;  /* iterations at most (30 in the paper) */
+    double delta;       /* stop when fewer than delta*k*|C| entries changed (0.001) */
+    uint64_t seed;      /* seed of the initial random graph */
+} c2_hyrec;
+
+/* Step 2 as Algorithm 2: c2_local_knn (brute force) in clusters of fewer than
+ * rho*k^2 members, Hyrec in the others.  The paper does not fix Hyrec's
+ * random choices; this form is deterministic: member a's initial list is the
+ * k best distinct of k uniform draws among the cluster's other members, draw
+ * q being SplitMix64 output number c + 1 from state `seed`, c = (cluster <<
+ * 40) | (a << 12) | q (cluster = index in cl_off, a = position in the
+ * cluster), reduced mod (|C| - 1) and shifted past a.  Each iteration then
+ * replaces, for all members at once, a's list by the k best distinct of its
+ * list and its neighbours' lists (a excluded), in the exact order.  It stops
+ * after an iteration that changed fewer than delta*k*|C| list entries, or
+ * after max_iter iterations.  Plain form only (synchronous: it reads the
+ * partition and the update counts on the host).  C2_E_UNSUPPORTED if a Hyrec
+ * cluster is needed and some profile holds 2^15 items or more.  Outputs as
+ * c2_local_knn.  ws: C2_OP_LOCAL_KNN_ALG2 bytes. */
+c2_status c2_local_knn_alg2(const c2_profiles *P, const uint32_t *members, const uint32_t *cl_off,
+                            const uint32_t *cl_cfg_off, const c2_params *p, const c2_hyrec *hy,
+                            const c2_tuning *tune, uint32_t *part_id, uint32_t *part_I, void *ws,
+                            size_t ws_bytes, void *stream);
 
 /* Step 3 (Section II-G, Algorithm 3): knn(u) = the k best entries of the union
  * of u's t partial lists (part_* as written by c2_local_knn), each neighbour

@@ -307,6 +307,11 @@ typedef struct {
     pthread_mutex_t mu;
     uint32_t *part_id, *part_I;
     uint32_t m;
+    /* Algorithm 2: clusters of at least rho*k^2 members take Hyrec */
+    int alg2;
+    uint32_t rho, max_iter;
+    double delta;
+    uint64_t seed;
 } lknn_ctx;
 
 static uint32_t cfg_of_cluster(const lknn_ctx *c, uint32_t cl)
@@ -363,6 +368,109 @@ static void local_cluster(lknn_ctx *c, uint32_t cl, uint8_t *mark,
     }
 }
 
+/* ------------------------------------------- Hyrec branch (Algorithm 2) -- */
+
+/* SplitMix64 (Steele, Lea and Flood, 2014): the (c+1)-th output of the
+ * generator whose state starts at `seed`; the state advances by the golden
+ * gamma and each output is the state passed through the published mixer. */
+static uint64_t splitmix_at(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * (c + 1);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_splitmix_at(uint64_t seed, uint64_t c) { return splitmix_at(seed, c); }
+
+/* Sort candidates (v = member position; positions follow ids), keep each
+ * position once, return the k best in out (count through *nout). */
+static void topk_distinct(cand_t *cand, uint32_t nc, uint32_t k, cand_t *out,
+                          uint32_t *nout)
+{
+    qsort(cand, nc, sizeof(cand_t), cand_cmp);
+    uint32_t o = 0;
+    for (uint32_t q = 0; q < nc && o < k; ++q) {
+        if (o > 0 && cand[q].v == out[o - 1].v) continue;
+        out[o++] = cand[q];
+    }
+    *nout = o;
+}
+
+/* Hyrec on one cluster, deterministic form: the initial graph gives member a
+ * the k best of k uniform draws among the other members (SplitMix64 counter
+ * (cluster << 40) | (a << 12) | q); then, synchronously, every member's new
+ * list is the k best of its list and its neighbours' lists (Section IV-B:
+ * neighbours' neighbours), until fewer than delta*k*s list entries changed in
+ * an iteration or max_iter iterations ran. */
+static void hyrec_cluster(lknn_ctx *c, uint32_t cl, uint8_t *mark)
+{
+    const uint32_t j = cfg_of_cluster(c, cl), k = c->k;
+    const uint32_t *S = c->members + c->cl_off[cl];
+    const uint32_t s = c->cl_off[cl + 1] - c->cl_off[cl];
+    cand_t *cur = (cand_t *)malloc((size_t)s * k * sizeof(cand_t));
+    cand_t *nxt = (cand_t *)malloc((size_t)s * k * sizeof(cand_t));
+    uint32_t *ncur = (uint32_t *)calloc(s, sizeof(uint32_t));
+    uint32_t *nnxt = (uint32_t *)calloc(s, sizeof(uint32_t));
+    cand_t *cand = (cand_t *)malloc((size_t)(k + k * k) * sizeof(cand_t));
+    for (uint32_t a = 0; a < s; ++a) {
+        const uint32_t u = S[a], Lu = plen(c->indptr, u);
+        for (int64_t p = c->indptr[u]; p < c->indptr[u + 1]; ++p) mark[c->indices[p]] = 1;
+        uint32_t nc = 0;
+        for (uint32_t q = 0; q < k; ++q) {
+            uint64_t r = splitmix_at(c->seed, ((uint64_t)cl << 40) | ((uint64_t)a << 12) | q);
+            uint32_t b = (uint32_t)(r % (s - 1));
+            if (b >= a) ++b;
+            uint32_t I = inter_marked(c, mark, S[b]);
+            cand[nc].v = b; cand[nc].I = I; cand[nc].U = Lu + plen(c->indptr, S[b]) - I;
+            ++nc;
+        }
+        for (int64_t p = c->indptr[u]; p < c->indptr[u + 1]; ++p) mark[c->indices[p]] = 0;
+        topk_distinct(cand, nc, k, cur + (size_t)a * k, &ncur[a]);
+    }
+    for (uint32_t it = 0; it < c->max_iter; ++it) {
+        uint64_t updates = 0;
+        for (uint32_t a = 0; a < s; ++a) {
+            const uint32_t u = S[a], Lu = plen(c->indptr, u);
+            for (int64_t p = c->indptr[u]; p < c->indptr[u + 1]; ++p) mark[c->indices[p]] = 1;
+            uint32_t nc = 0;
+            const cand_t *la = cur + (size_t)a * k;
+            for (uint32_t q = 0; q < ncur[a]; ++q) {
+                cand[nc++] = la[q];
+                const cand_t *lb = cur + (size_t)la[q].v * k;
+                for (uint32_t r = 0; r < ncur[la[q].v]; ++r) {
+                    const uint32_t b = lb[r].v;
+                    if (b == a) continue;
+                    uint32_t I = inter_marked(c, mark, S[b]);
+                    cand[nc].v = b; cand[nc].I = I; cand[nc].U = Lu + plen(c->indptr, S[b]) - I;
+                    ++nc;
+                }
+            }
+            for (int64_t p = c->indptr[u]; p < c->indptr[u + 1]; ++p) mark[c->indices[p]] = 0;
+            cand_t *na = nxt + (size_t)a * k;
+            topk_distinct(cand, nc, k, na, &nnxt[a]);
+            for (uint32_t q = 0; q < nnxt[a]; ++q) {
+                int found = 0;
+                for (uint32_t r = 0; r < ncur[a] && !found; ++r) found = la[r].v == na[q].v;
+                updates += !found;
+            }
+        }
+        cand_t *tc = cur; cur = nxt; nxt = tc;
+        uint32_t *tn = ncur; ncur = nnxt; nnxt = tn;
+        if ((double)updates < c->delta * (double)k * (double)s) break;
+    }
+    for (uint32_t a = 0; a < s; ++a) {
+        const uint32_t u = S[a];
+        uint32_t *oid = c->part_id + ((size_t)u * c->t + j) * k;
+        uint32_t *oI = c->part_I + ((size_t)u * c->t + j) * k;
+        for (uint32_t q = 0; q < k; ++q) {
+            oid[q] = q < ncur[a] ? S[cur[(size_t)a * k + q].v] : ORC_PAD;
+            oI[q] = q < ncur[a] ? cur[(size_t)a * k + q].I : 0;
+        }
+    }
+    free(cand); free(nnxt); free(ncur); free(nxt); free(cur);
+}
+
 static void *lknn_worker(void *arg)
 {
     lknn_ctx *c = (lknn_ctx *)arg;
@@ -378,7 +486,12 @@ static void *lknn_worker(void *arg)
         uint32_t q = c->next++;
         pthread_mutex_unlock(&c->mu);
         if (q >= c->ncl) break;
-        local_cluster(c, c->order[q], mark, cand);
+        const uint32_t cl = c->order[q];
+        const uint32_t s = c->cl_off[cl + 1] - c->cl_off[cl];
+        if (c->alg2 && s >= 2 && (uint64_t)s >= (uint64_t)c->rho * c->k * c->k)
+            hyrec_cluster(c, cl, mark);
+        else
+            local_cluster(c, cl, mark, cand);
     }
     free(cand);
     free(mark);
@@ -398,14 +511,16 @@ static int by_size_desc(const void *pa, const void *pb)
 /* Step 2: partial KNN of every cluster.  part_id/part_I are [n][t][k]; slot
  * (u, j) holds u's k best co-members in its configuration-j cluster, best
  * first, padded with (0xFFFFFFFF, 0). */
-void orc_local_knn(uint32_t n, uint32_t m, const int64_t *indptr,
-                   const uint32_t *indices, uint32_t t, uint32_t k,
-                   const uint32_t *members, const uint32_t *cl_off,
-                   const uint32_t *cl_cfg_off, uint32_t *part_id,
-                   uint32_t *part_I, int nthreads)
+static void local_knn_impl(uint32_t n, uint32_t m, const int64_t *indptr,
+                           const uint32_t *indices, uint32_t t, uint32_t k,
+                           const uint32_t *members, const uint32_t *cl_off,
+                           const uint32_t *cl_cfg_off, uint32_t *part_id,
+                           uint32_t *part_I, int nthreads, int alg2, uint32_t rho,
+                           double delta, uint32_t max_iter, uint64_t seed)
 {
     lknn_ctx c;
     memset(&c, 0, sizeof(c));
+    c.alg2 = alg2; c.rho = rho; c.delta = delta; c.max_iter = max_iter; c.seed = seed;
     c.n = n; c.t = t; c.k = k; c.m = m;
     c.indptr = indptr; c.indices = indices;
     c.members = members; c.cl_off = cl_off; c.cl_cfg_off = cl_cfg_off;
@@ -424,6 +539,29 @@ void orc_local_knn(uint32_t n, uint32_t m, const int64_t *indptr,
     pthread_mutex_destroy(&c.mu);
     free(th);
     free(order);
+}
+
+void orc_local_knn(uint32_t n, uint32_t m, const int64_t *indptr,
+                   const uint32_t *indices, uint32_t t, uint32_t k,
+                   const uint32_t *members, const uint32_t *cl_off,
+                   const uint32_t *cl_cfg_off, uint32_t *part_id,
+                   uint32_t *part_I, int nthreads)
+{
+    local_knn_impl(n, m, indptr, indices, t, k, members, cl_off, cl_cfg_off,
+                   part_id, part_I, nthreads, 0, 0, 0.0, 0, 0);
+}
+
+/* Algorithm 2: brute force in clusters of fewer than rho*k^2 members, Hyrec
+ * (hyrec_cluster) in the others. */
+void orc_local_knn_alg2(uint32_t n, uint32_t m, const int64_t *indptr,
+                        const uint32_t *indices, uint32_t t, uint32_t k,
+                        const uint32_t *members, const uint32_t *cl_off,
+                        const uint32_t *cl_cfg_off, uint32_t rho, double delta,
+                        uint32_t max_iter, uint64_t seed, uint32_t *part_id,
+                        uint32_t *part_I, int nthreads)
+{
+    local_knn_impl(n, m, indptr, indices, t, k, members, cl_off, cl_cfg_off,
+                   part_id, part_I, nthreads, 1, rho, delta, max_iter, seed);
 }
 
 /* ---------------------------------------------------------- merge (Alg.3) -- */

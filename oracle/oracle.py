@@ -53,6 +53,10 @@ def lib():
         L.orc_cluster_keys.argtypes = [u32, u32, P, P, P, P, u32, u32, P, P, P]
         L.orc_cluster_keys.restype = i32
         L.orc_local_knn.argtypes = [u32, u32, P, P, u32, u32, P, P, P, P, P, i32]
+        L.orc_splitmix_at.argtypes = [u64, u64]
+        L.orc_splitmix_at.restype = u64
+        L.orc_local_knn_alg2.argtypes = [u32, u32, P, P, u32, u32, P, P, P, u32,
+                                         ctypes.c_double, u32, u64, P, P, i32]
         L.orc_merge.argtypes = [u32, P, u32, u32, P, P, P, P, P]
         L.orc_brute_force.argtypes = [u32, u32, P, P, u32, P, u32, P, P, P, i32]
         L.orc_candidate_topk.argtypes = [u32, u32, P, P, u32, u32, P, P, P, P, u32,
@@ -137,6 +141,20 @@ def local_knn(indptr, indices, n, m, t, k, members, cl_off, cl_cfg_off, threads=
     pI = np.empty((n, t, k), dtype=np.uint32)
     lib().orc_local_knn(n, m, _p(ip), _p(ix), t, k, _p(mem), _p(off), _p(cfg),
                         _p(pid), _p(pI), int(threads))
+    return pid, pI
+
+
+def local_knn_alg2(indptr, indices, n, m, t, k, members, cl_off, cl_cfg_off, rho=5,
+                   delta=0.001, max_iter=30, seed=0, threads=1):
+    """Step 2 as Algorithm 2: brute force in clusters of fewer than rho*k^2
+    members, deterministic Hyrec (seeded SplitMix64 initial graph, synchronous
+    neighbours-of-neighbours iterations) in the others."""
+    ip, ix = _c(indptr, np.int64), _c(indices, np.uint32)
+    mem, off, cfg = _c(members, np.uint32), _c(cl_off, np.uint32), _c(cl_cfg_off, np.uint32)
+    pid = np.empty((n, t, k), dtype=np.uint32)
+    pI = np.empty((n, t, k), dtype=np.uint32)
+    lib().orc_local_knn_alg2(n, m, _p(ip), _p(ix), t, k, _p(mem), _p(off), _p(cfg), int(rho),
+                             float(delta), int(max_iter), int(seed), _p(pid), _p(pI), int(threads))
     return pid, pI
 
 

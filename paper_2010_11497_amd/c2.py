@@ -24,11 +24,13 @@ C2_OK = 0
 C2_PAD = 0xFFFFFFFF
 FORM_PLAIN = 0
 FORM_BATCHED = 1
-OP_VALIDATE, OP_CLUSTER, OP_LOCAL_KNN, OP_BUILD, OP_BRUTE_FORCE, OP_FINGERPRINT = range(6)
+(OP_VALIDATE, OP_CLUSTER, OP_LOCAL_KNN, OP_BUILD, OP_BRUTE_FORCE, OP_FINGERPRINT,
+ OP_LOCAL_KNN_ALG2) = range(7)
 
 # every entry point of include/c2.h
 SYMBOLS = ["c2_last_error", "c2_workspace_bytes", "c2_validate", "c2_hash_items", "c2_frh_keys",
-           "c2_cluster", "c2_cluster_keys", "c2_check_complete", "c2_local_knn", "c2_merge", "c2_build",
+           "c2_cluster", "c2_cluster_keys", "c2_check_complete", "c2_local_knn",
+           "c2_local_knn_alg2", "c2_merge", "c2_build",
            "c2_brute_force", "c2_fingerprint", "c2_assign_hidden", "c2_assign_keys",
            "c2_embag", "c2_embag_backward", "c2_graph_create", "c2_graph_launch",
            "c2_graph_destroy"]
@@ -49,6 +51,11 @@ class Profiles(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("t", ctypes.c_uint32), ("b", ctypes.c_uint32), ("cap", ctypes.c_uint32),
                 ("k", ctypes.c_uint32)]
+
+
+class Hyrec(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_uint32), ("max_iter", ctypes.c_uint32),
+                ("delta", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class Tuning(ctypes.Structure):
@@ -83,6 +90,7 @@ def load(path: str = LIB_PATH):
     L.c2_cluster_keys.argtypes = [PP, P, P, PA, i32, PT, P, P, P, P, sz, P]
     L.c2_check_complete.argtypes = [P, P]
     L.c2_local_knn.argtypes = [PP, P, P, P, PA, i32, PT, P, P, P, sz, P]
+    L.c2_local_knn_alg2.argtypes = [PP, P, P, P, PA, ctypes.POINTER(Hyrec), PT, P, P, P, sz, P]
     L.c2_merge.argtypes = [PP, P, P, PA, P, P, P, P]
     L.c2_build.argtypes = [PP, P, PA, i32, PT, P, P, P, P, sz, P]
     L.c2_brute_force.argtypes = [PP, u32, P, P, P, P, sz, P]
@@ -251,6 +259,22 @@ def local_knn(P: DeviceProfiles, members, cl_off, cl_cfg_off, p: Params, form=FO
     _check(load().c2_local_knn(ctypes.byref(P.c), _ptr(members), _ptr(cl_off), _ptr(cl_cfg_off),
                                ctypes.byref(p), form, ctypes.byref(tune) if tune else None,
                                _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def local_knn_alg2(P: DeviceProfiles, members, cl_off, cl_cfg_off, p: Params, rho=5,
+                   max_iter=30, delta=0.001, seed=0, tune: Optional[Tuning] = None, ws=None,
+                   out=None):
+    """Algorithm 2: brute force below rho*k^2 members, deterministic Hyrec at or
+    above (synchronous).  Returns (part_id, part_I) as local_knn()."""
+    if out is None:
+        out = (_u32((P.n, p.t, p.k), P.device), _u32((P.n, p.t, p.k), P.device))
+    ws = workspace(P, p, OP_LOCAL_KNN_ALG2) if ws is None else ws
+    hy = Hyrec(int(rho), int(max_iter), float(delta), int(seed))
+    _check(load().c2_local_knn_alg2(ctypes.byref(P.c), _ptr(members), _ptr(cl_off),
+                                    _ptr(cl_cfg_off), ctypes.byref(p), ctypes.byref(hy),
+                                    ctypes.byref(tune) if tune else None, _ptr(out[0]),
+                                    _ptr(out[1]), _ptr(ws), ws.numel(), _stream()))
     return out
 
 

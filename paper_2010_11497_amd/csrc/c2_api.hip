@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/c2.h"
 #include "c2_internal.h"
@@ -158,6 +159,30 @@ KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
     return k;
 }
 
+// Workspace of c2_local_knn_alg2: the local-KNN scratch (whose bit rows the
+// Hyrec kernels read), the rewritten partition, and Hyrec's double-buffered
+// lists over the largest possible cluster.
+struct Alg2Layout {
+    size_t knn, cl_off, cfg, keyA, keyB, IA, IB, upd, total;
+};
+
+Alg2Layout alg2_layout(uint32_t n, uint32_t m, const c2_params *p) {
+    Alg2Layout L;
+    size_t off = kHeader;
+    auto take = [&](size_t b) { size_t o = off; off += al(b); return o; };
+    const size_t NE = (size_t)p->t * n;
+    L.knn = take(knn_ws_bytes(n, (uint32_t)NE, knn_wmax(m), nullptr));
+    L.cl_off = take(4 * (NE + 1));
+    L.cfg = take(4 * ((size_t)p->t + 1));
+    L.keyA = take(8 * (size_t)n * p->k);
+    L.keyB = take(8 * (size_t)n * p->k);
+    L.IA = take(4 * (size_t)n * p->k);
+    L.IB = take(4 * (size_t)n * p->k);
+    L.upd = take(256);
+    L.total = off;
+    return L;
+}
+
 uint32_t rounds_from(const c2_tuning *tune) {
     uint32_t r = tune && tune->split_rounds ? tune->split_rounds : 8;
     return r > kMaxRounds ? kMaxRounds : r;
@@ -298,6 +323,9 @@ size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params 
                             2 * al(4 * (size_t)n * one.k);
         return head + knn_ws_bytes(n, n, knn_wmax(m), nullptr);
     }
+    case C2_OP_LOCAL_KNN_ALG2:
+        if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
+        return alg2_layout(n, m, p).total;
     case C2_OP_FINGERPRINT:
         if (check_sizes(n, m, nnz, nullptr, false) != C2_OK) return 0;
         if (!p || p->b < 1 || p->b > kFpMaxBits) {
@@ -488,6 +516,113 @@ c2_status c2_local_knn(const c2_profiles *P, const uint32_t *members, const uint
         return st;
     return run_knn(P, members, cl_off, cl_cfg_off, p->t, p->k, form, tune, part_id, part_I,
                    reinterpret_cast<char *>(ws) + kHeader, (hipStream_t)stream);
+}
+
+c2_status c2_local_knn_alg2(const c2_profiles *P, const uint32_t *members, const uint32_t *cl_off,
+                            const uint32_t *cl_cfg_off, const c2_params *p, const c2_hyrec *hy,
+                            const c2_tuning *tune, uint32_t *part_id, uint32_t *part_I, void *ws,
+                            size_t ws_bytes, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
+    if (!members || !cl_off || !cl_cfg_off || !part_id || !part_I || !hy)
+        return fail(C2_E_ARG, "NULL pointer");
+    if (hy->rho < 1) return fail(C2_E_ARG, "rho must be >= 1");
+    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_LOCAL_KNN_ALG2))) != C2_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = reinterpret_cast<char *>(ws);
+    const Alg2Layout L = alg2_layout(P->n, P->m, p);
+    const uint32_t t = p->t, k = p->k, n = P->n;
+    const uint64_t NE = (uint64_t)t * n;
+    // the partition on the host: which clusters take Hyrec
+    std::vector<uint32_t> cfg(t + 1);
+    C2_TRY(hipMemcpyAsync(cfg.data(), cl_cfg_off, 4 * (t + 1), hipMemcpyDeviceToHost, s), "copy");
+    C2_TRY(hipStreamSynchronize(s), "sync");
+    const uint32_t ncl = cfg[t];
+    if (ncl < 1 || ncl > NE) return fail(C2_E_ARG, "cl_cfg_off[t] = %u out of range", ncl);
+    std::vector<uint32_t> off(ncl + 1);
+    C2_TRY(hipMemcpyAsync(off.data(), cl_off, 4 * ((size_t)ncl + 1), hipMemcpyDeviceToHost, s), "copy");
+    C2_TRY(hipStreamSynchronize(s), "sync");
+    const uint64_t thr = (uint64_t)hy->rho * k * k;
+    std::vector<uint32_t> big;
+    for (uint32_t c = 0; c < ncl; ++c) {
+        if (off[c + 1] < off[c] || off[c + 1] > NE) return fail(C2_E_ARG, "cl_off not monotone");
+        const uint32_t sz = off[c + 1] - off[c];
+        if (sz >= 2 && sz >= thr) big.push_back(c);
+    }
+    if (big.empty())
+        return run_knn(P, members, cl_off, cl_cfg_off, t, k, C2_FORM_PLAIN, tune, part_id, part_I,
+                       base + L.knn, s);
+    if (ncl >= (1u << 24) || n >= (1u << 28))
+        return fail(C2_E_UNSUPPORTED, "Hyrec needs fewer than 2^24 clusters and 2^28 users");
+    {   // exact keys need |P_u| + |P_v| < 2^16
+        std::vector<int64_t> ip((size_t)n + 1);
+        C2_TRY(hipMemcpyAsync(ip.data(), P->indptr, 8 * ((size_t)n + 1), hipMemcpyDeviceToHost, s), "copy");
+        C2_TRY(hipStreamSynchronize(s), "sync");
+        for (uint32_t u = 0; u < n; ++u)
+            if (ip[u + 1] - ip[u] >= (1 << 15))
+                return fail(C2_E_UNSUPPORTED, "Hyrec clusters need profiles shorter than 2^15 items");
+    }
+    // brute force on the rest: every Hyrec cluster becomes singletons (pad lists),
+    // overwritten below
+    std::vector<uint32_t> off2, cfg2(t + 1);
+    off2.reserve(ncl + 1);
+    size_t bi = 0;
+    for (uint32_t j = 0; j < t; ++j) {
+        cfg2[j] = (uint32_t)off2.size();
+        for (uint32_t c = cfg[j]; c < cfg[j + 1]; ++c) {
+            if (bi < big.size() && big[bi] == c) {
+                for (uint32_t x = off[c]; x < off[c + 1]; ++x) off2.push_back(x);
+                ++bi;
+            } else {
+                off2.push_back(off[c]);
+            }
+        }
+    }
+    cfg2[t] = (uint32_t)off2.size();
+    off2.push_back((uint32_t)NE);
+    uint32_t *d_off2 = reinterpret_cast<uint32_t *>(base + L.cl_off);
+    uint32_t *d_cfg2 = reinterpret_cast<uint32_t *>(base + L.cfg);
+    C2_TRY(hipMemcpyAsync(d_off2, off2.data(), 4 * off2.size(), hipMemcpyHostToDevice, s), "copy");
+    C2_TRY(hipMemcpyAsync(d_cfg2, cfg2.data(), 4 * ((size_t)t + 1), hipMemcpyHostToDevice, s), "copy");
+    st = run_knn(P, members, d_off2, d_cfg2, t, k, C2_FORM_PLAIN, tune, part_id, part_I,
+                 base + L.knn, s);
+    C2_TRY(hipStreamSynchronize(s), "sync");  // off2 / cfg2 copied before they go
+    if (st != C2_OK) return st;
+    // Hyrec on the big clusters, reading the bit rows the local KNN left
+    KnnWs kw;
+    const uint32_t wmax = knn_wmax(P->m);
+    knn_ws_bytes(n, (uint32_t)NE, wmax, &kw);
+    const KnnPtrs kp = knn_ptrs(base + L.knn, kw);
+    uint64_t *kA = reinterpret_cast<uint64_t *>(base + L.keyA);
+    uint64_t *kB = reinterpret_cast<uint64_t *>(base + L.keyB);
+    uint32_t *iA = reinterpret_cast<uint32_t *>(base + L.IA);
+    uint32_t *iB = reinterpret_cast<uint32_t *>(base + L.IB);
+    uint32_t *upd = reinterpret_cast<uint32_t *>(base + L.upd);
+    for (uint32_t c : big) {
+        uint32_t j = 0;
+        while (cfg[j + 1] <= c) ++j;
+        const uint32_t *S = members + off[c];
+        const uint32_t sz = off[c + 1] - off[c];
+        C2_TRY(launch_hyrec_step(kp.rows, kp.rlen, wmax, S, sz, k, c, hy->seed, true, nullptr, kA,
+                                 iA, upd, s),
+               "hyrec init");
+        for (uint32_t it = 0; it < hy->max_iter; ++it) {
+            C2_TRY(launch_fill_u32(upd, 0, 1, s), "hyrec");
+            C2_TRY(launch_hyrec_step(kp.rows, kp.rlen, wmax, S, sz, k, c, hy->seed, false, kA, kB,
+                                     iB, upd, s),
+                   "hyrec step");
+            uint32_t h = 0;
+            C2_TRY(hipMemcpyAsync(&h, upd, 4, hipMemcpyDeviceToHost, s), "copy");
+            C2_TRY(hipStreamSynchronize(s), "sync");
+            uint64_t *tk = kA; kA = kB; kB = tk;
+            uint32_t *ti = iA; iA = iB; iB = ti;
+            if ((double)h < hy->delta * (double)k * (double)sz) break;
+        }
+        C2_TRY(launch_hyrec_out(S, sz, k, j, t, kA, iA, part_id, part_I, s), "hyrec out");
+    }
+    return C2_OK;
 }
 
 c2_status c2_merge(const c2_profiles *P, const uint32_t *part_id, const uint32_t *part_I,

@@ -125,6 +125,15 @@ struct KnnOpts {
 hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s);
 hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s);
 
+// ---- Hyrec branch of Algorithm 2
+hipError_t launch_hyrec_step(const uint32_t *rows, const uint32_t *rlen, uint32_t W,
+                             const uint32_t *S, uint32_t s, uint32_t k, uint32_t cl,
+                             uint64_t seed, bool init, const uint64_t *okey, uint64_t *nkey,
+                             uint32_t *nI, uint32_t *updates, hipStream_t st);
+hipError_t launch_hyrec_out(const uint32_t *S, uint32_t s, uint32_t k, uint32_t j, uint32_t t,
+                            const uint64_t *key, const uint32_t *I, uint32_t *part_id,
+                            uint32_t *part_I, hipStream_t st);
+
 // ---- merge
 hipError_t launch_merge(const int64_t *indptr, uint64_t nnz, uint32_t n, uint32_t t, uint32_t k,
                         const uint32_t *part_id, const uint32_t *part_I, uint32_t *knn_id,

@@ -394,26 +394,6 @@ C2_DEV uint64_t load_bits(const uint64_t *row, uint32_t chunk, uint32_t nchunks)
     return row[chunk < nchunks ? chunk : nchunks - 1];
 }
 
-// floor(I * (2^32 - 1) / U) for 0 <= I <= U < 2^16, U >= 1, without a
-// division: an fp32 estimate from the reciprocal of U (within 2^10 of the
-// quotient), one correction from the exact 32-bit remainder scaled by the
-// same reciprocal (within 1), and a final step on the sign and size of the
-// remainder.  Every remainder is below 2^31 in magnitude, so 32-bit integer
-// arithmetic is exact.  Checked against 64-bit division for all (I, U) with
-// the reciprocal exact, and on a sample with it 1 and 2 ulp off.
-C2_DEV uint32_t jkey(uint32_t I, uint32_t U) {
-    const float r = __builtin_amdgcn_rcpf((float)U);
-    const float qf = (float)I * r * 4294967296.0f;
-    const uint32_t q0 = qf >= 4294967295.0f ? 0xFFFFFFFFu : (uint32_t)qf;
-    const int32_t rem = (int32_t)((0u - I) - q0 * U);  // I * 2^32 - I - q0 * U
-    const int32_t c = (int32_t)floorf((float)rem * r);
-    uint32_t q = q0 + (uint32_t)c;
-    const int32_t rem1 = rem - c * (int32_t)U;
-    if (rem1 < 0) q -= 1;
-    else if (rem1 >= (int32_t)U) q += 1;
-    return q;
-}
-
 // I from key(I, U) and S = |P_u| + |P_v| (U = S - I): I/(S - I) is strictly
 // increasing in I, and S*key/(2^32 - 1 + key) is within 2^-16 of I.
 C2_DEV uint32_t key_to_I(uint32_t key, uint32_t S) {

@@ -444,6 +444,84 @@ def test_cluster_keys_split_uses_frh_from_the_start(orc):
         assert first[0] == frh[j].min()
 
 
+# ------------------------------------------- Algorithm 2, Hyrec branch ----
+
+def test_splitmix_published_outputs(orc):
+    """The generator of Hyrec's initial graph is SplitMix64: its published
+    first outputs from state 0."""
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    assert [orc.lib().orc_splitmix_at(0, c) for c in range(4)] == want
+
+
+def test_alg2_without_hyrec_is_brute_force(orc):
+    P = synth.random_profiles(50, 400, 200, 1, 30, 1.0)
+    bucket = orc.hash_items(synth.hash_tables(3, 51), 16, P.m)
+    mem, off, cfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, 80)
+    a = orc.local_knn(P.indptr, P.indices, P.n, P.m, 3, 5, mem, off, cfg)
+    b = orc.local_knn_alg2(P.indptr, P.indices, P.n, P.m, 3, 5, mem, off, cfg, rho=1000)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def hyrec_case(orc, seed, n=300, k=4, max_iter=30):
+    P = synth.random_profiles(seed, n, 120, 2, 25, 1.0)
+    t = 1
+    mem = np.arange(n, dtype=np.uint32)
+    off = np.array([0, n], dtype=np.uint32)
+    cfg = np.array([0, 1], dtype=np.uint32)
+    pid, pI = orc.local_knn_alg2(P.indptr, P.indices, n, P.m, t, k, mem, off, cfg, rho=5,
+                                 max_iter=max_iter, seed=seed)
+    return P, pid[:, 0], pI[:, 0]
+
+
+def test_hyrec_lists_are_valid(orc):
+    """Every Hyrec list holds distinct co-members other than u, with their
+    exact intersection, in the exact order."""
+    k = 4
+    for max_iter in (0, 1, 30):
+        P, pid, pI = hyrec_case(orc, 52, k=k, max_iter=max_iter)
+        rows = [set(P.indices[P.indptr[u]:P.indptr[u + 1]].tolist()) for u in range(P.n)]
+        for u in range(P.n):
+            ids = [int(v) for v in pid[u] if v != 0xFFFFFFFF]
+            assert len(ids) == len(set(ids)) and u not in ids and len(ids) >= 1
+            keys = []
+            for q, v in enumerate(ids):
+                I = len(rows[u] & rows[v])
+                assert pI[u, q] == I
+                keys.append((Fraction(I, len(rows[u] | rows[v])), -v))
+            assert keys == sorted(keys, reverse=True)
+
+
+def test_hyrec_converges_towards_brute_force(orc):
+    """Hyrec refines its random start: the graph after the iterations is far
+    better than the initial one and close to brute force's (Eq. 2)."""
+    k = 8                                   # rho*k^2 = 320 <= 400 members
+    P, pid0, pI0 = hyrec_case(orc, 53, n=400, k=k, max_iter=0)
+    _, pid, pI = hyrec_case(orc, 53, n=400, k=k, max_iter=30)
+    bid, bI, bU = orc.brute_force(P.indptr, P.indices, P.n, P.m, k)
+    lens = np.diff(P.indptr)
+
+    def avg(ids, I):
+        tot = 0.0
+        for u in range(P.n):
+            for q in range(k):
+                v = ids[u, q]
+                if v != 0xFFFFFFFF:
+                    tot += I[u, q] / (lens[u] + lens[v] - I[u, q])
+        return tot / (k * P.n)
+    exact = orc.avg_sim(bI, bU)
+    assert avg(pid, pI) > 0.93 * exact
+    assert avg(pid, pI) > avg(pid0, pI0) + 0.3 * exact
+
+
+def test_hyrec_independent_of_threads(orc):
+    P = synth.random_profiles(54, 500, 150, 2, 20, 1.0)
+    bucket = orc.hash_items(synth.hash_tables(2, 55), 2, P.m)
+    mem, off, cfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, P.n)
+    a = orc.local_knn_alg2(P.indptr, P.indices, P.n, P.m, 2, 3, mem, off, cfg, seed=9, threads=1)
+    b = orc.local_knn_alg2(P.indptr, P.indices, P.n, P.m, 2, 3, mem, off, cfg, seed=9, threads=8)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 # ------------------------------------------------- GoldFinger (II-F) ----
 
 def test_fingerprints_brute_force(orc):
