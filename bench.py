@@ -166,6 +166,43 @@ def goldfinger_variant(args, w, P, dP, c2, metrics, synth, torch, np, bf, B=1024
             "quality_def": "exact similarity of the chosen edges over the exact graph's"}
 
 
+def hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np, bf, rho=5):
+    """Algorithm 2's two branches side by side: the workload clustered
+    without splitting (cap = n, so the large top-level clusters reach rho*k^2
+    members), then the local KNN by brute force everywhere (c2_local_knn) and
+    by Algorithm 2 (Hyrec in the clusters of at least rho*k^2 members), each
+    merged and scored."""
+    p = c2.params(w.t, w.b, P.n, w.k)
+    bucket = c2.hash_items(dtab, w.b, w.m)
+    members, cl_off, cfg, _ = c2.cluster(dP, bucket, p, c2.FORM_PLAIN)
+    ncl = int(c2.to_u32(cfg)[-1])
+    sizes = np.diff(c2.to_u32(cl_off)[: ncl + 1].astype(np.int64))
+    big = sizes >= rho * w.k * w.k
+    res = {"rho": rho, "clusters": ncl, "hyrec_clusters": int(big.sum()),
+           "hyrec_members": int(sizes[big].sum()), "max_cluster": int(sizes.max())}
+    ws_bf = c2.workspace(dP, p, c2.OP_LOCAL_KNN)
+    ws_a2 = c2.workspace(dP, p, c2.OP_LOCAL_KNN_ALG2)
+    for name, fn in (("brute_force", lambda: c2.local_knn(dP, members, cl_off, cfg, p, ws=ws_bf)),
+                     ("alg2", lambda: c2.local_knn_alg2(dP, members, cl_off, cfg, p, rho=rho,
+                                                         ws=ws_a2))):
+        part = fn()
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 5))
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            part = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / reps
+        out = c2.merge(dP, part[0], part[1], p)
+        q = None
+        if bf is not None:
+            q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
+                                c2.to_u32(bf[2]))
+        res[name] = {"local_knn_ms": ms, "quality": q}
+        log("unsplit clusters, %s: local KNN %.3f ms, quality %s" % (name, ms, q))
+    return res
+
+
 def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_ms, batched_ms):
     """The learned cluster assigner: trained here on exact KNN edges of a
     100,000-user subsample, then the learned-assignment build (assignment,
@@ -247,6 +284,9 @@ def main():
                     help="also train the learned cluster assigner on this workload and time the "
                          "learned-assignment build beside the FastRandomHash forms")
     ap.add_argument("--learned-steps", type=int, default=1000)
+    ap.add_argument("--hyrec", action="store_true",
+                    help="also time Algorithm 2 (Hyrec in clusters of at least 5k^2 members) "
+                         "against brute force on the workload's unsplit clusters")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -354,6 +394,10 @@ def main():
     if args.learned:
         learned_leg = learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np,
                                       bf if quality is not None else None, plain_ms, batched_ms)
+    hyrec_leg = None
+    if args.hyrec:
+        hyrec_leg = hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np,
+                                  bf if quality is not None else None)
     ablation = gold = None
     if not args.no_ablation:
         ablation = minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np,
@@ -384,7 +428,7 @@ def main():
                    "tuning": tuned or "defaults"},
         "build_ms": {"graph": graph_ms, "batched": batched_ms, "plain": plain_ms},
         "quality": quality, "jaccard_evals": E, "clusters": ncl,
-        "minhash_ablation": ablation, "goldfinger": gold, "learned": learned_leg,
+        "minhash_ablation": ablation, "goldfinger": gold, "learned": learned_leg, "hyrec": hyrec_leg,
         "h2d_csr_ms": h2d_ms, "evals_per_s_incl_h2d": E / ((graph_ms + h2d_ms) * 1e-3),
         "local_knn_ms": knn_ms, "local_knn_evals_per_s": E / (knn_ms * 1e-3),
         "roofline": roof,

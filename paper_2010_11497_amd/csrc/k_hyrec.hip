@@ -17,6 +17,7 @@ namespace c2 {
 
 constexpr int kHyWaves = 4;
 constexpr uint32_t kHyInvalid = 0xFFFFFFFFu;
+constexpr int kHyGroup = 16;  // lanes per candidate when computing keys
 
 // SplitMix64 (Steele, Lea and Flood, 2014): output number c + 1 of the
 // generator whose state starts at `seed`.
@@ -77,27 +78,29 @@ __global__ __launch_bounds__(64 * kHyWaves) void k_hyrec_step(
     }
     hy_wave_sync();
 
-    // exact keys: the wave computes one candidate's intersection at a time
+    // exact keys: 16 lanes per candidate, 4 candidates per step
     const uint32_t u = S[a];
     const uint32_t *ru = rows + (size_t)u * W;
     const uint32_t lu = rlen[u];
-    for (uint32_t c = 0; c < NC; ++c) {
+    const int sub = lane & (kHyGroup - 1), slot = lane / kHyGroup;
+    for (uint32_t c0 = 0; c0 < (uint32_t)NC; c0 += 64 / kHyGroup) {
+        const uint32_t c = c0 + slot;
         const uint32_t pos = cpos[c];
-        uint64_t key = 0;
-        uint32_t I = 0;
+        uint32_t part = 0, lv = 0;
         if (pos != kHyInvalid) {
             const uint32_t v = S[pos];
             const uint32_t *rv = rows + (size_t)v * W;
-            uint32_t part = 0;
-            for (uint32_t w = lane; w < W; w += 64) part += __popc(ru[w] & rv[w]);
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d);
-            I = part;
-            key = ((uint64_t)jkey(I, lu + rlen[v] - I) << 32) | (uint64_t)(~pos);
+            lv = rlen[v];
+#pragma unroll 4
+            for (uint32_t w = sub; w < W; w += kHyGroup) part += __popc(ru[w] & rv[w]);
         }
-        if (lane == 0) {
-            ckey[c] = key;
-            cI[c] = I;
+#pragma unroll
+        for (int d = kHyGroup / 2; d >= 1; d >>= 1) part += __shfl_xor(part, d);
+        if (sub == 0) {
+            ckey[c] = pos != kHyInvalid
+                          ? ((uint64_t)jkey(part, lu + lv - part) << 32) | (uint64_t)(~pos)
+                          : 0ull;
+            cI[c] = pos != kHyInvalid ? part : 0u;
         }
     }
     hy_wave_sync();
