@@ -75,7 +75,14 @@ def cpu_baseline(P, tab, w, E, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or el / reps * (reps + 1) > 3 * budget_s:
             break
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": E * reps / el, "unit": "Jaccard evals/s", "cores": threads, "kind": "oracle",
+            "host_cpus": os.cpu_count(), "cpu_model": model,
             "sample": "%d whole build(s) of %s (hash, cluster, local KNN on a %d-thread pool "
                       "largest cluster first, merge): %.2f s each" % (reps, w.name, threads, el / reps)}
 
@@ -164,6 +171,57 @@ def goldfinger_variant(args, w, P, dP, c2, metrics, synth, torch, np, bf, B=1024
     return {"bits": B, "fingerprint_ms": fp_ms, "fingerprint_nnz": FP.nnz,
             "build_ms_plain": ms, "quality": q,
             "quality_def": "exact similarity of the chosen edges over the exact graph's"}
+
+
+def time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf,
+                    ts=(1, 2, 4, 8, 10, 12, 16), caps=(500, 1000, 2000, 3000, 4000, 10000)):
+    """The synthetic analogue of the paper's sensitivity study (Section VI,
+    Figs. 6-7): plain builds over the number of hash configurations t (nested
+    tables) and the split threshold N, each timed and scored against the exact
+    graph, next to the brute force itself (quality 1).  The fastest setting with
+    quality >= 0.95 is also timed as a HIP-graph replay of the batched form."""
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c2.brute_force(dP, w.k)
+    torch.cuda.synchronize()
+    res = {"brute_force_ms": (time.perf_counter() - t1) * 1e3, "points": []}
+    eI, eU = c2.to_u32(bf[1]), c2.to_u32(bf[2])
+    reps = 3
+    for t in ts:
+        dtab = c2.tables_to_device(synth.hash_tables(t, w.hash_seed))
+        for cap in caps:
+            p = c2.params(t, w.b, cap, w.k)
+            ws = c2.workspace(dP, p, c2.OP_BUILD)
+            out = c2.build(dP, dtab, p, c2.FORM_PLAIN, ws=ws)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                out = c2.build(dP, dtab, p, c2.FORM_PLAIN, ws=ws, out=out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) * 1e3 / reps
+            q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), eI, eU)
+            res["points"].append({"t": t, "N": cap, "build_ms_plain": ms, "quality": q})
+            log("t=%2d N=%5d: plain build %8.3f ms, quality %.4f" % (t, cap, ms, q))
+    ok = [x for x in res["points"] if x["quality"] >= 0.95]
+    if ok:
+        best = min(ok, key=lambda x: x["build_ms_plain"])
+        dtab = c2.tables_to_device(synth.hash_tables(best["t"], w.hash_seed))
+        p = c2.params(best["t"], w.b, best["N"], w.k)
+        from paper_2010_11497_amd import autotune
+        tuned = autotune.load_table(w.name) if (best["t"], best["N"]) == (w.t, w.cap) else None
+        g = c2.Graph(dP, dtab, p, c2.tuning(**(tuned or {})))
+        g.launch()
+        torch.cuda.synchronize()
+        g.check()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            g.launch()
+        torch.cuda.synchronize()
+        best = dict(best, build_ms_graph=(time.perf_counter() - t1) * 1e3 / reps)
+        g.close()
+        res["fastest_at_0.95"] = best
+        log("fastest setting with quality >= 0.95: %s" % best)
+    return res
 
 
 def hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np, bf, rho=5):
@@ -284,6 +342,9 @@ def main():
                     help="also train the learned cluster assigner on this workload and time the "
                          "learned-assignment build beside the FastRandomHash forms")
     ap.add_argument("--learned-steps", type=int, default=1000)
+    ap.add_argument("--sweep", action="store_true",
+                    help="time-to-quality curve: plain builds over t and the split threshold N, "
+                         "beside GPU brute force, and the fastest setting with quality >= 0.95")
     ap.add_argument("--hyrec", action="store_true",
                     help="also time Algorithm 2 (Hyrec in clusters of at least 5k^2 members) "
                          "against brute force on the workload's unsplit clusters")
@@ -394,6 +455,9 @@ def main():
     if args.learned:
         learned_leg = learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np,
                                       bf if quality is not None else None, plain_ms, batched_ms)
+    sweep_leg = None
+    if args.sweep and quality is not None:
+        sweep_leg = time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf)
     hyrec_leg = None
     if args.hyrec:
         hyrec_leg = hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np,
@@ -413,6 +477,7 @@ def main():
             "unit": "TFLOP/s", "frac": achieved / MFMA_FP4_PEAK,
             "traffic": traffic_from_profiles(w.name), "kernel": KNN_KERNEL,
             "ops_per_launch": ops,
+            "sparse_lower_bound_ops": int(work["sparse_pairs"]),
             "ops_def": "sum over clusters with >= %d members of 2*s^2*D: the 0/1 product of the "
                        "members' rows over the cluster's local dictionary (D = items held by >= "
                        "2 members), computed on e2m1 (fp4) MFMA with fp32 accumulation, exact"
@@ -428,7 +493,8 @@ def main():
                    "tuning": tuned or "defaults"},
         "build_ms": {"graph": graph_ms, "batched": batched_ms, "plain": plain_ms},
         "quality": quality, "jaccard_evals": E, "clusters": ncl,
-        "minhash_ablation": ablation, "goldfinger": gold, "learned": learned_leg, "hyrec": hyrec_leg,
+        "evals_vs_brute_force": E / (P.n * (P.n - 1) / 2),
+        "minhash_ablation": ablation, "goldfinger": gold, "learned": learned_leg, "hyrec": hyrec_leg, "time_to_quality": sweep_leg,
         "h2d_csr_ms": h2d_ms, "evals_per_s_incl_h2d": E / ((graph_ms + h2d_ms) * 1e-3),
         "local_knn_ms": knn_ms, "local_knn_evals_per_s": E / (knn_ms * 1e-3),
         "roofline": roof,

@@ -37,6 +37,9 @@ def cluster_work(members: np.ndarray, cl_off: np.ndarray, indptr: np.ndarray,
       ordered      = sum s^2
       bitmap_ops   = sum 2 * s^2 * ceil(D/32)   (AND + popcount-accumulate)
       dense_ops    = sum 2 * s^2 * D            (0/1 matrix product)
+      sparse_pairs = sum over clusters and items of f(f-1)/2, f = the item's
+                     count in the cluster (the intersections' own work: a
+                     lower bound for any method that touches only shared items)
     """
     off = np.asarray(cl_off, dtype=np.int64)
     s = np.diff(off)
@@ -45,6 +48,7 @@ def cluster_work(members: np.ndarray, cl_off: np.ndarray, indptr: np.ndarray,
     mem = np.asarray(members, dtype=np.int64)
     cl_of_slot = np.repeat(np.arange(len(s), dtype=np.int64), s)
     D = np.zeros(len(s), dtype=np.int64)
+    sparse = 0
     # clusters in chunks so that the (cluster, item) count table stays small
     chunk = max(1, (1 << 24) // max(m, 1))
     for c0 in range(0, len(s), chunk):
@@ -58,6 +62,7 @@ def cluster_work(members: np.ndarray, cl_off: np.ndarray, indptr: np.ndarray,
         items = np.asarray(indices, dtype=np.int64)[starts + within]
         cnt = np.bincount(cl * m + items, minlength=(c1 - c0) * m).reshape(c1 - c0, m)
         D[c0:c1] = (cnt >= 2).sum(axis=1)
+        sparse += int((cnt * (cnt - 1) // 2).sum())
     D[s < 2] = 0
     s2 = s * s
     return {
@@ -66,6 +71,7 @@ def cluster_work(members: np.ndarray, cl_off: np.ndarray, indptr: np.ndarray,
         "ordered": int(s2.sum()),
         "bitmap_ops": int((2 * s2 * ((D + 31) // 32)).sum()),
         "dense_ops": int((2 * s2 * D).sum()),
+        "sparse_pairs": sparse,
         "sizes": s,
         "dict": D,
     }

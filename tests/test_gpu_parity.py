@@ -455,3 +455,19 @@ def test_goldfinger_build(orc, name):
     want = orc.merge(ip, P.n, w.t, w.k, pid, pI)
     for a, b in zip(got, want):
         assert np.array_equal(u32(a), b)
+
+
+@pytest.mark.parametrize("name", ["n140k_m27k", "n500k_m50k"])
+def test_brute_force_sampled_large(orc, name):
+    """The exact graph that scores every quality figure, at the two largest
+    workloads: 200 seeded rows against the oracle's brute force over all n."""
+    w = synth.WORKLOADS[name]
+    say("brute force sampled", name)
+    P = synth.make_profiles(w)
+    dP = c2.DeviceProfiles.from_synth(P)
+    bf = c2.brute_force(dP, w.k)
+    torch.cuda.synchronize()
+    rows = np.random.Generator(np.random.PCG64(17)).choice(P.n, size=200, replace=False)
+    want = orc.brute_force(P.indptr, P.indices, P.n, P.m, w.k, rows=rows, threads=THREADS)
+    for g, ww in zip(bf, want):
+        assert np.array_equal(u32(g)[rows], ww)

@@ -628,3 +628,21 @@ def test_validate(orc):
     assert orc.validate(np.array([0, 2, 2]), ok.indices[:2], 2, 3) == -2   # empty row
     assert orc.validate(np.array([0, 2, 3]), np.array([2, 0, 1], np.uint32), 2, 3) == -2
     assert orc.validate(np.array([0, 2, 3]), np.array([1, 1, 1], np.uint32), 2, 3) == -2
+
+
+def test_cluster_work_sparse_pairs_identity(orc):
+    """Summed over same-cluster pairs, |P_u & P_v| counts every item once per
+    pair of members holding it: sum_{pairs} I = sum_{clusters, items} f(f-1)/2."""
+    from paper_2010_11497_amd import metrics
+    P = synth.random_profiles(60, 300, 100, 1, 25, 1.0)
+    bucket = orc.hash_items(synth.hash_tables(3, 61), 8, P.m)
+    mem, off, cfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, 50)
+    work = metrics.cluster_work(mem, off, P.indptr, P.indices, P.m)
+    rows = [set(P.indices[P.indptr[u]:P.indptr[u + 1]].tolist()) for u in range(P.n)]
+    tot = 0
+    for c in range(len(off) - 1):
+        S = mem[off[c]:off[c + 1]].tolist()
+        tot += sum(len(rows[a] & rows[b]) for i, a in enumerate(S) for b in S[i + 1:])
+    assert work["sparse_pairs"] == tot
+    assert work["pairs"] == sum(len(S) * (len(S) - 1) // 2 for S in
+                                (mem[off[c]:off[c + 1]] for c in range(len(off) - 1)))
