@@ -193,29 +193,37 @@ __global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
 
     const uint32_t tiles_per_head = b / kTileB;
     const uint32_t ntiles = t * tiles_per_head;
-    // cooperative tile load: 64 rows x 512 B in 16-byte chunks
-    auto load_tile = [&](uint32_t T, uint4 (&r)[kChunksPerThread], float &bias) {
-        const size_t row0 = (size_t)T * kTileB;
-#pragma unroll
-        for (int z = 0; z < kChunksPerThread; ++z) {
-            const uint32_t q = threadIdx.x + 64 * kKeyWaves * z;
-            r[z] = *reinterpret_cast<const uint4 *>(W2 + (row0 + q / 32) * kAsgHidden + (q % 32) * 8);
-        }
-        bias = threadIdx.x < kTileB ? b2[row0 + threadIdx.x] : 0.f;
-    };
-    auto store_tile = [&](int buf, const uint4 (&r)[kChunksPerThread], float bias) {
-#pragma unroll
-        for (int z = 0; z < kChunksPerThread; ++z) {
-            const uint32_t q = threadIdx.x + 64 * kKeyWaves * z;
-            *reinterpret_cast<uint4 *>(&wt[buf][(q / 32) * kRowPad + (q % 32) * 8]) = r[z];
-        }
-        if (threadIdx.x < kTileB) bt[buf][threadIdx.x] = bias;
-    };
+    // cooperative tile load: 64 rows x 512 B in 16-byte chunks, four per
+    // thread, held in named registers between the load and the LDS store
+    static_assert(kChunksPerThread == 4, "four chunks per thread");
+    const uint32_t q0 = threadIdx.x, qs = 64 * kKeyWaves;
+    const uint32_t g0 = (q0 / 32) * kAsgHidden + (q0 % 32) * 8;  // element offset in the tile
+    const uint32_t gs = (qs / 32) * kAsgHidden;                    // step between a thread's chunks
+    const uint32_t l0 = (q0 / 32) * kRowPad + (q0 % 32) * 8;
+    const uint32_t ls = (qs / 32) * kRowPad;
+    uint4 p0, p1, p2, p3;
+    float pbias = 0.f;
+#define C2_LOAD_TILE(T)                                                                        \
+    do {                                                                                       \
+        const uint16_t *src_ = W2 + (size_t)(T) * kTileB * kAsgHidden + g0;                    \
+        p0 = *reinterpret_cast<const uint4 *>(src_);                                           \
+        p1 = *reinterpret_cast<const uint4 *>(src_ + gs);                                      \
+        p2 = *reinterpret_cast<const uint4 *>(src_ + 2 * gs);                                  \
+        p3 = *reinterpret_cast<const uint4 *>(src_ + 3 * gs);                                  \
+        pbias = threadIdx.x < kTileB ? b2[(size_t)(T) * kTileB + threadIdx.x] : 0.f;           \
+    } while (0)
+#define C2_STORE_TILE(BUF)                                                                     \
+    do {                                                                                       \
+        uint16_t *dst_ = &wt[BUF][l0];                                                         \
+        *reinterpret_cast<uint4 *>(dst_) = p0;                                                 \
+        *reinterpret_cast<uint4 *>(dst_ + ls) = p1;                                            \
+        *reinterpret_cast<uint4 *>(dst_ + 2 * ls) = p2;                                        \
+        *reinterpret_cast<uint4 *>(dst_ + 3 * ls) = p3;                                        \
+        if (threadIdx.x < kTileB) bt[BUF][threadIdx.x] = pbias;                                \
+    } while (0)
 
-    uint4 pre[kChunksPerThread];
-    float pbias;
-    load_tile(0, pre, pbias);
-    store_tile(0, pre, pbias);
+    C2_LOAD_TILE(0);
+    C2_STORE_TILE(0);
     __syncthreads();
 
     Best best[2];
@@ -223,7 +231,7 @@ __global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
     best_reset(best[1]);
     for (uint32_t T = 0; T < ntiles; ++T) {
         const int buf = T & 1;
-        if (T + 1 < ntiles) load_tile(T + 1, pre, pbias);
+        if (T + 1 < ntiles) C2_LOAD_TILE(T + 1);
         // accumulators start at the bias of their bucket row
         f32x16 acc[2][2];
 #pragma unroll
@@ -246,14 +254,46 @@ __global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
             }
         }
         const uint32_t tin = T % tiles_per_head;
+        if constexpr (kSecond) {
+            // a group whose maximum does not beat the runner-up changes nothing
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const uint32_t c = tin * kTileB + 32 * rb + 8 * (r / 4) + 4 * half + (r % 4);
-                best_push<kSecond>(best[0], acc[rb][0][r], c);
-                best_push<kSecond>(best[1], acc[rb][1][r], c);
-            }
+                for (int cb = 0; cb < 2; ++cb) {
+                    const f32x16 &v = acc[rb][cb];
+                    float mx = fmaxf(fmaxf(v[0], v[1]), v[2]);
+#pragma unroll
+                    for (int r = 3; r < 15; r += 2) mx = fmaxf(fmaxf(mx, v[r]), v[r + 1]);
+                    mx = fmaxf(mx, v[15]);
+                    if (mx > best[cb].v2) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            best_push<true>(best[cb], v[r],
+                                            tin * kTileB + 32 * rb + 8 * (r / 4) + 4 * half + (r % 4));
+                    }
+                }
+        } else {
+            // the lane's 16 values of a row block rarely hold a new maximum once
+            // a few tiles have passed: take their maximum first, and search for
+            // the first (lowest) bucket holding it only when it beats the best
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const f32x16 &v = acc[rb][cb];
+                    float mx = fmaxf(fmaxf(v[0], v[1]), v[2]);
+#pragma unroll
+                    for (int r = 3; r < 15; r += 2) mx = fmaxf(fmaxf(mx, v[r]), v[r + 1]);
+                    mx = fmaxf(mx, v[15]);
+                    if (mx > best[cb].v1) {
+                        int first = 15;
+#pragma unroll
+                        for (int r = 14; r >= 0; --r) first = v[r] == mx ? r : first;
+                        best[cb].v1 = mx;
+                        best[cb].idx = tin * kTileB + 32 * rb + 8 * (first / 4) + 4 * half + (first % 4);
+                    }
+                }
+        }
         if (tin == tiles_per_head - 1) {
             const uint32_t j = T / tiles_per_head;
 #pragma unroll
@@ -272,10 +312,13 @@ __global__ __launch_bounds__(64 * kKeyWaves) void k_assign_keys(
                 best_reset(best[c]);
             }
         }
-        __syncthreads();
-        if (T + 1 < ntiles) store_tile(buf ^ 1, pre, pbias);
+        // buf ^ 1 was last read before the previous barrier: store the next
+        // tile there, then one barrier publishes it and retires buf
+        if (T + 1 < ntiles) C2_STORE_TILE(buf ^ 1);
         __syncthreads();
     }
+#undef C2_LOAD_TILE
+#undef C2_STORE_TILE
 }
 
 // -------------------------------------------------------------- training
