@@ -345,6 +345,10 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="time-to-quality curve: plain builds over t and the split threshold N, "
                          "beside GPU brute force, and the fastest setting with quality >= 0.95")
+    ap.add_argument("--sweep-t", default="1,2,4,8,10,12,16",
+                    help="hash-configuration counts of the sweep (comma separated)")
+    ap.add_argument("--sweep-n", default="500,1000,2000,3000,4000,10000",
+                    help="split thresholds N of the sweep (comma separated)")
     ap.add_argument("--hyrec", action="store_true",
                     help="also time Algorithm 2 (Hyrec in clusters of at least 5k^2 members) "
                          "against brute force on the workload's unsplit clusters")
@@ -457,7 +461,9 @@ def main():
                                       bf if quality is not None else None, plain_ms, batched_ms)
     sweep_leg = None
     if args.sweep and quality is not None:
-        sweep_leg = time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf)
+        sweep_leg = time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf,
+                                    tuple(int(x) for x in args.sweep_t.split(",")),
+                                    tuple(int(x) for x in args.sweep_n.split(",")))
     hyrec_leg = None
     if args.hyrec:
         hyrec_leg = hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np,
