@@ -27,7 +27,7 @@ constexpr uint32_t kMC = 128;        // columns per MFMA step
 constexpr int kOpStride = 48;        // bytes per staged 64-item row of nibbles (32 + pad: no bank conflicts)
 constexpr int kTileStride = 132;     // u32 per row of the transposed result tile
 constexpr uint32_t kDefaultMfmaMin = 2;
-constexpr uint32_t kPf = 8;          // chunks of bit rows prefetched ahead (MFMA path)
+constexpr uint32_t kPf = 4;          // chunks of bit rows prefetched ahead (MFMA path)
 constexpr uint32_t kGroupTiles = 4;  // column tiles per work item before a row block is split
 constexpr uint32_t kMaxGroups = 4;   // column groups a row block is split into at most
 constexpr uint32_t kUserBitsGrid = 512;  // blocks of k_user_bits at most
