@@ -9,6 +9,7 @@ replays), checks that every point produces the same graph, and writes the
 fastest point to tuning/<workload>.json.  bench.py reads that table.
 
 Run on the GPU:  python -m paper_2010_11497_amd.autotune --workload n6k_m3.7k
+(each grid axis can be replaced from the command line, e.g. --mfma-min-rows 2,64)
 """
 import argparse
 import itertools
@@ -44,7 +45,12 @@ def main():
     ap.add_argument("--workload", default="n6k_m3.7k")
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--out", default=None)
+    for key in GRID:
+        ap.add_argument("--" + key.replace("_", "-"), default=None,
+                        help="comma-separated values (default %s)" % GRID[key])
     args = ap.parse_args()
+    grid = {key: ([int(x) for x in getattr(args, key).split(",")] if getattr(args, key)
+                  else GRID[key]) for key in GRID}
 
     import numpy as np
     import torch
@@ -58,8 +64,8 @@ def main():
     dtab = c2.tables_to_device(tab)
     p = c2.params(w.t, w.b, w.cap, w.k)
     results, ref = [], None
-    for vals in itertools.product(*GRID.values()):
-        point = dict(zip(GRID.keys(), vals))
+    for vals in itertools.product(*grid.values()):
+        point = dict(zip(grid.keys(), vals))
         g = c2.Graph(dP, dtab, p, c2.tuning(**point))
         for _ in range(2):
             g.launch()
@@ -82,7 +88,7 @@ def main():
         print(json.dumps({"workload": w.name, **point, "build_ms": round(ms, 4)}), flush=True)
     best = min(results, key=lambda r: r["build_ms"])
     out = {"workload": w.name, "best": best["point"], "best_build_ms": best["build_ms"],
-           "grid": GRID, "results": results,
+           "grid": grid, "results": results,
            "device": torch.cuda.get_device_name(0)}
     path = args.out or table_path(w.name)
     os.makedirs(os.path.dirname(path), exist_ok=True)
