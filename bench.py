@@ -63,6 +63,18 @@ def traffic_from_profiles(workload):
     return d.get("bytes_per_launch")
 
 
+def mfma_busy_from_profiles(workload):
+    """Hardware MFMA busy share of the local-KNN kernel (SQ_VALU_MFMA_BUSY_CYCLES
+    over the dispatch's cycles times the SIMD count) from the committed PMC
+    summary, only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_mfma_busy.json" % (KNN_KERNEL, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    return d.get("mfma_busy_frac") if d.get("source_hash") == source_hash() else None
+
+
 def cpu_baseline(P, tab, w, E, budget_s):
     """The oracle as it stands, on the host's cores, on whole builds of the same
     workload repeated until about budget_s seconds have passed."""
@@ -482,6 +494,7 @@ def main():
     roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_FP4_PEAK / 1e12,
             "unit": "TFLOP/s", "frac": achieved / MFMA_FP4_PEAK,
             "traffic": traffic_from_profiles(w.name), "kernel": KNN_KERNEL,
+            "hw_mfma_busy_frac": mfma_busy_from_profiles(w.name),
             "ops_per_launch": ops,
             "sparse_lower_bound_ops": int(work["sparse_pairs"]),
             "ops_def": "sum over clusters with >= %d members of 2*s^2*D: the 0/1 product of the "
