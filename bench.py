@@ -277,34 +277,45 @@ def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_m
     """The learned cluster assigner: trained here on exact KNN edges of a
     100,000-user subsample, then the learned-assignment build (assignment,
     clustering from keys with FastRandomHash splits, local KNN, merge) timed in
-    the plain eager form and scored against the exact graph."""
-    from paper_2010_11497_amd import learned
+    the plain and batched eager forms and scored against the exact graph.  Heads
+    and split threshold default to the workload's t and N."""
+    from paper_2010_11497_amd import learned, synth
     b = 8192 if w.n >= 100000 else w.b
+    T = args.learned_t or w.t
+    cap = args.learned_cap or w.cap
     t0 = time.perf_counter()
     pairs = learned.exact_pairs(P, 100000, w.k, seed=1)
-    A = learned.Assigner(P.m, w.t, b, seed=2)
+    A = learned.Assigner(P.m, T, b, seed=2)
     st = learned.train(A, dP, pairs, steps=args.learned_steps, batch=2048, w_bal=1.0, w_neg=1.0,
                        w_ent=1.0, lr=3e-3, log=log)
     train_s = time.perf_counter() - t0
     W = A.inference_weights()
-    out = None
-    res = {"buckets": b, "train_s": train_s, "train_steps": st.steps, "train_pairs": st.pairs,
-           "loss": [st.first_loss, st.last_loss], "min_gap": {}}
+    tabT = c2.tables_to_device(synth.hash_tables(T, w.hash_seed)) if T != w.t else dtab
+    pT = c2.params(T, w.b, cap, w.k)
+    res = {"buckets": b, "heads": T, "N": cap, "train_s": train_s, "train_steps": st.steps,
+           "train_pairs": st.pairs, "loss": [st.first_loss, st.last_loss], "min_gap": {}}
+    tb = c2.tuning(split_rounds=64)
     for gap in (0.0, 0.5):
-        for _ in range(args.warmup):
-            out = learned.build(A, dP, dtab, p, gap, weights=W)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            out = learned.build(A, dP, dtab, p, gap, weights=W)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        entry = {}
+        for form, tu, key in ((c2.FORM_PLAIN, None, "build_ms_plain"),
+                              (c2.FORM_BATCHED, tb, "build_ms_batched")):
+            out = None
+            for _ in range(args.warmup):
+                out = learned.build(A, dP, tabT, pT, gap, form, tu, weights=W)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                out = learned.build(A, dP, tabT, pT, gap, form, tu, weights=W)
+            torch.cuda.synchronize()
+            entry[key] = (time.perf_counter() - t1) * 1e3 / args.steps
         q = None
         if bf is not None:
             q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
                                 c2.to_u32(bf[2]))
-        res["min_gap"][str(gap)] = {"build_ms_plain": ms, "quality": q}
-        log("learned assigner (min_gap %.1f): plain build %.3f ms, quality %s" % (gap, ms, q))
+        entry["quality"] = q
+        res["min_gap"][str(gap)] = entry
+        log("learned assigner (t=%d, N=%d, min_gap %.1f): plain %.3f ms, batched %.3f ms, "
+            "quality %s" % (T, cap, gap, entry["build_ms_plain"], entry["build_ms_batched"], q))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):
@@ -354,6 +365,10 @@ def main():
                     help="also train the learned cluster assigner on this workload and time the "
                          "learned-assignment build beside the FastRandomHash forms")
     ap.add_argument("--learned-steps", type=int, default=1000)
+    ap.add_argument("--learned-t", type=int, default=0,
+                    help="heads (hash configurations) of the learned build (default: the workload's t)")
+    ap.add_argument("--learned-cap", type=int, default=0,
+                    help="split threshold N of the learned build (default: the workload's)")
     ap.add_argument("--sweep", action="store_true",
                     help="time-to-quality curve: plain builds over t and the split threshold N, "
                          "beside GPU brute force, and the fastest setting with quality >= 0.95")

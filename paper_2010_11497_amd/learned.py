@@ -156,6 +156,8 @@ def build(A: Assigner, P: c2.DeviceProfiles, tab: torch.Tensor, p: c2.Params,
     keys = A.keys(P, frh, min_gap, weights)
     kb = 2 * max(p.b, A.b)
     pk = c2.params(p.t, kb, p.cap, p.k)
-    members, cl_off, cfg, _ = c2.cluster_keys(P, keys, bucket, pk, form, tune)
+    members, cl_off, cfg, ws = c2.cluster_keys(P, keys, bucket, pk, form, tune)
+    if form == c2.FORM_BATCHED:
+        c2.check_complete(ws)   # enough split rounds were enqueued (synchronous)
     part = c2.local_knn(P, members, cl_off, cfg, pk, form, tune)
     return c2.merge(P, part[0], part[1], pk)
