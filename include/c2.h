@@ -103,6 +103,11 @@ typedef struct c2_tuning {
                                  bit_width(b) <= 20; otherwise the grid rounds are used) */
     void *ev_knn_begin;       /* optional hipEvent_t (host handles, caller-owned): recorded on */
     void *ev_knn_end;         /* the stream right before / after the pairwise local-KNN kernel */
+    uint32_t compact;         /* per-cluster item dictionaries (Section II-F staging: only items
+                                 held by >= 2 members can be in an intersection): 0 automatic
+                                 (on when bit rows reach 512 words, m >= 16384), 1 off, 2 on.
+                                 Clusters of 2..8192 members whose dictionary saves at least a
+                                 quarter of the row are multiplied over it; the result is the same */
 } c2_tuning;
 
 /* Workspace queries: which call the size is for. */

@@ -62,7 +62,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("mfma_min_rows", ctypes.c_uint32), ("persistent_wgs", ctypes.c_uint32),
                 ("split_rounds", ctypes.c_uint32), ("group_tiles", ctypes.c_uint32),
                 ("cluster_path", ctypes.c_uint32),
-                ("ev_knn_begin", ctypes.c_void_p), ("ev_knn_end", ctypes.c_void_p)]
+                ("ev_knn_begin", ctypes.c_void_p), ("ev_knn_end", ctypes.c_void_p),
+                ("compact", ctypes.c_uint32)]
 
 
 _lib = None
@@ -169,14 +170,15 @@ def params(t, b, cap, k) -> Params:
 
 
 CLUSTER_AUTO, CLUSTER_GRID, CLUSTER_WORKGROUP = 0, 1, 2
+COMPACT_AUTO, COMPACT_OFF, COMPACT_ON = 0, 1, 2
 
 
 def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0, group_tiles=0,
-           cluster_path=CLUSTER_AUTO, events=None) -> Tuning:
+           cluster_path=CLUSTER_AUTO, events=None, compact=COMPACT_AUTO) -> Tuning:
     """events: optional (begin, end) torch.cuda.Event(enable_timing=True) pair
     recorded around the local-KNN kernel."""
     tu = Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), int(group_tiles),
-                int(cluster_path), None, None)
+                int(cluster_path), None, None, int(compact))
     if events is not None:
         for ev in events:
             ev.record()           # materialise the underlying hipEvent_t

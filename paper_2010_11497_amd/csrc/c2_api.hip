@@ -156,6 +156,11 @@ KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
     k.pc = u32(w.pc);
     k.ccls = u32(w.ccls);
     k.cpos = u32(w.cpos);
+    k.cbits = u32(w.cbits);
+    k.cw = u32(w.cw);
+    k.coff = u64(w.coff);
+    k.ccur = reinterpret_cast<unsigned long long *>(base + w.ccur);
+    k.cbits_words = w.cbits_words;
     return k;
 }
 
@@ -276,6 +281,7 @@ c2_status run_knn(const c2_profiles *P, const uint32_t *members, const uint32_t 
         o.persistent_wgs = tune->persistent_wgs;
         o.mfma_min = tune->mfma_min_rows;
         o.group_tiles = tune->group_tiles;
+        o.compact = tune->compact;
         o.ev_begin = (hipEvent_t)tune->ev_knn_begin;
         o.ev_end = (hipEvent_t)tune->ev_knn_end;
     }

@@ -101,7 +101,8 @@ struct KnnArgs {
 struct KnnWs {
     size_t rows, rlen, cnt, items_m, items_b, slots, sbase, rb_done, skeys, csort_key,
         csort_key_alt, csort_val, csort_val_alt, hist, htmp, ctmp, ctr, bmax, pc, ccls, cpos,
-        total;
+        cbits, cw, coff, ccur, total;
+    size_t cbits_words;  // capacity of the compacted-row region
 };
 struct KnnPtrs {
     uint32_t *rows, *rlen;
@@ -112,6 +113,10 @@ struct KnnPtrs {
     uint32_t *csort_val, *csort_val_alt, *hist, *htmp;
     uint64_t *ctmp;
     uint32_t *ctr, *bmax, *pc, *ccls, *cpos;
+    uint32_t *cbits, *cw;          // compacted rows, words per compacted row of each cluster
+    uint64_t *coff;                // first word of each compacted cluster in cbits
+    unsigned long long *ccur;      // allocation cursor of cbits
+    uint64_t cbits_words;
 };
 size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w);
 uint32_t knn_wmax(uint32_t m);
@@ -120,6 +125,7 @@ struct KnnOpts {
     uint32_t persistent_wgs = 0;
     uint32_t mfma_min = 0;
     uint32_t group_tiles = 0;
+    uint32_t compact = 0;  // 0 automatic, 1 off, 2 on
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
 hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s);

@@ -37,6 +37,11 @@ constexpr uint32_t kBitmapPersistent = 256;  // persistent bitmap-path workgroup
 constexpr uint32_t kCostClasses = 64;
 constexpr uint32_t kSlotCtr = kCostClasses, kBitmapCtr = kCostClasses + 1;
 constexpr uint32_t kPlanCtr = kCostClasses + 2;
+// per-cluster dictionaries: automatic from rows of this many words, for
+// clusters of at most kCompactMaxS members
+constexpr uint32_t kCompactMinW = 512;
+constexpr uint32_t kCompactMaxS = 8192;
+constexpr uint32_t kCompactGrid = 1024;
 
 // Words per bit row: the item universe padded to a multiple of 64 * kPf items,
 // so the MFMA K loop runs whole unrolled groups.
@@ -503,6 +508,9 @@ struct MfmaScratch {
     uint64_t *keys;       // [slot][kMR][kMaxK]
     uint32_t *rb_done;    // per (cluster, row block) of a split row block
     const uint32_t *sbase;  // first slot of each cluster
+    const uint32_t *cbits;  // compacted rows (nullptr: compaction off)
+    const uint32_t *cw;     // words per compacted row of each cluster, 0 = full rows
+    const uint64_t *coff;   // first word of each compacted cluster
 };
 
 C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *ulen,
@@ -512,7 +520,9 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
     const uint32_t wr = w >> 1, wc = w & 1;
     const ClusterView cv = view(a, c);
-    const uint32_t s = cv.s, W = a.wmax, nchunks = W / 2;
+    const uint32_t Wc = sc.cw ? sc.cw[c] : 0u;  // compacted row width, 0 = full rows
+    const uint32_t s = cv.s, W = a.wmax, nchunks = (Wc ? Wc : W) / 2;
+    const uint32_t *cbase = Wc ? sc.cbits + sc.coff[c] : nullptr;
     // selection: row r of the block belongs to the thread pair (2r, 2r + 1);
     // both filter half of each tile, the even thread keeps the heap
     const uint32_t r = t >> 1, half = t & 1;
@@ -535,7 +545,11 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     for (uint32_t cb = g * per; cb < cb_end; ++cb) {
         // staged row of this thread: owner row t, or column t - 128
         const uint32_t us = t < kMR ? us_row : member(a, cv, cb * kMC + (t - kMR));
-        const uint64_t *src = reinterpret_cast<const uint64_t *>(ubits + (size_t)us * W);
+        // the member's row over the cluster's dictionary, or its full row (the
+        // all-zero row n for padding, which is at least as long as any row)
+        const uint32_t pos = t < kMR ? rb * kMR + t : cb * kMC + (t - kMR);
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(
+            cbase && pos < s ? cbase + (size_t)pos * Wc : ubits + (size_t)us * W);
         if (t >= kMR) {
             L.cuid[t - kMR] = us;
             L.clen[t - kMR] = us < a.n ? ulen[us] : 0;
@@ -832,6 +846,195 @@ __global__ __launch_bounds__(256, 2) void k_knn_mfma(KnnArgs a, const uint32_t *
     }
 }
 
+// ------------------------------------------------------- cluster dictionaries
+//
+// Only items held by at least two members of a cluster can be in an
+// intersection, so a cluster's pairwise counts need only those items (its
+// local dictionary).  For each cluster of 2..kCompactMaxS members a block
+// builds the dictionary from the members' bit rows (an item is in it when a
+// second member also has it: twice |= once & x; once |= x), numbers its items
+// in order with a prefix of popcounts, and, when the dictionary is at most
+// three quarters of the row, writes every member's row restricted to it
+// (padded to 256 items) to cbits; cw[c] then holds the compacted width.  The
+// dot products over the compacted rows equal those over the full rows.
+// Compacted copies of two members' rows (src1 may repeat src0) into this
+// wave's LDS buffers rowb and rowb + wc: the words are loaded 8 per lane per
+// member before any is used, so 16 loads are in flight.
+C2_DEV void set_local_bits(uint32_t x, uint32_t d, uint32_t base, uint32_t *rowb) {
+    while (x) {
+        const uint32_t b = __builtin_ctz(x);
+        x &= x - 1;
+        const uint32_t li = base + __popc(d & ((1u << b) - 1u));
+        atomicOr(&rowb[li >> 5], 1u << (li & 31));
+    }
+}
+
+C2_DEV void compact_rows2(const uint32_t *src0, const uint32_t *src1, bool two,
+                          const uint32_t *dm, const uint32_t *pre, uint32_t W, uint32_t lane,
+                          uint32_t *rowb, uint32_t wc) {
+    for (uint32_t w0 = lane; w0 < W; w0 += 64 * 8) {
+        uint32_t x0[8], x1[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t w = w0 + 64 * q;
+            x0[q] = w < W ? src0[w] : 0u;
+            x1[q] = (two && w < W) ? src1[w] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t w = w0 + 64 * q;
+            if (w < W) {
+                const uint32_t d = dm[w], base = pre[w];
+                set_local_bits(x0[q] & d, d, base, rowb);
+                set_local_bits(x1[q] & d, d, base, rowb + wc);
+            }
+        }
+    }
+}
+
+// One pass of the dictionary over 4 words per thread (wbase + NT * i, i < 4):
+// groups of 8 member rows, the next group loaded while this one is folded in,
+// so 32 loads are in flight per thread.
+template <int NT>
+C2_DEV void dict_words(const KnnArgs &a, const ClusterView &cv, const uint32_t *ubits,
+                       uint32_t W, uint32_t wbase, uint32_t *dm) {
+    const uint32_t s = cv.s;
+    uint32_t o[4] = {0, 0, 0, 0}, t2[4] = {0, 0, 0, 0};
+    uint32_t wi[4];
+    bool ok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        wi[i] = wbase + NT * i;
+        ok[i] = wi[i] < W;
+    }
+    auto row = [&](uint32_t r) -> const uint32_t * {
+        const uint32_t u = a.members[cv.o + r];
+        return ubits + (size_t)(u < a.n ? u : a.n) * W;
+    };
+    uint32_t nx[8][4];
+    const uint32_t full = s / 8 * 8;
+    if (full) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t *rw = row(q);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) nx[q][i] = ok[i] ? rw[wi[i]] : 0u;
+        }
+    }
+    for (uint32_t r = 0; r < full; r += 8) {
+        uint32_t x[8][4];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[q][i] = nx[q][i];
+        if (r + 8 < full) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t *rw = row(r + 8 + q);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) nx[q][i] = ok[i] ? rw[wi[i]] : 0u;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                t2[i] |= o[i] & x[q][i];
+                o[i] |= x[q][i];
+            }
+    }
+    for (uint32_t r = full; r < s; ++r) {
+        const uint32_t *rw = row(r);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t x = ok[i] ? rw[wi[i]] : 0u;
+            t2[i] |= o[i] & x;
+            o[i] |= x;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (ok[i]) dm[wi[i]] = t2[i];
+}
+
+// NT threads per block (NT/64 waves, two row buffers each).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_compact(KnnArgs a, const uint32_t *__restrict__ ubits,
+                                                uint32_t *__restrict__ cbits, uint64_t cap,
+                                                uint32_t *__restrict__ cw,
+                                                uint64_t *__restrict__ coff,
+                                                unsigned long long *ccur, uint32_t *cnext) {
+    constexpr uint32_t NWV = NT / 64;
+    extern __shared__ uint32_t lds[];
+    const uint32_t W = a.wmax;
+    uint32_t *dm = lds, *pre = lds + W;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint32_t *rowb = lds + 2 * W + wid * 2 * W;  // two row buffers per wave
+    __shared__ uint32_t wsum[NT / 64 + 1];
+    __shared__ unsigned long long sh_off;
+    __shared__ uint32_t sh_ok, sh_c;
+    const uint32_t ncl = a.cl_cfg_off[a.t];
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) sh_c = atomicAdd(cnext, 1u);
+        __syncthreads();
+        const uint32_t c = sh_c;
+        if (c >= ncl) break;
+        const ClusterView cv = view(a, c);
+        const uint32_t s = cv.s;
+        if (s < 2 || s > kCompactMaxS) {
+            if (tid == 0) cw[c] = 0;
+            continue;
+        }
+        // dictionary: items held by >= 2 members
+        for (uint32_t wb = tid; wb < W; wb += 4 * NT) dict_words<NT>(a, cv, ubits, W, wb, dm);
+        __syncthreads();
+        // local index of each word's first dictionary item: exclusive prefix of
+        // popcounts, each thread over a contiguous range of words
+        const uint32_t per = (W + NT - 1) / NT, w0 = tid * per;
+        uint32_t mine = 0;
+        for (uint32_t w = w0; w < w0 + per && w < W; ++w) mine += __popc(dm[w]);
+        uint32_t total;
+        uint32_t run = block_excl_scan<uint32_t, NT>(mine, wsum, &total);
+        for (uint32_t w = w0; w < w0 + per && w < W; ++w) {
+            pre[w] = run;
+            run += __popc(dm[w]);
+        }
+        const uint32_t wc = ((total ? total : 1u) + 255u) / 256u * 8u;  // words, a multiple of 8
+        if (tid == 0) {
+            sh_ok = 0;
+            if (4 * wc <= 3 * W) {
+                const unsigned long long need = (unsigned long long)s * wc;
+                const unsigned long long off = atomicAdd(ccur, need);
+                if (off + need <= cap) {
+                    sh_ok = 1;
+                    sh_off = off;
+                }
+            }
+            cw[c] = sh_ok ? wc : 0u;
+            if (sh_ok) coff[c] = sh_off;
+        }
+        __syncthreads();
+        if (!sh_ok) continue;
+        // each wave compacts two member rows at a time in its LDS buffers
+        for (uint32_t r = 2 * wid; r < s; r += 2 * NWV) {
+            const bool two = r + 1 < s;
+            for (uint32_t o2 = lane; o2 < 2 * wc; o2 += 64) rowb[o2] = 0;
+            wave_sync();
+            const uint32_t u0 = a.members[cv.o + r];
+            const uint32_t u1 = two ? a.members[cv.o + r + 1] : a.n;
+            compact_rows2(ubits + (size_t)(u0 < a.n ? u0 : a.n) * W,
+                          ubits + (size_t)(u1 < a.n ? u1 : a.n) * W, two, dm, pre, W, lane, rowb,
+                          wc);
+            wave_sync();
+            uint32_t *dst = cbits + sh_off + (size_t)r * wc;
+            const uint32_t nw = two ? 2 * wc : wc;
+            for (uint32_t o2 = lane; o2 < nw; o2 += 64) dst[o2] = rowb[o2];
+            wave_sync();
+        }
+    }
+}
+
 // ---------------------------------------------------------------- planning
 
 // Column groups of an MFMA cluster of s members.
@@ -1027,6 +1230,16 @@ size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w) {
     x.pc = take(4 * kPlanCtr);
     x.ccls = take(4 * (size_t)NE);
     x.cpos = take(4 * (size_t)NE);
+    // compacted rows: room for half of every member slot's full row, at most
+    // 2^30 words (2^24 when the automatic rule leaves compaction off)
+    size_t cap = (size_t)NE * wmax / 2;
+    const size_t cmax = wmax >= kCompactMinW ? ((size_t)1 << 30) : ((size_t)1 << 24);
+    if (cap > cmax) cap = cmax;
+    x.cbits_words = cap;
+    x.cbits = take(4 * cap);
+    x.cw = take(4 * (size_t)NE);
+    x.coff = take(8 * (size_t)NE);
+    x.ccur = take(16);
     x.total = off;
     if (w) *w = x;
     return off;
@@ -1062,6 +1275,15 @@ static hipError_t plan(const KnnArgs &a, const KnnPtrs &w, const uint32_t *order
     return hipGetLastError();
 }
 
+// k_compact keeps 2 + 2 * waves rows in LDS: 8 waves up to 2048-word rows, else 4
+static uint32_t compact_threads(uint32_t wmax) { return wmax <= 2048 ? 512u : 256u; }
+
+static bool compact_on(const KnnArgs &a, const KnnOpts &o) {
+    const uint32_t waves = compact_threads(a.wmax) / 64;
+    if ((size_t)(2 + 2 * waves) * a.wmax * 4 + 1024 > 160 * 1024) return false;
+    return o.compact == 2 || (o.compact == 0 && a.wmax >= kCompactMinW);
+}
+
 static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o,
                                uint32_t grid_m, uint32_t grid_b, bool batched, hipStream_t s) {
     // the events bracket the MFMA kernel, which carries the large clusters
@@ -1071,6 +1293,10 @@ static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts
     sc.keys = w.skeys;
     sc.rb_done = w.rb_done;
     sc.sbase = w.sbase;
+    const bool cmp = compact_on(a, o);
+    sc.cbits = cmp ? w.cbits : nullptr;
+    sc.cw = cmp ? w.cw : nullptr;
+    sc.coff = cmp ? w.coff : nullptr;
     if (grid_m)
         hipLaunchKernelGGL(k_knn_mfma, dim3(grid_m), dim3(256), 0, s, a, w.rows, w.rlen, sc,
                            w.items_m, w.ctr, batched ? w.ctr + 2 : nullptr);
@@ -1082,9 +1308,29 @@ static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts
     return hipGetLastError();
 }
 
+static hipError_t compact(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
+    if (!compact_on(a, o)) return hipSuccess;
+    const uint32_t nt = compact_threads(a.wmax);
+    const size_t lds = (size_t)(2 + 2 * (nt / 64)) * a.wmax * 4;  // dictionary, prefix, row buffers
+    const void *fn = nt == 512 ? (const void *)k_compact<512> : (const void *)k_compact<256>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    // allocation cursor (u64) and cluster cursor (u32)
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(w.ccur), 0, 4, s)) != hipSuccess) return e;
+    uint32_t *cnext = reinterpret_cast<uint32_t *>(w.ccur) + 2;
+    if (nt == 512)
+        hipLaunchKernelGGL(k_compact<512>, dim3(kCompactGrid), dim3(512), lds, s, a, w.rows,
+                           w.cbits, (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
+    else
+        hipLaunchKernelGGL(k_compact<256>, dim3(kCompactGrid), dim3(256), lds, s, a, w.rows,
+                           w.cbits, (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
+    return hipGetLastError();
+}
+
 hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
     hipError_t e = user_bits(a, w, s);
     if (e != hipSuccess) return e;
+    if ((e = compact(a, w, o, s)) != hipSuccess) return e;
     if ((e = plan(a, w, nullptr, o, false, s)) != hipSuccess) return e;
     uint32_t n[2] = {0, 0};
     e = hipMemcpyAsync(n, w.ctr, 8, hipMemcpyDeviceToHost, s);
@@ -1096,6 +1342,7 @@ hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipSt
 hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
     hipError_t e = user_bits(a, w, s);
     if (e != hipSuccess) return e;
+    if ((e = compact(a, w, o, s)) != hipSuccess) return e;
     // items by cost class, costliest first (the size-ordered queue of
     // Section II-F), without a sort
     const dim3 g((uint32_t)div_up(a.NE, 256));

@@ -471,3 +471,62 @@ def test_brute_force_sampled_large(orc, name):
     want = orc.brute_force(P.indptr, P.indices, P.n, P.m, w.k, rows=rows, threads=THREADS)
     for g, ww in zip(bf, want):
         assert np.array_equal(u32(g)[rows], ww)
+
+
+# ------------------------------------------- per-cluster dictionaries ----
+
+@pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
+@pytest.mark.parametrize("name,P,tab,b,cap,k", CASES + [
+    ("sparse", synth.random_profiles(9600, 3000, 20000, 5, 120, 1.0), synth.hash_tables(4, 9601),
+     64, 400, 16)], ids=[c[0] for c in CASES] + ["sparse"])
+def test_local_knn_compacted(orc, name, P, tab, b, cap, k, form):
+    """The local KNN over per-cluster dictionaries (forced on) against the
+    oracle on the oracle's partition: the compaction must not change a bit."""
+    say("local_knn compact", name, form)
+    t = tab.shape[0]
+    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, orc.hash_items(tab, b, P.m), cap)
+    dP = c2.DeviceProfiles.from_synth(P)
+    dev = lambda a: torch.as_tensor(a.astype(np.uint32).view(np.int32)).cuda()
+    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), c2.params(t, b, cap, k), form,
+                           c2.tuning(compact=c2.COMPACT_ON))
+    wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
+    assert np.array_equal(u32(pid), wid)
+    assert np.array_equal(u32(pI), wI)
+
+
+def test_compaction_on_equals_off_n6k():
+    w = synth.WORKLOADS["n6k_m3.7k"]
+    P = synth.make_profiles(w)
+    dP, dtab = gpu_inputs(P, synth.hash_tables(w.t, w.hash_seed))
+    p = c2.params(w.t, w.b, w.cap, w.k)
+    on = c2.build(dP, dtab, p, c2.FORM_BATCHED, c2.tuning(split_rounds=16, compact=c2.COMPACT_ON))
+    off = c2.build(dP, dtab, p, c2.FORM_BATCHED, c2.tuning(split_rounds=16, compact=c2.COMPACT_OFF))
+    torch.cuda.synchronize()
+    for a, b2 in zip(on, off):
+        assert torch.equal(a, b2)
+
+
+def test_workload_sampled_parity_n140k(orc):
+    """140,000 users over 27,000 items (rows of 848 words: the dictionaries are
+    on by default): the graph form with the tuned schedule on sampled users
+    against the definition (top-k over the users sharing a final cluster)."""
+    from paper_2010_11497_amd import autotune
+    name = "n140k_m27k"
+    w = synth.WORKLOADS[name]
+    say("workload sampled", name)
+    P = synth.make_profiles(w)
+    tab = synth.hash_tables(w.t, w.hash_seed)
+    dP, dtab = gpu_inputs(P, tab)
+    p = c2.params(w.t, w.b, w.cap, w.k)
+    bucket = orc.hash_items(tab, w.b, w.m)
+    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, w.cap)
+    g = c2.Graph(dP, dtab, p, c2.tuning(**(autotune.load_table(name) or {})))
+    out = [u32(x) for x in g.launch()]
+    torch.cuda.synchronize()
+    g.check()
+    g.close()
+    rows = np.random.Generator(np.random.PCG64(8)).choice(P.n, size=200, replace=False)
+    want = orc.candidate_topk(P.indptr, P.indices, P.n, P.m, w.t, w.k, om, ooff, ocfg,
+                              rows=rows, threads=THREADS)
+    for a, ww in zip(out, want):
+        assert np.array_equal(a[rows], ww)
