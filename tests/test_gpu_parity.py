@@ -494,6 +494,54 @@ def test_local_knn_compacted(orc, name, P, tab, b, cap, k, form):
     assert np.array_equal(u32(pI), wI)
 
 
+def _blocks_partition(n, t, size, seed):
+    """t configurations, each a seeded permutation of the users cut into
+    consecutive clusters of `size` (members ascending inside a cluster)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    members, off, cfg = [], [0], [0]
+    for j in range(t):
+        perm = np.arange(n) if j == 0 else rng.permutation(n)
+        for a in range(0, n, size):
+            members.append(np.sort(perm[a:a + size]))
+            off.append(off[-1] + len(members[-1]))
+        cfg.append(len(off) - 1)
+    return (np.concatenate(members).astype(np.uint32), np.asarray(off, np.uint32),
+            np.asarray(cfg, np.uint32))
+
+
+@pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
+def test_local_knn_compaction_store_overflow(orc, form):
+    """More clusters want compacted rows than the store holds (it reserves
+    half of every member slot's full row): those past the end keep their full
+    rows.  Rows of 512 words; clusters of 400 users with 70-95 uniform items
+    each hold about 2 copies of an average item, so about 60 % of the items
+    are shared and every cluster's compacted width (~312 words) is below the
+    three-quarter limit while their total exceeds the store."""
+    n, m, t, k, size = 4000, 16384, 2, 10, 400
+    P = synth.random_profiles(77, n, m, 70, 95)
+    om, ooff, ocfg = _blocks_partition(n, t, size, 78)
+    W = (m + 255) // 256 * 8
+    ip = np.asarray(P.indptr)
+    want_words = 0
+    for c in range(len(ooff) - 1):
+        mem = om[ooff[c]:ooff[c + 1]]
+        items = np.concatenate([P.indices[ip[u]:ip[u + 1]] for u in mem])
+        D = int((np.bincount(items, minlength=m) >= 2).sum())
+        wc = (max(D, 1) + 255) // 256 * 8
+        assert 4 * wc <= 3 * W               # every cluster qualifies
+        want_words += len(mem) * wc
+    assert want_words > t * n * W // 2       # and together they overflow the store
+    say("local_knn compact overflow", form)
+    dP = c2.DeviceProfiles.from_synth(P)
+    dev = lambda a: torch.as_tensor(a.astype(np.uint32).view(np.int32)).cuda()
+    p = c2.params(t, 64, size, k)
+    wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
+    for mode in (c2.COMPACT_ON, c2.COMPACT_AUTO):
+        pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, c2.tuning(compact=mode))
+        assert np.array_equal(u32(pid), wid)
+        assert np.array_equal(u32(pI), wI)
+
+
 def test_compaction_on_equals_off_n6k():
     w = synth.WORKLOADS["n6k_m3.7k"]
     P = synth.make_profiles(w)
