@@ -850,126 +850,29 @@ __global__ __launch_bounds__(256, 2) void k_knn_mfma(KnnArgs a, const uint32_t *
 //
 // Only items held by at least two members of a cluster can be in an
 // intersection, so a cluster's pairwise counts need only those items (its
-// local dictionary).  For each cluster of 2..kCompactMaxS members a block
-// builds the dictionary from the members' bit rows (an item is in it when a
-// second member also has it: twice |= once & x; once |= x), numbers its items
-// in order with a prefix of popcounts, and, when the dictionary is at most
-// three quarters of the row, writes every member's row restricted to it
-// (padded to 256 items) to cbits; cw[c] then holds the compacted width.  The
-// dot products over the compacted rows equal those over the full rows.
-// Compacted copies of two members' rows (src1 may repeat src0) into this
-// wave's LDS buffers rowb and rowb + wc: the words are loaded 8 per lane per
-// member before any is used, so 16 loads are in flight.
-C2_DEV void set_local_bits(uint32_t x, uint32_t d, uint32_t base, uint32_t *rowb) {
-    while (x) {
-        const uint32_t b = __builtin_ctz(x);
-        x &= x - 1;
-        const uint32_t li = base + __popc(d & ((1u << b) - 1u));
-        atomicOr(&rowb[li >> 5], 1u << (li & 31));
-    }
-}
-
-C2_DEV void compact_rows2(const uint32_t *src0, const uint32_t *src1, bool two,
-                          const uint32_t *dm, const uint32_t *pre, uint32_t W, uint32_t lane,
-                          uint32_t *rowb, uint32_t wc) {
-    for (uint32_t w0 = lane; w0 < W; w0 += 64 * 8) {
-        uint32_t x0[8], x1[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t w = w0 + 64 * q;
-            x0[q] = w < W ? src0[w] : 0u;
-            x1[q] = (two && w < W) ? src1[w] : 0u;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t w = w0 + 64 * q;
-            if (w < W) {
-                const uint32_t d = dm[w], base = pre[w];
-                set_local_bits(x0[q] & d, d, base, rowb);
-                set_local_bits(x1[q] & d, d, base, rowb + wc);
-            }
-        }
-    }
-}
-
-// One pass of the dictionary over 4 words per thread (wbase + NT * i, i < 4):
-// groups of 8 member rows, the next group loaded while this one is folded in,
-// so 32 loads are in flight per thread.
+// local dictionary).  For each cluster of 2..kCompactMaxS members one block
+// works from the members' CSR lists (a few hundred bytes per member, where
+// the bit rows are W words):
+//   1. every item sets its bit in `once` with a returning atomicOr, and in
+//      `twice` when the bit was already set (LDS);
+//   2. an exclusive prefix of popcounts of `twice` numbers the dictionary
+//      items in item order (stored over `once`);
+//   3. when the dictionary, padded to 256 items, is at most three quarters of
+//      the row and fits the rest of the store, each wave sets the local bits
+//      of one member at a time in an LDS row buffer and writes the row to
+//      cbits; cw[c] then holds the compacted width, else 0.
+// The dot products over the compacted rows equal those over the full rows.
 template <int NT>
-C2_DEV void dict_words(const KnnArgs &a, const ClusterView &cv, const uint32_t *ubits,
-                       uint32_t W, uint32_t wbase, uint32_t *dm) {
-    const uint32_t s = cv.s;
-    uint32_t o[4] = {0, 0, 0, 0}, t2[4] = {0, 0, 0, 0};
-    uint32_t wi[4];
-    bool ok[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        wi[i] = wbase + NT * i;
-        ok[i] = wi[i] < W;
-    }
-    auto row = [&](uint32_t r) -> const uint32_t * {
-        const uint32_t u = a.members[cv.o + r];
-        return ubits + (size_t)(u < a.n ? u : a.n) * W;
-    };
-    uint32_t nx[8][4];
-    const uint32_t full = s / 8 * 8;
-    if (full) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t *rw = row(q);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) nx[q][i] = ok[i] ? rw[wi[i]] : 0u;
-        }
-    }
-    for (uint32_t r = 0; r < full; r += 8) {
-        uint32_t x[8][4];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) x[q][i] = nx[q][i];
-        if (r + 8 < full) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint32_t *rw = row(r + 8 + q);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) nx[q][i] = ok[i] ? rw[wi[i]] : 0u;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                t2[i] |= o[i] & x[q][i];
-                o[i] |= x[q][i];
-            }
-    }
-    for (uint32_t r = full; r < s; ++r) {
-        const uint32_t *rw = row(r);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t x = ok[i] ? rw[wi[i]] : 0u;
-            t2[i] |= o[i] & x;
-            o[i] |= x;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if (ok[i]) dm[wi[i]] = t2[i];
-}
-
-// NT threads per block (NT/64 waves, two row buffers each).
-template <int NT>
-__global__ __launch_bounds__(NT) void k_compact(KnnArgs a, const uint32_t *__restrict__ ubits,
-                                                uint32_t *__restrict__ cbits, uint64_t cap,
-                                                uint32_t *__restrict__ cw,
+__global__ __launch_bounds__(NT) void k_compact(KnnArgs a, uint32_t *__restrict__ cbits,
+                                                uint64_t cap, uint32_t *__restrict__ cw,
                                                 uint64_t *__restrict__ coff,
                                                 unsigned long long *ccur, uint32_t *cnext) {
-    constexpr uint32_t NWV = NT / 64;
+    constexpr uint32_t NWV = NT / 64, G = 16, NG = NT / G;
     extern __shared__ uint32_t lds[];
-    const uint32_t W = a.wmax;
-    uint32_t *dm = lds, *pre = lds + W;
+    const uint32_t W = a.wmax, RB = 3 * W / 4;  // a compacted row has at most RB words
+    uint32_t *once = lds, *twice = lds + W, *pre = lds;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    uint32_t *rowb = lds + 2 * W + wid * 2 * W;  // two row buffers per wave
+    uint32_t *rowb = lds + 2 * W + wid * RB;
     __shared__ uint32_t wsum[NT / 64 + 1];
     __shared__ unsigned long long sh_off;
     __shared__ uint32_t sh_ok, sh_c;
@@ -986,19 +889,41 @@ __global__ __launch_bounds__(NT) void k_compact(KnnArgs a, const uint32_t *__res
             if (tid == 0) cw[c] = 0;
             continue;
         }
-        // dictionary: items held by >= 2 members
-        for (uint32_t wb = tid; wb < W; wb += 4 * NT) dict_words<NT>(a, cv, ubits, W, wb, dm);
+        for (uint32_t w = tid; w < 2 * W; w += NT) lds[w] = 0;
         __syncthreads();
-        // local index of each word's first dictionary item: exclusive prefix of
-        // popcounts, each thread over a contiguous range of words
+        // 1. dictionary: 16 lanes per member, 4 items per lane in flight
+        {
+            const uint32_t sub = tid & (G - 1);
+            for (uint32_t r = tid / G; r < s; r += NG) {
+                const uint32_t u = a.members[cv.o + r];
+                if (u >= a.n) continue;
+                uint64_t p0, p1;
+                row_range(a.indptr, u, a.nnz, p0, p1);
+                for (uint64_t p = p0 + sub; p < p1; p += 4 * G) {
+                    uint32_t it[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        it[q] = p + q * G < p1 ? a.indices[p + q * G] : 0xFFFFFFFFu;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (it[q] >= a.m) continue;
+                        const uint32_t bit = 1u << (it[q] & 31);
+                        if (atomicOr(&once[it[q] >> 5], bit) & bit) atomicOr(&twice[it[q] >> 5], bit);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // 2. local index of each word's first dictionary item
         const uint32_t per = (W + NT - 1) / NT, w0 = tid * per;
         uint32_t mine = 0;
-        for (uint32_t w = w0; w < w0 + per && w < W; ++w) mine += __popc(dm[w]);
+        for (uint32_t w = w0; w < w0 + per && w < W; ++w) mine += __popc(twice[w]);
         uint32_t total;
         uint32_t run = block_excl_scan<uint32_t, NT>(mine, wsum, &total);
         for (uint32_t w = w0; w < w0 + per && w < W; ++w) {
-            pre[w] = run;
-            run += __popc(dm[w]);
+            const uint32_t c2 = __popc(twice[w]);
+            pre[w] = run;  // over `once`, which is no longer read
+            run += c2;
         }
         const uint32_t wc = ((total ? total : 1u) + 255u) / 256u * 8u;  // words, a multiple of 8
         if (tid == 0) {
@@ -1016,20 +941,33 @@ __global__ __launch_bounds__(NT) void k_compact(KnnArgs a, const uint32_t *__res
         }
         __syncthreads();
         if (!sh_ok) continue;
-        // each wave compacts two member rows at a time in its LDS buffers
-        for (uint32_t r = 2 * wid; r < s; r += 2 * NWV) {
-            const bool two = r + 1 < s;
-            for (uint32_t o2 = lane; o2 < 2 * wc; o2 += 64) rowb[o2] = 0;
+        // 3. compacted rows, one member per wave at a time
+        for (uint32_t r = wid; r < s; r += NWV) {
+            for (uint32_t o2 = lane; o2 < wc; o2 += 64) rowb[o2] = 0;
             wave_sync();
-            const uint32_t u0 = a.members[cv.o + r];
-            const uint32_t u1 = two ? a.members[cv.o + r + 1] : a.n;
-            compact_rows2(ubits + (size_t)(u0 < a.n ? u0 : a.n) * W,
-                          ubits + (size_t)(u1 < a.n ? u1 : a.n) * W, two, dm, pre, W, lane, rowb,
-                          wc);
+            const uint32_t u = a.members[cv.o + r];
+            if (u < a.n) {
+                uint64_t p0, p1;
+                row_range(a.indptr, u, a.nnz, p0, p1);
+                for (uint64_t p = p0 + lane; p < p1; p += 2 * 64) {
+                    uint32_t it[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        it[q] = p + q * 64 < p1 ? a.indices[p + q * 64] : 0xFFFFFFFFu;
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        if (it[q] >= a.m) continue;
+                        const uint32_t w = it[q] >> 5, b = it[q] & 31, d = twice[w];
+                        if ((d >> b) & 1u) {
+                            const uint32_t li = pre[w] + __popc(d & ((1u << b) - 1u));
+                            atomicOr(&rowb[li >> 5], 1u << (li & 31));
+                        }
+                    }
+                }
+            }
             wave_sync();
             uint32_t *dst = cbits + sh_off + (size_t)r * wc;
-            const uint32_t nw = two ? 2 * wc : wc;
-            for (uint32_t o2 = lane; o2 < nw; o2 += 64) dst[o2] = rowb[o2];
+            for (uint32_t o2 = lane; o2 < wc; o2 += 64) dst[o2] = rowb[o2];
             wave_sync();
         }
     }
@@ -1231,9 +1169,9 @@ size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w) {
     x.ccls = take(4 * (size_t)NE);
     x.cpos = take(4 * (size_t)NE);
     // compacted rows: room for half of every member slot's full row, at most
-    // 2^30 words (2^24 when the automatic rule leaves compaction off)
+    // 2^32 words, 16 GiB (2^24 when the automatic rule leaves compaction off)
     size_t cap = (size_t)NE * wmax / 2;
-    const size_t cmax = wmax >= kCompactMinW ? ((size_t)1 << 30) : ((size_t)1 << 24);
+    const size_t cmax = wmax >= kCompactMinW ? ((size_t)1 << 32) : ((size_t)1 << 24);
     if (cap > cmax) cap = cmax;
     x.cbits_words = cap;
     x.cbits = take(4 * cap);
@@ -1275,12 +1213,15 @@ static hipError_t plan(const KnnArgs &a, const KnnPtrs &w, const uint32_t *order
     return hipGetLastError();
 }
 
-// k_compact keeps 2 + 2 * waves rows in LDS: 8 waves up to 2048-word rows, else 4
+// k_compact's LDS: two W-word bitmaps and one 3W/4-word row buffer per wave;
+// 8 waves up to 2048-word rows, else 4
 static uint32_t compact_threads(uint32_t wmax) { return wmax <= 2048 ? 512u : 256u; }
+static size_t compact_lds(uint32_t wmax) {
+    return ((size_t)2 * wmax + (size_t)(compact_threads(wmax) / 64) * (3 * wmax / 4)) * 4;
+}
 
 static bool compact_on(const KnnArgs &a, const KnnOpts &o) {
-    const uint32_t waves = compact_threads(a.wmax) / 64;
-    if ((size_t)(2 + 2 * waves) * a.wmax * 4 + 1024 > 160 * 1024) return false;
+    if (compact_lds(a.wmax) + 1024 > 160 * 1024) return false;
     return o.compact == 2 || (o.compact == 0 && a.wmax >= kCompactMinW);
 }
 
@@ -1311,7 +1252,7 @@ static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts
 static hipError_t compact(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
     if (!compact_on(a, o)) return hipSuccess;
     const uint32_t nt = compact_threads(a.wmax);
-    const size_t lds = (size_t)(2 + 2 * (nt / 64)) * a.wmax * 4;  // dictionary, prefix, row buffers
+    const size_t lds = compact_lds(a.wmax);
     const void *fn = nt == 512 ? (const void *)k_compact<512> : (const void *)k_compact<256>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1319,11 +1260,11 @@ static hipError_t compact(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, 
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(w.ccur), 0, 4, s)) != hipSuccess) return e;
     uint32_t *cnext = reinterpret_cast<uint32_t *>(w.ccur) + 2;
     if (nt == 512)
-        hipLaunchKernelGGL(k_compact<512>, dim3(kCompactGrid), dim3(512), lds, s, a, w.rows,
-                           w.cbits, (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
+        hipLaunchKernelGGL(k_compact<512>, dim3(kCompactGrid), dim3(512), lds, s, a, w.cbits,
+                           (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
     else
-        hipLaunchKernelGGL(k_compact<256>, dim3(kCompactGrid), dim3(256), lds, s, a, w.rows,
-                           w.cbits, (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
+        hipLaunchKernelGGL(k_compact<256>, dim3(kCompactGrid), dim3(256), lds, s, a, w.cbits,
+                           (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
     return hipGetLastError();
 }
 
