@@ -372,24 +372,27 @@ struct __attribute__((aligned(16))) MfmaLds {
     uint64_t hk[kMaxK * kMR];
 };
 
-// 64 bits -> 32 bytes of e2m1 nibbles (0x2 = 1.0 for a set bit).  Dword q
-// holds bits 8q .. 8q+7, bit 8q+i in nibble 2i and bit 8q+4+i in nibble
-// 2i+1: (x * 0x408102) moves bit i of a 4-bit x to bit 8i+1 with no carries
-// (the partial products are 7 apart), and the high half is moved up 4 bits.
-// Every row is expanded the same way, so item pairs stay aligned in the dot
-// product whatever order the MFMA assigns to the nibbles.
-C2_DEV uint32_t nibbles8(uint32_t w, int s) {
-    const uint32_t x = w >> s;
-    const uint32_t y = __umul24(x & 0x0Fu, 0x408102u);
-    const uint32_t z = __umul24(x & 0xF0u, 0x408102u);  // (high half * 0x408102) << 4
-    return (z | y) & 0x22222222u;
+// 64 bits -> 32 bytes of e2m1 nibbles (0x2 = 1.0 for a set bit).  Dword s
+// of a 32-bit word w holds, in byte q, bit 8q+2s of w in its low nibble and
+// bit 8q+2s+1 in its high nibble: (w >> 2s) & 0x03030303 puts each byte's
+// 2-bit pair in the low bits of that byte, and v_perm_b32 looks the pair up
+// in a 4-byte table {0x00, 0x02, 0x20, 0x22} held in both sources (so either
+// source order gives the same bytes).  Every row is expanded the same way,
+// so item pairs stay aligned in the dot product whatever order the MFMA
+// assigns to the nibbles.
+constexpr uint32_t kPairLut = 0x22200200u;
+
+C2_DEV uint4 nibbles32(uint32_t w) {
+    return make_uint4(__builtin_amdgcn_perm(kPairLut, kPairLut, w & 0x03030303u),
+                      __builtin_amdgcn_perm(kPairLut, kPairLut, (w >> 2) & 0x03030303u),
+                      __builtin_amdgcn_perm(kPairLut, kPairLut, (w >> 4) & 0x03030303u),
+                      __builtin_amdgcn_perm(kPairLut, kPairLut, (w >> 6) & 0x03030303u));
 }
 
 C2_DEV void expand64(uint64_t bits, uint8_t *dst) {
-    const uint32_t lo = (uint32_t)bits, hi = (uint32_t)(bits >> 32);
     uint4 *d = reinterpret_cast<uint4 *>(dst);
-    d[0] = make_uint4(nibbles8(lo, 0), nibbles8(lo, 8), nibbles8(lo, 16), nibbles8(lo, 24));
-    d[1] = make_uint4(nibbles8(hi, 0), nibbles8(hi, 8), nibbles8(hi, 16), nibbles8(hi, 24));
+    d[0] = nibbles32((uint32_t)bits);
+    d[1] = nibbles32((uint32_t)(bits >> 32));
 }
 
 // Unconditional load (chunk clamped into the row) so the compiler can count
