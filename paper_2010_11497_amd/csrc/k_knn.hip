@@ -24,10 +24,9 @@ constexpr uint32_t kRowBlock = 64;   // rows (members) per bitmap work item
 constexpr int kWordChunk = 16;       // bit-row words staged per step (bitmap path)
 constexpr uint32_t kMR = 128;        // rows per MFMA work item (row owners)
 constexpr uint32_t kMC = 128;        // columns per MFMA step
-constexpr int kOpStride = 48;        // bytes per staged 64-item row of nibbles (32 + pad: no bank conflicts)
 constexpr int kTileStride = 132;     // u32 per row of the transposed result tile
 constexpr uint32_t kDefaultMfmaMin = 2;
-constexpr uint32_t kPf = 4;          // chunks of bit rows prefetched ahead (MFMA path)
+constexpr uint32_t kPf = 4;          // chunks prefetched ahead (two pairs); rows pad to kPf chunks
 constexpr uint32_t kGroupTiles = 4;  // column tiles per work item before a row block is split
 constexpr uint32_t kMaxGroups = 4;   // column groups a row block is split into at most
 constexpr uint32_t kUserBitsGrid = 512;  // blocks of k_user_bits at most
@@ -365,7 +364,7 @@ constexpr int kBisectSteps = 9;        // brackets the tile's k-th best code to 
 
 struct __attribute__((aligned(16))) MfmaLds {
     union __attribute__((aligned(16))) {
-        uint8_t op[2][kMR + kMC][kOpStride];
+        uint2 raw[2][2][kMR + kMC];  // [stage][word half][staged row]: bits of two chunks
         uint16_t itile[kMR][kTile16Stride];
     } u;
     uint32_t cuid[kMC], clen[kMC];
@@ -389,17 +388,13 @@ C2_DEV uint4 nibbles32(uint32_t w) {
                       __builtin_amdgcn_perm(kPairLut, kPairLut, (w >> 6) & 0x03030303u));
 }
 
-C2_DEV void expand64(uint64_t bits, uint8_t *dst) {
-    uint4 *d = reinterpret_cast<uint4 *>(dst);
-    d[0] = nibbles32((uint32_t)bits);
-    d[1] = nibbles32((uint32_t)(bits >> 32));
-}
+C2_DEV v4i as_v4i(uint4 x) { return v4i{(int)x.x, (int)x.y, (int)x.z, (int)x.w}; }
 
-// Unconditional load (chunk clamped into the row) so the compiler can count
-// outstanding loads; values past the row are expanded into the idle stage
-// buffer but never multiplied.
-C2_DEV uint64_t load_bits(const uint64_t *row, uint32_t chunk, uint32_t nchunks) {
-    return row[chunk < nchunks ? chunk : nchunks - 1];
+// Bits of chunks 2p and 2p+1 (row words 4p .. 4p+3).  The load is
+// unconditional (p clamped into the row) so the compiler can count outstanding
+// loads; pairs past the row are staged but never multiplied.
+C2_DEV uint4 load_pair(const uint4 *row, uint32_t p, uint32_t npairs) {
+    return row[p < npairs ? p : npairs - 1];
 }
 
 // I from key(I, U) and S = |P_u| + |P_v| (U = S - I): I/(S - I) is strictly
@@ -542,7 +537,6 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
     h.k = a.k;
     h.cnt = 0;
     h.root = 0;
-    const uint32_t hl = (lane >> 5) * 16;  // byte offset of this lane's 32 items (nibbles)
     const uint32_t tiles = (s + kMC - 1) / kMC, per = (tiles + ng - 1) / ng;
     const uint32_t cb_end = (g + 1) * per < tiles ? (g + 1) * per : tiles;
     for (uint32_t cb = g * per; cb < cb_end; ++cb) {
@@ -558,34 +552,55 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
             L.clen[t - kMR] = us < a.n ? ulen[us] : 0;
         }
         v16f acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-        // bits of chunk ch live in pf[ch % kPf] from kPf - 1 chunks before use;
-        // the loop is unrolled by kPf so every slot index is a constant
-        uint64_t pf[kPf];
+        // Staging: thread t stages its row's bits for two chunks at a time,
+        // word half h of both chunks in raw[.][h][t], so that the 32 lanes of
+        // a wave that read half h read 256 contiguous bytes.  Each wave reads
+        // the words of its 64 A rows and 64 B rows and expands them to fp4
+        // nibbles in registers right before the MFMAs: LDS carries 16 bytes
+        // per row and pair of chunks instead of 64 bytes of nibbles per row
+        // and chunk.  Pair p + 1 waits in pf[(p + 1) % 2], loaded two pairs
+        // ahead; the loop is unrolled by 2 so the slot index is a constant.
+        const uint4 *src4 = reinterpret_cast<const uint4 *>(src);
+        const uint32_t npairs = nchunks / 2;  // even: rows are padded to 4 chunks
+        uint4 pf[2];
+        pf[1] = load_pair(src4, 1, npairs);
+        {
+            const uint4 x = load_pair(src4, 0, npairs);
+            L.u.raw[0][0][t] = make_uint2(x.x, x.z);
+            L.u.raw[0][1][t] = make_uint2(x.y, x.w);
+        }
+        pf[0] = load_pair(src4, 2, npairs);
+        const uint32_t hh = lane >> 5, rr = lane & 31;
+        for (uint32_t p0 = 0; p0 < npairs; p0 += 2) {
 #pragma unroll
-        for (int q = 1; q < (int)kPf; ++q) pf[q] = load_bits(src, q, nchunks);
-        expand64(load_bits(src, 0, nchunks), L.u.op[0][t]);
-        pf[0] = load_bits(src, kPf, nchunks);
-        // nchunks is a multiple of kPf: the unrolled body has no branch, so the
-        // compiler can wait for exactly the one load each expansion needs
-        for (uint32_t ch0 = 0; ch0 < nchunks; ch0 += kPf) {
-#pragma unroll
-            for (int u = 0; u < (int)kPf; ++u) {
-                const uint32_t ch = ch0 + u;
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t pp = p0 + u;
                 lds_barrier();
-                const uint32_t st = u & 1;
-                {
-                    const v4i A0 = *reinterpret_cast<const v4i *>(&L.u.op[st][wr * 64 + (lane & 31)][hl]);
-                    const v4i A1 = *reinterpret_cast<const v4i *>(&L.u.op[st][wr * 64 + 32 + (lane & 31)][hl]);
-                    const v4i B0 = *reinterpret_cast<const v4i *>(&L.u.op[st][kMR + wc * 64 + (lane & 31)][hl]);
-                    const v4i B1 = *reinterpret_cast<const v4i *>(&L.u.op[st][kMR + wc * 64 + 32 + (lane & 31)][hl]);
+                const int st = u;
+                const uint2 a0 = L.u.raw[st][hh][wr * 64 + rr];
+                const uint2 a1 = L.u.raw[st][hh][wr * 64 + 32 + rr];
+                const uint2 b0 = L.u.raw[st][hh][kMR + wc * 64 + rr];
+                const uint2 b1 = L.u.raw[st][hh][kMR + wc * 64 + 32 + rr];
+                {  // chunk 2pp
+                    const v4i A0 = as_v4i(nibbles32(a0.x)), A1 = as_v4i(nibbles32(a1.x));
+                    const v4i B0 = as_v4i(nibbles32(b0.x)), B1 = as_v4i(nibbles32(b1.x));
                     acc00 = mfma_fp4(A0, B0, acc00);
                     acc01 = mfma_fp4(A0, B1, acc01);
                     acc10 = mfma_fp4(A1, B0, acc10);
                     acc11 = mfma_fp4(A1, B1, acc11);
                 }
-                const int nx = (u + 1) % kPf;
-                expand64(pf[nx], L.u.op[st ^ 1][t]);
-                pf[nx] = load_bits(src, ch + 1 + kPf, nchunks);
+                {  // chunk 2pp + 1
+                    const v4i A0 = as_v4i(nibbles32(a0.y)), A1 = as_v4i(nibbles32(a1.y));
+                    const v4i B0 = as_v4i(nibbles32(b0.y)), B1 = as_v4i(nibbles32(b1.y));
+                    acc00 = mfma_fp4(A0, B0, acc00);
+                    acc01 = mfma_fp4(A0, B1, acc01);
+                    acc10 = mfma_fp4(A1, B0, acc10);
+                    acc11 = mfma_fp4(A1, B1, acc11);
+                }
+                const int nx = (u + 1) & 1;
+                L.u.raw[st ^ 1][0][t] = make_uint2(pf[nx].x, pf[nx].z);
+                L.u.raw[st ^ 1][1][t] = make_uint2(pf[nx].y, pf[nx].w);
+                pf[nx] = load_pair(src4, pp + 3, npairs);
             }
         }
         __syncthreads();
