@@ -23,7 +23,7 @@ TABLE_DIR = os.path.join(HERE, "tuning")
 GRID = {
     "persistent_wgs": [256, 384, 512, 768, 1024],
     "mfma_min_rows": [2],
-    "group_tiles": [1, 2, 4, 8, 16, 32],
+    "group_tiles": [1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 24, 32],
 }
 
 

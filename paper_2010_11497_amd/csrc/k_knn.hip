@@ -300,6 +300,7 @@ __global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *ub
     __shared__ BitmapLds L;
     __shared__ uint32_t next;
     const uint32_t total = *n_items;
+    if (total == 0) return;  // the usual case: every cluster is on the MFMA path
     if (!cursor) {
         if (blockIdx.x >= total) return;
         const uint64_t it = items[blockIdx.x];
@@ -321,10 +322,11 @@ __global__ __launch_bounds__(64) void k_knn_bitmap(KnnArgs a, const uint32_t *ub
 //
 // One block of 4 waves per work item (cluster, block of 128 rows).  For every
 // 128-column tile of the cluster the block computes the 128 x 128 matrix of
-// intersection counts: 256 threads each expand one staged row's next 64 bits
-// into 64 bytes of 0/1 (double-buffered in LDS), and each wave multiplies a
-// 64 x 64 sub-tile as 2 x 2 fp4 MFMAs of 32 x 32 x 64.  The counts are written
-// to LDS transposed (16 bits each) so that thread t < 128 reads row t.
+// intersection counts: 256 threads stage their rows' raw bits in LDS two
+// 64-item chunks at a time (double-buffered), and each wave expands the words
+// of its 64 rows and 64 columns to fp4 nibbles in registers and multiplies
+// its 64 x 64 sub-tile as 2 x 2 MFMAs of 32 x 32 x 64.  The counts are written
+// to LDS transposed (16 bits each) so that the thread pair of row r reads it.
 //
 // Selection on this path uses an exact 32-bit similarity key,
 //   key(I, U) = floor(I * (2^32 - 1) / U),
