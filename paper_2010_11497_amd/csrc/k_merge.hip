@@ -65,8 +65,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
             for (int q = 0; q < 16; ++q) {
                 const uint32_t e = e0 + q * kMergeThreads + lane;
                 if (e >= total) continue;
-                const uint32_t ul = e / tk, rem = e % tk;
-                const uint32_t d = (ul * G + rem / k) * k + rem % k;
+                // entry e = ul*tk + j*k + r goes to slot (ul*G + j)*k + r
+                const uint32_t ul = e / tk;
+                const uint32_t d = e + ul * (G - t) * k;
                 const bool ok = v[q] < n;
                 // the row bounds clamped as row_range does
                 const int64_t lb = b0[q] < 0 ? 0 : b0[q];

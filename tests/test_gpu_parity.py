@@ -542,6 +542,26 @@ def test_local_knn_compaction_store_overflow(orc, form):
         assert np.array_equal(u32(pI), wI)
 
 
+@pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
+def test_local_knn_compacted_widest_rows(orc, form):
+    """The largest item universe (m = 131072: rows of 4096 words, where the
+    dictionary pass runs with 256 threads and its LDS is largest), dictionaries
+    forced on and automatic, against the oracle on the oracle's partition."""
+    n, m, t, b, cap, k = 1500, 131072, 3, 16, 300, 12
+    P = synth.random_profiles(91, n, m, 20, 400, 0.9)
+    tab = synth.hash_tables(t, 92)
+    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, orc.hash_items(tab, b, P.m), cap)
+    say("local_knn compact widest", form)
+    dP = c2.DeviceProfiles.from_synth(P)
+    dev = lambda a: torch.as_tensor(a.astype(np.uint32).view(np.int32)).cuda()
+    wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
+    for mode in (c2.COMPACT_ON, c2.COMPACT_AUTO):
+        pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), c2.params(t, b, cap, k), form,
+                               c2.tuning(compact=mode))
+        assert np.array_equal(u32(pid), wid)
+        assert np.array_equal(u32(pI), wI)
+
+
 def test_compaction_on_equals_off_n6k():
     w = synth.WORKLOADS["n6k_m3.7k"]
     P = synth.make_profiles(w)
