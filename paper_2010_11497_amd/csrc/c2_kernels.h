@@ -75,7 +75,7 @@ struct ClusterArgs {
 size_t cluster_ws_elems(const ClusterDims &d, ClusterWs *w);
 // one workgroup per configuration (n <= kWgMaxN), all split rounds in LDS
 constexpr uint32_t kWgMaxN = 8192;
-constexpr int kSigD = 8;  // smallest distinct hash values kept per (configuration, user)
+constexpr int kSigD = 4;  // smallest distinct hash values kept per (configuration, user)
 size_t cluster_wg_ws_bytes(uint32_t n, uint32_t t);
 bool cluster_wg_fits(uint32_t n, uint32_t b);
 hipError_t cluster_wg_run(const ClusterArgs &a, uint32_t *members, uint32_t *cl_off,
