@@ -1076,38 +1076,57 @@ __global__ __launch_bounds__(256) void k_plan_fill(KnnArgs a, const uint32_t *or
 // class counter, and scratch slots (split row blocks) and bitmap items by
 // atomics on their counters; k_user_bits cleared the counters.  The order of
 // clusters inside a class changes only the schedule, never a result.
+// Positions inside each class come from per-block counts in LDS, then one
+// global atomic per (block, counter): with one global atomic per cluster,
+// thousands of clusters of one class serialise on one address.  The order
+// of items inside a class is arbitrary either way.
 __global__ __launch_bounds__(256) void k_plan_classes(KnnArgs a, uint32_t mfma_min,
                                                       uint32_t group_tiles,
                                                       const uint32_t *bmax, uint32_t nbmax,
                                                       uint32_t *pc, uint32_t *ccls,
                                                       uint32_t *cpos, uint32_t *sbase) {
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t lcnt[kPlanCtr], lbase[kPlanCtr];
+    for (uint32_t q = threadIdx.x; q < kPlanCtr; q += blockDim.x) lcnt[q] = 0;
+    // (block_max_len begins with a barrier, which also orders the zeroing)
     if (block_max_len(bmax, nbmax) >= kMfmaMaxLen) mfma_min = 0xFFFFFFFFu;
-    if (c >= a.NE || c >= a.cl_cfg_off[a.t]) return;
-    const ClusterView cv = view(a, c);
-    uint32_t cls = 0xFFFFFFFFu, pos = 0;
-    if (cv.s >= mfma_min && cv.s >= 2) {
-        const uint32_t ng = mfma_groups(cv.s, group_tiles);
-        const uint32_t tiles = (cv.s + kMC - 1) / kMC, per = (tiles + ng - 1) / ng;
-        const uint32_t nit = ((cv.s + kMR - 1) / kMR) * ng;
-        cls = kCostClasses - 1 - (per < kCostClasses - 1 ? per : kCostClasses - 1);
-        pos = atomicAdd(&pc[cls], nit);
-        if (ng > 1) sbase[c] = atomicAdd(&pc[kSlotCtr], nit);
-    } else if (cv.s >= 2) {
-        cls = kCostClasses;
-        pos = atomicAdd(&pc[kBitmapCtr], (cv.s + kRowBlock - 1) / kRowBlock);
-    } else if (cv.s == 1) {
-        const uint32_t u = member(a, cv, 0);
-        if (u < a.n && cv.j < a.t) {
-            const size_t base = ((size_t)u * a.t + cv.j) * a.k;
-            for (uint32_t r = 0; r < a.k; ++r) {
-                a.part_id[base + r] = kPad;
-                a.part_I[base + r] = 0;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = c < a.NE && c < a.cl_cfg_off[a.t];
+    uint32_t cls = 0xFFFFFFFFu, ctr = 0, lpos = 0, lslot = 0;
+    bool split = false;
+    if (live) {
+        const ClusterView cv = view(a, c);
+        if (cv.s >= mfma_min && cv.s >= 2) {
+            const uint32_t ng = mfma_groups(cv.s, group_tiles);
+            const uint32_t tiles = (cv.s + kMC - 1) / kMC, per = (tiles + ng - 1) / ng;
+            const uint32_t nit = ((cv.s + kMR - 1) / kMR) * ng;
+            cls = kCostClasses - 1 - (per < kCostClasses - 1 ? per : kCostClasses - 1);
+            ctr = cls;
+            lpos = atomicAdd(&lcnt[cls], nit);
+            split = ng > 1;
+            if (split) lslot = atomicAdd(&lcnt[kSlotCtr], nit);
+        } else if (cv.s >= 2) {
+            cls = kCostClasses;
+            ctr = kBitmapCtr;
+            lpos = atomicAdd(&lcnt[kBitmapCtr], (cv.s + kRowBlock - 1) / kRowBlock);
+        } else if (cv.s == 1) {
+            const uint32_t u = member(a, cv, 0);
+            if (u < a.n && cv.j < a.t) {
+                const size_t base = ((size_t)u * a.t + cv.j) * a.k;
+                for (uint32_t r = 0; r < a.k; ++r) {
+                    a.part_id[base + r] = kPad;
+                    a.part_I[base + r] = 0;
+                }
             }
         }
     }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < kPlanCtr; q += blockDim.x)
+        lbase[q] = lcnt[q] ? atomicAdd(&pc[q], lcnt[q]) : 0u;
+    __syncthreads();
+    if (!live) return;
+    if (split) sbase[c] = lbase[kSlotCtr] + lslot;
     ccls[c] = cls;
-    cpos[c] = pos;
+    cpos[c] = cls == 0xFFFFFFFFu ? 0u : lbase[ctr] + lpos;
 }
 
 __global__ __launch_bounds__(256) void k_plan_items(KnnArgs a, uint32_t group_tiles,
