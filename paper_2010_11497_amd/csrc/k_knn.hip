@@ -882,8 +882,13 @@ __global__ __launch_bounds__(256, 2) void k_knn_mfma(KnnArgs a, const uint32_t *
 //      of one member at a time in an LDS row buffer and writes the row to
 //      cbits; cw[c] then holds the compacted width, else 0.
 // The dot products over the compacted rows equal those over the full rows.
+// Clusters come from the MFMA work list, each at its first item (row block 0,
+// group 0): in the batched form the list is costliest first, so the largest
+// clusters start first and do not trail at the end of the pass.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_compact(KnnArgs a, uint32_t *__restrict__ cbits,
+__global__ __launch_bounds__(NT) void k_compact(KnnArgs a, const uint64_t *__restrict__ items,
+                                                const uint32_t *n_items,
+                                                uint32_t *__restrict__ cbits,
                                                 uint64_t cap, uint32_t *__restrict__ cw,
                                                 uint64_t *__restrict__ coff,
                                                 unsigned long long *ccur, uint32_t *cnext) {
@@ -896,13 +901,19 @@ __global__ __launch_bounds__(NT) void k_compact(KnnArgs a, uint32_t *__restrict_
     __shared__ uint32_t wsum[NT / 64 + 1];
     __shared__ unsigned long long sh_off;
     __shared__ uint32_t sh_ok, sh_c;
-    const uint32_t ncl = a.cl_cfg_off[a.t];
+    const uint32_t total_items = *n_items;
     for (;;) {
         __syncthreads();
-        if (tid == 0) sh_c = atomicAdd(cnext, 1u);
+        if (tid == 0) {
+            const uint32_t i = atomicAdd(cnext, 1u);
+            // cluster of the item, or ~0 past the end; 0xFFFFFFFE: not a first item
+            sh_c = i >= total_items ? 0xFFFFFFFFu
+                   : ((uint32_t)items[i] >> 4) == 0 ? (uint32_t)(items[i] >> 32) : 0xFFFFFFFEu;
+        }
         __syncthreads();
         const uint32_t c = sh_c;
-        if (c >= ncl) break;
+        if (c == 0xFFFFFFFFu) break;
+        if (c == 0xFFFFFFFEu) continue;
         const ClusterView cv = view(a, c);
         const uint32_t s = cv.s;
         if (s < 2 || s > kCompactMaxS) {
@@ -1299,19 +1310,20 @@ static hipError_t compact(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, 
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(w.ccur), 0, 4, s)) != hipSuccess) return e;
     uint32_t *cnext = reinterpret_cast<uint32_t *>(w.ccur) + 2;
     if (nt == 512)
-        hipLaunchKernelGGL(k_compact<512>, dim3(kCompactGrid), dim3(512), lds, s, a, w.cbits,
-                           (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
+        hipLaunchKernelGGL(k_compact<512>, dim3(kCompactGrid), dim3(512), lds, s, a, w.items_m,
+                           w.ctr, w.cbits, (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
     else
-        hipLaunchKernelGGL(k_compact<256>, dim3(kCompactGrid), dim3(256), lds, s, a, w.cbits,
-                           (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
+        hipLaunchKernelGGL(k_compact<256>, dim3(kCompactGrid), dim3(256), lds, s, a, w.items_m,
+                           w.ctr, w.cbits, (uint64_t)w.cbits_words, w.cw, w.coff, w.ccur, cnext);
     return hipGetLastError();
 }
 
 hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
     hipError_t e = user_bits(a, w, s);
     if (e != hipSuccess) return e;
-    if ((e = compact(a, w, o, s)) != hipSuccess) return e;
     if ((e = plan(a, w, nullptr, o, false, s)) != hipSuccess) return e;
+    // the dictionaries take their clusters from the work list the plan wrote
+    if ((e = compact(a, w, o, s)) != hipSuccess) return e;
     uint32_t n[2] = {0, 0};
     e = hipMemcpyAsync(n, w.ctr, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1322,7 +1334,6 @@ hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipSt
 hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s) {
     hipError_t e = user_bits(a, w, s);
     if (e != hipSuccess) return e;
-    if ((e = compact(a, w, o, s)) != hipSuccess) return e;
     // items by cost class, costliest first (the size-ordered queue of
     // Section II-F), without a sort
     const dim3 g((uint32_t)div_up(a.NE, 256));
@@ -1333,6 +1344,8 @@ hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hip
     hipLaunchKernelGGL(k_plan_items, g, dim3(256), 0, s, a, gt, w.pc, w.ccls, w.cpos, w.sbase,
                        w.items_m, w.items_b, w.rb_done, w.ctr, w.ctr + 2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the dictionaries take their clusters from that list, largest first
+    if ((e = compact(a, w, o, s)) != hipSuccess) return e;
     const uint32_t gm = o.persistent_wgs ? o.persistent_wgs : 512;
     return launch_paths(a, w, o, gm, kBitmapPersistent, true, s);
 }
