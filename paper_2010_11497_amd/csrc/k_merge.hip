@@ -14,9 +14,11 @@ namespace c2 {
 
 constexpr int kMergeThreads = 64;
 
-// One wave of 64 lanes serves 64/G users.  The wave first copies its users'
-// t lists (contiguous in part_*) into LDS with U computed, coalesced; the
-// selection loop then runs from LDS.
+// One wave of 64 lanes serves 32/G users (one if G = 64): all 64 lanes copy
+// the users' t lists (contiguous in part_*) into LDS with U computed,
+// coalesced, in one pass of loads; the selection loop then runs from LDS on
+// the first 32 lanes.  Half the users per wave (rather than 64/G) doubles
+// the waves in flight, which the latency-bound staging needs.
 template <int G>
 __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restrict__ indptr,
                                                          uint64_t nnz, uint32_t n, uint32_t t,
@@ -26,7 +28,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
                                                          uint32_t *__restrict__ knn_id,
                                                          uint32_t *__restrict__ knn_I,
                                                          uint32_t *__restrict__ knn_U) {
-    constexpr int UPW = kMergeThreads / G;  // users per wave
+    constexpr int UPW = G <= kMergeThreads / 2 ? kMergeThreads / G / 2 : 1;  // users per wave
     __shared__ uint32_t sv[UPW * G * kMaxK], sI[UPW * G * kMaxK], sU[UPW * G * kMaxK];
     const uint32_t lane = threadIdx.x;
     const uint64_t u0 = (uint64_t)blockIdx.x * UPW;
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
     __syncthreads();
     const uint32_t ul = lane / G, j = lane % G;
     const uint64_t u = u0 + ul;
-    if (u >= n) return;
+    if (ul >= (uint32_t)UPW || u >= n) return;
     const uint32_t lb = (ul * G + j) * k;
     uint32_t ptr = 0, hv = kPad, hI = 0, hU = 0;
     auto load = [&]() {
@@ -132,7 +134,8 @@ hipError_t launch_merge(const int64_t *indptr, uint64_t nnz, uint32_t n, uint32_
                         uint32_t *knn_I, uint32_t *knn_U, hipStream_t s) {
     uint32_t G = 1;
     while (G < t) G <<= 1;
-    const dim3 grid((uint32_t)div_up((uint64_t)n * G, kMergeThreads));
+    const uint32_t upw = G <= kMergeThreads / 2 ? kMergeThreads / G / 2 : 1;
+    const dim3 grid((uint32_t)div_up((uint64_t)n, upw));
 #define C2_MERGE(GG)                                                                           \
     case GG:                                                                                   \
         hipLaunchKernelGGL(k_merge<GG>, grid, dim3(kMergeThreads), 0, s, indptr, nnz, n, t, k,  \
