@@ -75,16 +75,20 @@ __global__ __launch_bounds__(kStageThreads) void k_user_bits(const int64_t *__re
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t *rb = lds + wid * Wg;
     uint32_t longest = 0;
-    for (uint32_t u = blockIdx.x * kStageWaves + wid; u <= n; u += gridDim.x * kStageWaves) {
+    // the next user's row range is loaded while this user's row is built
+    const uint32_t step = gridDim.x * kStageWaves;
+    uint32_t u = blockIdx.x * kStageWaves + wid;
+    uint64_t na = 0, ne = 0;
+    if (u < n) row_range(indptr, u, nnz, na, ne);
+    for (; u <= n; u += step) {
+        const uint64_t p0 = na, p1 = ne;
+        na = ne = 0;
+        if ((uint64_t)u + step < n) row_range(indptr, u + step, nnz, na, ne);
         for (uint32_t w = lane; w < Wg; w += 64) rb[w] = 0;
         wave_sync();
-        uint64_t p0 = 0, p1 = 0;
-        if (u < n) {
-            row_range(indptr, u, nnz, p0, p1);
-            for (uint64_t p = p0 + lane; p < p1; p += 64) {
-                const uint32_t i = indices[p];
-                if (i < m) atomicOr(&rb[i >> 5], 1u << (i & 31));
-            }
+        for (uint64_t p = p0 + lane; p < p1; p += 64) {
+            const uint32_t i = indices[p];
+            if (i < m) atomicOr(&rb[i >> 5], 1u << (i & 31));
         }
         wave_sync();
         uint32_t *out = ubits + (size_t)u * Wg;
@@ -922,14 +926,20 @@ __global__ __launch_bounds__(NT) void k_compact(KnnArgs a, const uint64_t *__res
         }
         for (uint32_t w = tid; w < 2 * W; w += NT) lds[w] = 0;
         __syncthreads();
-        // 1. dictionary: 16 lanes per member, 4 items per lane in flight
+        // 1. dictionary: 16 lanes per member, 4 items per lane in flight; the
+        //    next member's row range and the id after it are loaded while the
+        //    current member's items are folded in
         {
-            const uint32_t sub = tid & (G - 1);
-            for (uint32_t r = tid / G; r < s; r += NG) {
-                const uint32_t u = a.members[cv.o + r];
-                if (u >= a.n) continue;
-                uint64_t p0, p1;
-                row_range(a.indptr, u, a.nnz, p0, p1);
+            const uint32_t sub = tid & (G - 1), r0 = tid / G;
+            uint64_t na = 0, ne = 0;
+            uint32_t nu = r0 < s ? a.members[cv.o + r0] : a.n;
+            if (nu < a.n) row_range(a.indptr, nu, a.nnz, na, ne);
+            nu = r0 + NG < s ? a.members[cv.o + r0 + NG] : a.n;
+            for (uint32_t r = r0; r < s; r += NG) {
+                const uint64_t p0 = na, p1 = ne;
+                na = ne = 0;
+                if (nu < a.n) row_range(a.indptr, nu, a.nnz, na, ne);
+                nu = r + 2 * NG < s ? a.members[cv.o + r + 2 * NG] : a.n;
                 for (uint64_t p = p0 + sub; p < p1; p += 4 * G) {
                     uint32_t it[4];
 #pragma unroll
@@ -972,27 +982,31 @@ __global__ __launch_bounds__(NT) void k_compact(KnnArgs a, const uint64_t *__res
         }
         __syncthreads();
         if (!sh_ok) continue;
-        // 3. compacted rows, one member per wave at a time
+        // 3. compacted rows, one member per wave at a time, with the next
+        //    member's row range and the id after it in flight as in step 1
+        uint64_t na = 0, ne = 0;
+        uint32_t nu = wid < s ? a.members[cv.o + wid] : a.n;
+        if (nu < a.n) row_range(a.indptr, nu, a.nnz, na, ne);
+        nu = wid + NWV < s ? a.members[cv.o + wid + NWV] : a.n;
         for (uint32_t r = wid; r < s; r += NWV) {
+            const uint64_t p0 = na, p1 = ne;
+            na = ne = 0;
+            if (nu < a.n) row_range(a.indptr, nu, a.nnz, na, ne);
+            nu = r + 2 * NWV < s ? a.members[cv.o + r + 2 * NWV] : a.n;
             for (uint32_t o2 = lane; o2 < wc; o2 += 64) rowb[o2] = 0;
             wave_sync();
-            const uint32_t u = a.members[cv.o + r];
-            if (u < a.n) {
-                uint64_t p0, p1;
-                row_range(a.indptr, u, a.nnz, p0, p1);
-                for (uint64_t p = p0 + lane; p < p1; p += 2 * 64) {
-                    uint32_t it[2];
+            for (uint64_t p = p0 + lane; p < p1; p += 2 * 64) {
+                uint32_t it[2];
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
-                        it[q] = p + q * 64 < p1 ? a.indices[p + q * 64] : 0xFFFFFFFFu;
+                for (int q = 0; q < 2; ++q)
+                    it[q] = p + q * 64 < p1 ? a.indices[p + q * 64] : 0xFFFFFFFFu;
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        if (it[q] >= a.m) continue;
-                        const uint32_t w = it[q] >> 5, b = it[q] & 31, d = twice[w];
-                        if ((d >> b) & 1u) {
-                            const uint32_t li = pre[w] + __popc(d & ((1u << b) - 1u));
-                            atomicOr(&rowb[li >> 5], 1u << (li & 31));
-                        }
+                for (int q = 0; q < 2; ++q) {
+                    if (it[q] >= a.m) continue;
+                    const uint32_t w = it[q] >> 5, b = it[q] & 31, d = twice[w];
+                    if ((d >> b) & 1u) {
+                        const uint32_t li = pre[w] + __popc(d & ((1u << b) - 1u));
+                        atomicOr(&rowb[li >> 5], 1u << (li & 31));
                     }
                 }
             }
