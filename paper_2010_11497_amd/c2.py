@@ -175,8 +175,12 @@ COMPACT_AUTO, COMPACT_OFF, COMPACT_ON = 0, 1, 2
 
 def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0, group_tiles=0,
            cluster_path=CLUSTER_AUTO, events=None, compact=COMPACT_AUTO) -> Tuning:
-    """events: optional (begin, end) torch.cuda.Event(enable_timing=True) pair
-    recorded around the local-KNN kernel."""
+    """Schedule fields of c2_tuning (0 = the library's default; include/c2.h
+    documents each).  compact: COMPACT_AUTO (per-cluster item dictionaries
+    when bit rows reach 512 words), COMPACT_OFF or COMPACT_ON; results are
+    the same either way.  events: optional (begin, end)
+    torch.cuda.Event(enable_timing=True) pair recorded around the local-KNN
+    kernel."""
     tu = Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), int(group_tiles),
                 int(cluster_path), None, None, int(compact))
     if events is not None:
