@@ -331,7 +331,8 @@ c2_status c2_embag_backward(const c2_profiles *P, const uint32_t *rows, uint32_t
  * data needs, then captures the batched build with that many rounds (plus
  * one) on `stream`.  Launch replays it (asynchronous); after it, the result is
  * valid if c2_check_complete(ws) is C2_OK (data changed in place may need
- * more rounds).  Destroy releases the graph (host handle). */
+ * more rounds).  Destroy releases the graph (host handle) and frees it even
+ * when the runtime reports an error, which it returns as C2_E_HIP. */
 typedef struct c2_graph c2_graph;
 c2_status c2_graph_create(const c2_profiles *P, const uint64_t *tab, const c2_params *p,
                           const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I,

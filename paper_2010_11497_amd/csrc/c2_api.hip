@@ -743,7 +743,7 @@ c2_status c2_graph_create(const c2_profiles *P, const uint64_t *tab, const c2_pa
     hipStream_t cap;
     C2_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
     c2_graph *g = new (std::nothrow) c2_graph;
-    if (!g) { hipStreamDestroy(cap); return fail(C2_E_ARG, "out of host memory"); }
+    if (!g) { (void)hipStreamDestroy(cap); return fail(C2_E_ARG, "out of host memory"); }
     g->rounds = rounds + 1;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
@@ -757,14 +757,15 @@ c2_status c2_graph_create(const c2_profiles *P, const uint64_t *tab, const c2_pa
             e2 = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
             if (e2 != hipSuccess) st = hip_fail(e2, "graph instantiate");
         } else if (graph) {
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             graph = nullptr;
         }
-        if (st != C2_OK && graph) hipGraphDestroy(graph);
+        if (st != C2_OK && graph) (void)hipGraphDestroy(graph);
     } else {
         st = hip_fail(e, "begin capture");
     }
-    hipStreamDestroy(cap);
+    const hipError_t ed = hipStreamDestroy(cap);
+    if (st == C2_OK && ed != hipSuccess) st = hip_fail(ed, "capture stream destroy");
     if (st != C2_OK) {
         delete g;
         return st;
@@ -781,9 +782,11 @@ c2_status c2_graph_launch(c2_graph *g, void *stream) {
 
 c2_status c2_graph_destroy(c2_graph *g) {
     if (!g) return C2_OK;
-    hipGraphExecDestroy(g->exec);
-    hipGraphDestroy(g->graph);
+    const hipError_t e1 = hipGraphExecDestroy(g->exec);
+    const hipError_t e2 = hipGraphDestroy(g->graph);
     delete g;
+    if (e1 != hipSuccess) return hip_fail(e1, "graph exec destroy");
+    if (e2 != hipSuccess) return hip_fail(e2, "graph destroy");
     return C2_OK;
 }
 

@@ -45,7 +45,6 @@ C2_DEV uint32_t bag_sum_wide(const int64_t *indptr, const uint32_t *indices, uin
     for (uint64_t c = a; c < e; c += 64) {
         const uint32_t cnt = (uint32_t)(e - c < 64 ? e - c : 64);
         const uint32_t mine = (uint32_t)lane < cnt ? indices[c + lane] : 0xFFFFFFFFu;
-#pragma unroll 4
         for (uint32_t q = 0; q < cnt; q += 8) {
             const uint32_t i = __shfl(mine, (int)(q + g));
             if (q + g < cnt && i < m) {

@@ -24,7 +24,6 @@ constexpr uint32_t kRowBlock = 64;   // rows (members) per bitmap work item
 constexpr int kWordChunk = 16;       // bit-row words staged per step (bitmap path)
 constexpr uint32_t kMR = 128;        // rows per MFMA work item (row owners)
 constexpr uint32_t kMC = 128;        // columns per MFMA step
-constexpr int kTileStride = 132;     // u32 per row of the transposed result tile
 constexpr uint32_t kDefaultMfmaMin = 2;
 constexpr uint32_t kPf = 4;          // chunks prefetched ahead (two pairs); rows pad to kPf chunks
 constexpr uint32_t kGroupTiles = 4;  // column tiles per work item before a row block is split
@@ -627,10 +626,9 @@ C2_DEV void mfma_item(const KnnArgs &a, const uint32_t *ubits, const uint32_t *u
         {
             const uint32_t ncol = s - cb * kMC < kMC ? s - cb * kMC : kMC;
             const uint32_t self = ra - cb * kMC;  // column index of the row's own member
-            // the owner's heap state, shared with its helper lane
-            const uint32_t rlo = __shfl((uint32_t)h.root, lane & ~1u);
+            // the owner's heap state, shared with its helper lane (the root's
+            // key word is all the filter needs)
             const uint32_t rhi = __shfl((uint32_t)(h.root >> 32), lane & ~1u);
-            const uint64_t root = ((uint64_t)rhi << 32) | rlo;
             const bool full = __shfl((int)h.full(), lane & ~1u) != 0;
             // sigma = key_T / (2^32 - 1 + key_T): I >= sigma * (|P_u| + |P_v|) is necessary
             const float kt = (float)rhi;
