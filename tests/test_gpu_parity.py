@@ -574,12 +574,14 @@ def test_compaction_on_equals_off_n6k():
         assert torch.equal(a, b2)
 
 
-def test_workload_sampled_parity_n140k(orc):
-    """140,000 users over 27,000 items (rows of 848 words: the dictionaries are
-    on by default): the graph form with the tuned schedule on sampled users
-    against the definition (top-k over the users sharing a final cluster)."""
+@pytest.mark.parametrize("name", ["n140k_m27k", "n500k_m50k"])
+def test_workload_sampled_parity_large(orc, name):
+    """140,000 users over 27,000 items and 500,000 over 50,000 (rows of 848 and
+    1568 words: the dictionaries are on by default, and at 500,000 users the
+    compacted-row store is at its largest): the graph form with the tuned
+    schedule on sampled users against the definition (top-k over the users
+    sharing a final cluster)."""
     from paper_2010_11497_amd import autotune
-    name = "n140k_m27k"
     w = synth.WORKLOADS[name]
     say("workload sampled", name)
     P = synth.make_profiles(w)
