@@ -28,7 +28,7 @@ constexpr uint32_t kDefaultMfmaMin = 2;
 constexpr uint32_t kPf = 4;          // chunks prefetched ahead (two pairs); rows pad to kPf chunks
 constexpr uint32_t kGroupTiles = 4;  // column tiles per work item before a row block is split
 constexpr uint32_t kMaxGroups = 4;   // column groups a row block is split into at most
-constexpr uint32_t kUserBitsGrid = 512;  // blocks of k_user_bits at most
+constexpr uint32_t kUserBitsGrid = 2048;  // blocks of k_user_bits at most
 constexpr uint32_t kBitmapPersistent = 256;  // persistent bitmap-path workgroups (batched form)
 // batched planning counters: kCostClasses item counts, then scratch slots and
 // bitmap items
