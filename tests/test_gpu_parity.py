@@ -140,7 +140,7 @@ def test_cluster_random(orc, name, P, tab, b, cap, k, form, path):
 @pytest.mark.parametrize("path", list(CPATHS))
 def test_cluster_identical_profiles_deep(orc, path):
     # 40 identical users with 30 distinct hash values: a chain of splits deeper
-    # than the workgroup path's 8 precomputed values per user
+    # than the workgroup path's 4 precomputed values per user
     say("cluster deep chain", path)
     sets = [set(range(30))] * 40
     P = synth.profiles_from_sets(sets, 30)
