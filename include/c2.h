@@ -56,12 +56,12 @@ typedef int32_t c2_status;
 #define C2_E_PROFILE (-2)      /* profile data invalid (c2_validate only) */
 #define C2_E_WORKSPACE (-3)    /* workspace smaller than c2_workspace_bytes */
 #define C2_E_HIP (-4)          /* a HIP runtime call failed */
-#define C2_E_UNSUPPORTED (-5)  /* sizes outside what this build supports */
+#define C2_E_UNSUPPORTED (-5)  /* sizes outside what the library supports */
 #define C2_E_INCOMPLETE (-6)   /* batched clustering needed more split rounds */
 
 #define C2_PAD 0xFFFFFFFFu     /* padding id in neighbour lists */
 
-/* Limits of this build: n <= 2^31 - 1 users and t*n < 2^32, m <= 131072 items,
+/* Limits of the library: n <= 2^31 - 1 users and t*n < 2^32, m <= 131072 items,
  * nnz < 2^40, every profile shorter than 2^20 items, 1 <= t <= 64,
  * 1 <= b <= 2^24, cap >= 1, 1 <= k <= 32. */
 
