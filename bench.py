@@ -273,6 +273,35 @@ def hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np, bf, rho=5):
     return res
 
 
+def learned_graph(args, A, dP, tab, p, gap, tb, W, ref, c2, torch, learned):
+    """The batched learned build captured once as a graph and replayed: the
+    time per replay, and whether every replay (checked after each, with the
+    split-round status) equals the eager batched result `ref`."""
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, capture_error_mode="thread_local"):
+            gout, gws = learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W,
+                                      check=False, with_ws=True)
+        equal = True
+        for _ in range(max(args.warmup, 2)):
+            g.replay()
+            torch.cuda.synchronize()
+            c2.check_complete(gws)
+            equal &= all(torch.equal(a, b) for a, b in zip(gout, ref))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        c2.check_complete(gws)
+        equal &= all(torch.equal(a, b) for a, b in zip(gout, ref))
+        del g
+        return {"build_ms_graph": ms, "graph_equals_eager": bool(equal)}
+    except Exception as e:  # report, do not lose the rest of the leg
+        return {"build_ms_graph": None, "graph_error": str(e)[:200]}
+
+
 def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_ms, batched_ms):
     """The learned cluster assigner: trained here on exact KNN edges of a
     100,000-user subsample, then the learned-assignment build (assignment,
@@ -308,6 +337,7 @@ def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_m
                 out = learned.build(A, dP, tabT, pT, gap, form, tu, weights=W)
             torch.cuda.synchronize()
             entry[key] = (time.perf_counter() - t1) * 1e3 / args.steps
+        entry.update(learned_graph(args, A, dP, tabT, pT, gap, tb, W, out, c2, torch, learned))
         q = None
         if bf is not None:
             q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
@@ -315,7 +345,10 @@ def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_m
         entry["quality"] = q
         res["min_gap"][str(gap)] = entry
         log("learned assigner (t=%d, N=%d, min_gap %.1f): plain %.3f ms, batched %.3f ms, "
-            "quality %s" % (T, cap, gap, entry["build_ms_plain"], entry["build_ms_batched"], q))
+            "graph %s ms (equal %s), quality %s" % (T, cap, gap, entry["build_ms_plain"],
+                                                   entry["build_ms_batched"],
+                                                   entry.get("build_ms_graph"),
+                                                   entry.get("graph_equals_eager"), q))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):

@@ -147,17 +147,21 @@ def train(A: Assigner, P: c2.DeviceProfiles, pairs: np.ndarray, steps: int = 400
 
 def build(A: Assigner, P: c2.DeviceProfiles, tab: torch.Tensor, p: c2.Params,
           min_gap: float = 0.0, form=c2.FORM_PLAIN, tune: Optional[c2.Tuning] = None,
-          weights=None):
+          weights=None, check: bool = True, with_ws: bool = False):
     """The learned-assignment build: keys (FastRandomHash fallback below
     min_gap), clustering from keys with FastRandomHash splits, local KNN,
-    merge.  p.b is FastRandomHash's bucket count; the keys span 2*max(b, A.b)."""
+    merge.  p.b is FastRandomHash's bucket count; the keys span 2*max(b, A.b).
+    In the batched form nothing waits on the host, so the call can be captured
+    in a graph: pass check=False there and call c2.check_complete on the
+    clustering workspace (with_ws=True returns it) after each replay."""
     bucket = c2.hash_items(tab, p.b, P.m)
     frh = c2.frh_keys(P, bucket) if min_gap > 0 else None
     keys = A.keys(P, frh, min_gap, weights)
     kb = 2 * max(p.b, A.b)
     pk = c2.params(p.t, kb, p.cap, p.k)
     members, cl_off, cfg, ws = c2.cluster_keys(P, keys, bucket, pk, form, tune)
-    if form == c2.FORM_BATCHED:
+    if form == c2.FORM_BATCHED and check:
         c2.check_complete(ws)   # enough split rounds were enqueued (synchronous)
     part = c2.local_knn(P, members, cl_off, cfg, pk, form, tune)
-    return c2.merge(P, part[0], part[1], pk)
+    out = c2.merge(P, part[0], part[1], pk)
+    return (out, ws) if with_ws else out
