@@ -274,10 +274,24 @@ def hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np, bf, rho=5):
 
 
 def learned_graph(args, A, dP, tab, p, gap, tb, W, ref, c2, torch, learned):
-    """The batched learned build captured once as a graph and replayed: the
-    time per replay, and whether every replay (checked after each, with the
-    split-round status) equals the eager batched result `ref`."""
+    """The batched learned build captured once as a graph, with the fewest
+    split rounds that complete, and replayed: the time per replay, and whether
+    every replay (checked after each, with the split-round status) equals the
+    eager batched result `ref`."""
     try:
+        # the fewest split rounds that complete on this data (synchronous
+        # status check), as the FastRandomHash graph learns them from a plain run
+        rounds = 64
+        for r in (2, 4, 8, 16, 32):
+            try:
+                learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, c2.tuning(split_rounds=r),
+                              weights=W)
+                rounds = r
+                break
+            except c2.C2Error:
+                continue
+        tb = c2.tuning(split_rounds=rounds)
+        torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, capture_error_mode="thread_local"):
             gout, gws = learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W,
@@ -297,7 +311,8 @@ def learned_graph(args, A, dP, tab, p, gap, tb, W, ref, c2, torch, learned):
         c2.check_complete(gws)
         equal &= all(torch.equal(a, b) for a, b in zip(gout, ref))
         del g
-        return {"build_ms_graph": ms, "graph_equals_eager": bool(equal)}
+        return {"build_ms_graph": ms, "graph_split_rounds": rounds,
+                "graph_equals_eager": bool(equal)}
     except Exception as e:  # report, do not lose the rest of the leg
         return {"build_ms_graph": None, "graph_error": str(e)[:200]}
 
