@@ -222,3 +222,38 @@ def test_learned_pipeline_end_to_end(A, orc):
         for (i1, u1, v1), (i2, u2, v2) in zip(row, row[1:]):
             assert i1 * u2 > i2 * u1 or (i1 * u2 == i2 * u1 and v1 < v2)
         assert len({v for _, _, v in row}) == len(row) and u not in {v for _, _, v in row}
+
+
+def test_learned_build_graph_replays_equal_eager():
+    """The batched learned build (keys, clustering from keys, local KNN,
+    merge) captured once in a graph: several replays, with eager work and
+    synchronisations between them, each checked for the split-round status
+    and against the eager batched result."""
+    from paper_2010_11497_amd import learned
+    say("learned graph replays")
+    P = synth.random_profiles(123, 3000, 800, 5, 60, 1.0)
+    dP = c2.DeviceProfiles.from_synth(P)
+    t, b, k = 4, 64, 10
+    tab = c2.tables_to_device(synth.hash_tables(t, 124))
+    p = c2.params(t, 32, 300, k)
+    Asg = learned.Assigner(P.m, t, b, seed=5)
+    W = Asg.inference_weights()
+    tb = c2.tuning(split_rounds=16)
+    ref = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, capture_error_mode="thread_local"):
+        gout, gws = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W,
+                                  check=False, with_ws=True)
+    for rep in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        c2.check_complete(gws)
+        for a, b2 in zip(gout, ref):
+            assert torch.equal(a, b2), rep
+        # eager work between replays
+        again = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W)
+        torch.cuda.synchronize()
+        for a, b2 in zip(again, ref):
+            assert torch.equal(a, b2)
+    del g
