@@ -646,3 +646,178 @@ def test_cluster_work_sparse_pairs_identity(orc):
     assert work["sparse_pairs"] == tot
     assert work["pairs"] == sum(len(S) * (len(S) - 1) // 2 for S in
                                 (mem[off[c]:off[c + 1]] for c in range(len(off) - 1)))
+
+
+# ------------------------------------------------- Eq. 1 and Eq. 2 by hand --
+
+# A graph of 4 users with k = 3.  User 0 keeps an edge with I = 0, user 1 an
+# edge with I = 0 and one padded slot, user 3 only padded slots.  By hand, its
+# Jaccard values sum to 1/2 + 1/5 + 0 + 1 + 0 + 1/2 + 1/4 + 1/8 = 103/40, so
+# Eq. 1 over the k*n = 12 slots gives 103/480.  The "exact" graph beside it
+# sums to 31/30 + 23/18 + 13/12 + 1/10 = 629/180, i.e. 629/2160, so Eq. 2
+# gives (103/480) / (629/2160) = 927/1258.
+EQ_APPROX = ([[2, 1, 0], [3, 0, 0], [1, 1, 1], [0, 0, 0]],
+             [[4, 5, 7], [3, 9, 0], [2, 4, 8], [0, 0, 0]])
+EQ_EXACT = ([[2, 1, 1], [3, 1, 1], [1, 1, 1], [1, 0, 0]],
+            [[4, 3, 5], [3, 6, 9], [2, 3, 4], [10, 0, 0]])
+
+
+def test_eq1_eq2_hand_computed(orc):
+    """Eq. 1 divides by k*n whatever the number of filled slots, and counts
+    I = 0 edges as 0; Eq. 2 is the ratio of two Eq. 1 values.  Both the
+    oracle's and the benchmark's implementations against the hand values."""
+    from paper_2010_11497_amd import metrics
+    aI, aU = (np.array(x, dtype=np.uint32) for x in EQ_APPROX)
+    eI, eU = (np.array(x, dtype=np.uint32) for x in EQ_EXACT)
+    for mod in (orc, metrics):
+        assert mod.avg_sim(aI, aU) == pytest.approx(103 / 480, rel=1e-15)
+        assert mod.avg_sim(eI, eU) == pytest.approx(629 / 2160, rel=1e-15)
+        assert mod.quality(aI, aU, eI, eU) == pytest.approx(927 / 1258, rel=1e-15)
+        # the exact graph against itself
+        assert mod.quality(eI, eU, eI, eU) == 1.0
+
+
+# ------------------------------- Algorithm 2, Hyrec, restated in Python ----
+
+def splitmix64(seed, c):
+    """Output c + 1 of SplitMix64 from state `seed` (Steele, Lea and Flood,
+    2014): the state advances by the golden gamma 0x9E3779B97F4A7C15 and is
+    passed through the published 64-bit mixer."""
+    z = (seed + 0x9E3779B97F4A7C15 * (c + 1)) % (1 << 64)
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) % (1 << 64)
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) % (1 << 64)
+    return z ^ (z >> 31)
+
+
+def hyrec_python(sets, S, cl, k, seed, delta, max_iter, own=True, sync=True):
+    """Reading R25 of Algorithm 2's Hyrec branch on one cluster (members S,
+    ascending ids, cluster index cl), with rational Jaccard values:
+      start:  member a draws k members q = 0..k-1 (SplitMix64 output number
+              (cl << 40) | (a << 12) | q, modulo s - 1, shifted past a) and
+              keeps the k best distinct;
+      step:   synchronously, a's new list is the k best distinct of its own
+              list and its neighbours' lists, a itself excluded;
+      stop:   after a step in which fewer than delta*k*s entries of the new
+              lists were absent from the old ones, or after max_iter steps.
+    own=False and sync=False give two plausible misreadings (a's own list left
+    out; lists replaced during the step), used to show the pin catches them.
+    Returns the member positions per list and the number of steps taken."""
+    s = len(S)
+
+    def J(a, b):
+        return Fraction(len(sets[S[a]] & sets[S[b]]), len(sets[S[a]] | sets[S[b]]))
+
+    def best(a, pool):
+        return sorted(set(pool) - {a}, key=lambda b: (-J(a, b), b))[:k]
+
+    lists = []
+    for a in range(s):
+        draws = []
+        for q in range(k):
+            b = splitmix64(seed, (cl << 40) | (a << 12) | q) % (s - 1)
+            draws.append(b + 1 if b >= a else b)
+        lists.append(best(a, draws))
+    steps = 0
+    while steps < max_iter:
+        new = [list(x) for x in lists]
+        src = lists if sync else new
+        for a in range(s):
+            pool = (list(src[a]) if own else []) + [c for b in src[a] for c in src[b]]
+            new[a] = best(a, pool)
+        updates = sum(len(set(new[a]) - set(lists[a])) for a in range(s))
+        lists = new
+        steps += 1
+        if updates < delta * k * s:
+            break
+    return lists, steps
+
+
+def hyrec_partition(seed, s=16, lead=3, m=40):
+    """t = 1 partition of lead + s users: a small cluster first (brute force
+    under rho = 1 when lead < k^2), then one of s members at cluster index 1
+    (Hyrec), the members interleaved so that positions differ from ids."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = lead + s
+    sets = [set(rng.choice(m, size=int(rng.integers(2, 9)), replace=False).tolist())
+            for _ in range(n)]
+    perm = rng.permutation(n)
+    first = np.sort(perm[:lead]).astype(np.uint32)
+    hy = np.sort(perm[lead:]).astype(np.uint32)
+    members = np.concatenate([first, hy])
+    cl_off = np.array([0, lead, n], dtype=np.uint32)
+    cfg = np.array([0, 2], dtype=np.uint32)
+    return sets, members, cl_off, cfg, hy.tolist()
+
+
+def hyrec_oracle_rows(orc, sets, members, cl_off, cfg, k, seed, delta, max_iter):
+    P = synth.profiles_from_sets(sets, 1 + max(max(x) for x in sets))
+    pid, pI = orc.local_knn_alg2(P.indptr, P.indices, len(sets), P.m, 1, k, members, cl_off,
+                                 cfg, rho=1, delta=delta, max_iter=max_iter, seed=seed)
+    return pid[:, 0], pI[:, 0]
+
+
+def expected_rows(sets, S, lists, k):
+    out = {}
+    for a, u in enumerate(S):
+        ids = [S[b] for b in lists[a]]
+        I = [len(sets[u] & sets[v]) for v in ids]
+        out[u] = (ids + [PAD] * (k - len(ids)), I + [0] * (k - len(ids)))
+    return out
+
+
+@pytest.mark.parametrize("k,seed", [(2, 61), (3, 62), (2, 63)])
+def test_hyrec_steps_equal_restatement(orc, k, seed):
+    """The oracle's Hyrec lists equal the Python restatement exactly after 0,
+    1 and 2 synchronous steps (delta = 0: no early stop); the cluster sits at
+    index 1, so the draw counter's cluster field is exercised."""
+    sets, members, cl_off, cfg, S = hyrec_partition(seed)
+    for max_iter in (0, 1, 2):
+        lists, steps = hyrec_python(sets, S, 1, k, seed, 0.0, max_iter)
+        assert steps == max_iter
+        pid, pI = hyrec_oracle_rows(orc, sets, members, cl_off, cfg, k, seed, 0.0, max_iter)
+        for u, (ids, I) in expected_rows(sets, S, lists, k).items():
+            assert pid[u].tolist() == ids and pI[u].tolist() == I, (max_iter, u)
+
+
+def test_hyrec_restatement_separates_misreadings():
+    """Premise of the step pin: on its cases, leaving a member's own list out
+    of its candidates, or replacing lists during a step, changes the lists."""
+    diff_own = diff_sync = False
+    for k, seed in [(2, 61), (3, 62), (2, 63)]:
+        sets, _, _, _, S = hyrec_partition(seed)
+        for it in (1, 2):
+            ref, _ = hyrec_python(sets, S, 1, k, seed, 0.0, it)
+            diff_own |= hyrec_python(sets, S, 1, k, seed, 0.0, it, own=False)[0] != ref
+            diff_sync |= hyrec_python(sets, S, 1, k, seed, 0.0, it, sync=False)[0] != ref
+    assert diff_own and diff_sync
+
+
+def test_hyrec_stop_rule_is_strict(orc):
+    """The stop rule 'fewer than delta*k*s changed entries': with k*s = 32 the
+    threshold delta*k*s is an exact integer.  A case whose steps change u1 > u2
+    entries (u2 >= 1) and whose third step still changes the lists stops after
+    step 2 for delta*32 = u2 + 1, and runs on for delta*32 = u2 (not fewer)."""
+    k, s = 2, 16
+    for seed in range(100, 200):
+        sets, members, cl_off, cfg, S = hyrec_partition(seed, s=s)
+        l1, _ = hyrec_python(sets, S, 1, k, seed, 0.0, 1)
+        l2, _ = hyrec_python(sets, S, 1, k, seed, 0.0, 2)
+        l3, _ = hyrec_python(sets, S, 1, k, seed, 0.0, 3)
+        l0, _ = hyrec_python(sets, S, 1, k, seed, 0.0, 0)
+        u1 = sum(len(set(l1[a]) - set(l0[a])) for a in range(s))
+        u2 = sum(len(set(l2[a]) - set(l1[a])) for a in range(s))
+        if u1 > u2 >= 1 and l3 != l2:
+            break
+    else:
+        pytest.fail("no seed with the premise")
+    for thr, want_steps in ((u2 + 1, 2), (u2, None)):
+        delta = thr / (k * s)
+        assert delta * k * s == thr
+        lists, steps = hyrec_python(sets, S, 1, k, seed, delta, 30)
+        if want_steps is not None:
+            assert steps == 2 and lists == l2
+        else:
+            assert steps > 2
+        pid, pI = hyrec_oracle_rows(orc, sets, members, cl_off, cfg, k, seed, delta, 30)
+        for u, (ids, I) in expected_rows(sets, S, lists, k).items():
+            assert pid[u].tolist() == ids and pI[u].tolist() == I, (thr, u)
