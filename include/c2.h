@@ -257,6 +257,22 @@ c2_status c2_build(const c2_profiles *P, const uint64_t *tab, const c2_params *p
                    const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U,
                    void *ws, size_t ws_bytes, void *stream);
 
+/* c2_build for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, forms, arithmetic and outputs as c2_build, but the workspace is
+ * a fixed array of 256 MiB in device memory that the library holds on each
+ * GPU it runs on until the process ends; the call itself allocates nothing.
+ * C2_E_WORKSPACE (nothing enqueued) when c2_workspace_bytes(..., C2_OP_BUILD)
+ * exceeds 256 MiB.  Every call on one GPU uses that GPU's one array, so calls
+ * that overlap on one GPU (other streams, other host threads) race and give
+ * undefined results; calls on one stream are ordered and safe.
+ * status_out: NULL, or a device u32 that receives, in stream order, 0 if the
+ * build split every oversized cluster and 1 if the batched form needed more
+ * split rounds (the c2_check_complete condition; the plain form writes 0). */
+c2_status c2_build_noalloc(const c2_profiles *P, const uint64_t *tab, const c2_params *p,
+                           int form, const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I,
+                           uint32_t *knn_U, uint32_t *status_out, void *stream);
+
 /* The exact KNN graph (Section IV-B, brute force): c2_local_knn on one cluster
  * holding all users.  Outputs as c2_merge.  ws: C2_OP_BRUTE_FORCE bytes. */
 c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uint32_t *knn_I,

@@ -30,7 +30,7 @@ FORM_BATCHED = 1
 # every entry point of include/c2.h
 SYMBOLS = ["c2_last_error", "c2_workspace_bytes", "c2_validate", "c2_hash_items", "c2_frh_keys",
            "c2_cluster", "c2_cluster_keys", "c2_check_complete", "c2_local_knn",
-           "c2_local_knn_alg2", "c2_merge", "c2_build",
+           "c2_local_knn_alg2", "c2_merge", "c2_build", "c2_build_noalloc",
            "c2_brute_force", "c2_fingerprint", "c2_assign_hidden", "c2_assign_keys",
            "c2_embag", "c2_embag_backward", "c2_graph_create", "c2_graph_launch",
            "c2_graph_destroy"]
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     L.c2_local_knn_alg2.argtypes = [PP, P, P, P, PA, ctypes.POINTER(Hyrec), PT, P, P, P, sz, P]
     L.c2_merge.argtypes = [PP, P, P, PA, P, P, P, P]
     L.c2_build.argtypes = [PP, P, PA, i32, PT, P, P, P, P, sz, P]
+    L.c2_build_noalloc.argtypes = [PP, P, PA, i32, PT, P, P, P, P, P]
     L.c2_brute_force.argtypes = [PP, u32, P, P, P, P, sz, P]
     L.c2_fingerprint.argtypes = [PP, P, u32, P, P, ctypes.POINTER(u64), P, sz, P]
     L.c2_assign_hidden.argtypes = [PP, P, P, P, P, P]
@@ -301,6 +302,19 @@ def build(P: DeviceProfiles, tab: torch.Tensor, p: Params, form=FORM_PLAIN,
     _check(load().c2_build(ctypes.byref(P.c), _ptr(tab), ctypes.byref(p), form,
                            ctypes.byref(tune) if tune else None, _ptr(out[0]), _ptr(out[1]),
                            _ptr(out[2]), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def build_noalloc(P: DeviceProfiles, tab: torch.Tensor, p: Params, form=FORM_PLAIN,
+                  tune: Optional[Tuning] = None, out=None, status=None):
+    """c2_build on the library's fixed per-GPU workspace (no allocation in the
+    call).  status: optional int32 tensor of one element that receives the
+    split-completeness word (0 = complete)."""
+    if out is None:
+        out = tuple(_u32((P.n, p.k), P.device) for _ in range(3))
+    _check(load().c2_build_noalloc(ctypes.byref(P.c), _ptr(tab), ctypes.byref(p), form,
+                                   ctypes.byref(tune) if tune else None, _ptr(out[0]),
+                                   _ptr(out[1]), _ptr(out[2]), _ptr(status), _stream()))
     return out
 
 

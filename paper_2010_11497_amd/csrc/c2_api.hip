@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -298,6 +299,39 @@ c2_status check_ws(void *ws, size_t have, size_t need) {
 
 c2_status check_form(int form) {
     if (form != C2_FORM_PLAIN && form != C2_FORM_BATCHED) return fail(C2_E_ARG, "bad form %d", form);
+    return C2_OK;
+}
+
+// ------------------------------------------------------------ no allocation
+//
+// Workspace of c2_build_noalloc: a fixed array in device memory, one copy per
+// GPU, held from the module's load until the process ends.  Host code never
+// passes the array's name to a kernel or copy (on the host it is a stand-in,
+// not a device address): the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and is kept here.
+constexpr size_t kNoAllocBytes = (size_t)256 << 20;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+__global__ void k_copy_status(const uint32_t *src, uint32_t *dst) { *dst = *src; }
+
+std::mutex g_noalloc_mu;
+char *g_noalloc_base[kNoAllocDevices] = {};
+
+// Device address of this GPU's copy of the array (the current device).
+c2_status noalloc_base(char **out) {
+    int dev = 0;
+    C2_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kNoAllocDevices)
+        return fail(C2_E_UNSUPPORTED, "device %d: at most %d devices", dev, kNoAllocDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_base[dev]) {
+        void *ptr = nullptr;
+        C2_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(C2_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_noalloc_base[dev] = reinterpret_cast<char *>(ptr);
+    }
+    *out = g_noalloc_base[dev];
     return C2_OK;
 }
 
@@ -679,6 +713,34 @@ c2_status c2_build(const c2_profiles *P, const uint64_t *tab, const c2_params *p
         return st;
     return build_impl(P, tab, p, form, tune, rounds_from(tune), knn_id, knn_I, knn_U,
                       reinterpret_cast<char *>(ws), (hipStream_t)stream, nullptr);
+}
+
+c2_status c2_build_noalloc(const c2_profiles *P, const uint64_t *tab, const c2_params *p,
+                           int form, const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I,
+                           uint32_t *knn_U, uint32_t *status_out, void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
+    if ((st = check_form(form)) != C2_OK) return st;
+    if (!tab || !knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
+    const size_t need = c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_BUILD);
+    if (need == 0) return C2_E_ARG;
+    if (need > kNoAllocBytes)
+        return fail(C2_E_WORKSPACE,
+                    "c2_build_noalloc: these sizes need %zu bytes of workspace, more than its "
+                    "fixed %zu (use c2_build with a caller workspace)", need, kNoAllocBytes);
+    char *base = nullptr;
+    if ((st = noalloc_base(&base)) != C2_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = build_impl(P, tab, p, form, tune, rounds_from(tune), knn_id, knn_I, knn_U, base, s,
+                    nullptr);
+    if (st != C2_OK) return st;
+    if (status_out) {
+        hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, s,
+                           reinterpret_cast<const uint32_t *>(base), status_out);
+        C2_TRY(hipGetLastError(), "status copy");
+    }
+    return C2_OK;
 }
 
 c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uint32_t *knn_I,
