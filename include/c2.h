@@ -61,7 +61,8 @@ typedef int32_t c2_status;
 
 #define C2_PAD 0xFFFFFFFFu     /* padding id in neighbour lists */
 
-/* Limits of the library: n <= 2^31 - 1 users and t*n < 2^32, m <= 131072 items,
+/* Limits of the library: n <= 2^31 - 1 users and t*n < 2^32, m <= 2^19 items
+ * (two m-bit dictionary bitmaps per cluster live in the 160 KiB of LDS),
  * nnz < 2^40, every profile shorter than 2^20 items, 1 <= t <= 64,
  * 1 <= b <= 2^24, cap >= 1, 1 <= k <= 32. */
 
@@ -89,25 +90,25 @@ typedef struct c2_params {
                               all clusters of all configurations, largest first; capturable */
 
 /* Tile and schedule choices of c2_local_knn (written by the autotuner).  A
- * NULL pointer or a zero field means the built-in default. */
+ * NULL pointer or a zero field means the built-in default.  None of them
+ * changes a result. */
 typedef struct c2_tuning {
     uint32_t mfma_min_rows;   /* clusters with at least this many members use the
-                                 MFMA path, smaller ones the bitmap path */
-    uint32_t persistent_wgs;  /* workgroups of the persistent launch (batched form) */
+                                 MFMA path, smaller ones the bitmap path (default 2) */
+    uint32_t persistent_wgs;  /* MFMA path, batched form: persistent waves (one per block;
+                                 default 1024, one per SIMD) */
     uint32_t split_rounds;    /* split rounds enqueued by the batched form */
-    uint32_t group_tiles;     /* MFMA path: a block of 128 rows whose cluster spans more than
-                                 this many 128-column tiles is split into up to 4 work items
-                                 over disjoint column ranges (default 4) */
+    uint32_t group_tiles;     /* MFMA path: a row block whose cluster spans more than this many
+                                 column tiles is split into up to 4 work items over disjoint
+                                 column ranges (default 4) */
     uint32_t cluster_path;    /* 0: automatic; 1: grid rounds (any size); 2: one workgroup per
                                  configuration with every split round in LDS (n <= 8192 and
                                  bit_width(b) <= 20; otherwise the grid rounds are used) */
     void *ev_knn_begin;       /* optional hipEvent_t (host handles, caller-owned): recorded on */
     void *ev_knn_end;         /* the stream right before / after the pairwise local-KNN kernel */
-    uint32_t compact;         /* per-cluster item dictionaries (Section II-F staging: only items
-                                 held by >= 2 members can be in an intersection): 0 automatic
-                                 (on when bit rows reach 512 words, m >= 16384), 1 off, 2 on.
-                                 Clusters of 2..8192 members whose dictionary saves at least a
-                                 quarter of the row are multiplied over it; the result is the same */
+    uint32_t tile32_max;      /* MFMA path tile shape per cluster: clusters of at most this many */
+    uint32_t tile64_max;      /* members take 32 x 32 tiles (default 32), of at most tile64_max
+                                 64 x 64 tiles (default 64), larger ones 128 x 128 tiles */
 } c2_tuning;
 
 /* Workspace queries: which call the size is for. */
@@ -118,6 +119,9 @@ typedef struct c2_tuning {
 #define C2_OP_BRUTE_FORCE 4
 #define C2_OP_FINGERPRINT 5
 #define C2_OP_LOCAL_KNN_ALG2 6
+#define C2_OP_LOCAL_KNN_MIN 7  /* the smallest workspace c2_local_knn accepts: its fixed part
+                                  plus a 4096-byte store (the store takes every byte beyond
+                                  the fixed part) */
 
 /* Message for the last non-OK status returned on this thread (host string,
  * valid until the next call on this thread). */
@@ -187,7 +191,10 @@ c2_status c2_cluster_keys(const c2_profiles *P, const uint32_t *keys, const uint
                           void *stream);
 
 /* Synchronous: C2_OK if the last batched c2_cluster / c2_build that used this
- * workspace split every oversized cluster, C2_E_INCOMPLETE otherwise. */
+ * workspace split every oversized cluster and the last local KNN found room
+ * for every cluster's dictionary rows; C2_E_INCOMPLETE if split rounds were
+ * missing, C2_E_WORKSPACE if the store was too small (the results are then
+ * invalid). */
 c2_status c2_check_complete(const void *ws, void *stream);
 
 /* Step 2 (Section II-F, Algorithm 2, brute-force branch): for every cluster
@@ -197,18 +204,29 @@ c2_status c2_check_complete(const void *ws, void *stream);
  *   part_id[(u*t + j)*k + r], part_I[(u*t + j)*k + r]  (device, [n][t][k]),
  * best first, padded with (C2_PAD, 0).  Every (u, j) slot is written exactly
  * once, so every user must appear once per configuration.
- * Pairwise intersections are exact integer counts over per-user bit rows
- * (one bit per item, all m items): the MFMA path expands 64-item chunks of
- * the rows to fp4 (e2m1) values 0 and 1 and multiplies them with the gfx950
- * block-scaled MFMA at unit scale, whose fp32 sums of 0/1 products are exact
- * integer counts (used when every profile has fewer than 2^15 items, where an
- * exact 32-bit similarity key exists); the bitmap path uses AND and
- * population count.
+ * Pairwise intersections are exact integer counts over bit rows built per
+ * cluster from the CSR lists, over the cluster's dictionary (the items held
+ * by at least two of its members; no other item can be in an intersection):
+ * the MFMA path expands 64-position chunks of the rows to fp4 (e2m1) values 0
+ * and 1 and multiplies them with the gfx950 block-scaled MFMA at unit scale,
+ * whose fp32 sums of 0/1 products are exact integer counts (used when every
+ * profile has fewer than 2^15 items, where an exact 32-bit similarity key
+ * exists); the bitmap path uses AND and population count.
  * form: C2_FORM_PLAIN reads the cluster table back (synchronises once) and
  * launches one grid over (cluster, row block) pairs in cluster order;
  * C2_FORM_BATCHED plans on the device and runs one persistent launch that
  * takes (cluster, row block) pairs largest cluster first.
- * tune: NULL or c2_tuning.  ws: C2_OP_LOCAL_KNN bytes. */
+ * tune: NULL or c2_tuning.
+ * ws: C2_OP_LOCAL_KNN bytes by default.  The rows live in a store that takes
+ * all of the workspace beyond a fixed part, so a caller may pass more (or
+ * less, down to the fixed part and 4 KiB); the default holds about four
+ * words per (configuration, profile item), which covered every workload
+ * measured.  When a partition's rows do not fit, the plain form returns
+ * C2_E_WORKSPACE and the batched form leaves its results invalid and makes
+ * c2_check_complete(ws) return C2_E_WORKSPACE.  Either way, after the call
+ * bytes 8..15 of ws hold (u64, device, in stream order) the store bytes / 4
+ * that the partition needs, so a caller can retry with C2_OP_LOCAL_KNN_MIN
+ * bytes + 4 times that. */
 c2_status c2_local_knn(const c2_profiles *P, const uint32_t *members, const uint32_t *cl_off,
                        const uint32_t *cl_cfg_off, const c2_params *p, int form,
                        const c2_tuning *tune, uint32_t *part_id, uint32_t *part_I,
@@ -252,7 +270,8 @@ c2_status c2_merge(const c2_profiles *P, const uint32_t *part_id, const uint32_t
 
 /* The whole method: c2_hash_items, c2_frh_keys, c2_cluster, c2_local_knn,
  * c2_merge on the workspace.  tab as in c2_hash_items.  Outputs as c2_merge.
- * ws: C2_OP_BUILD bytes. */
+ * ws: C2_OP_BUILD bytes by default; the store of the local KNN takes what is
+ * left after the other stages' buffers (see c2_local_knn). */
 c2_status c2_build(const c2_profiles *P, const uint64_t *tab, const c2_params *p, int form,
                    const c2_tuning *tune, uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U,
                    void *ws, size_t ws_bytes, void *stream);

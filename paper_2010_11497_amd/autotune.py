@@ -1,12 +1,13 @@
 """Autotuner for the local-KNN schedule of libc2.so.
 
 For one workload it builds the graph form of the batched build for every
-point of a small grid over the c2_tuning fields that change the schedule but
-not the arithmetic -- persistent workgroups of the MFMA launch, the cluster
-size from which the MFMA path is used, and how many 128-column tiles a work
-item takes before a row block is split -- times each (median of repeated
-replays), checks that every point produces the same graph, and writes the
-fastest point to tuning/<workload>.json.  bench.py reads that table.
+point of a small grid over the c2_tuning fields that change the schedule and
+the tile shapes but not the arithmetic -- persistent waves of the MFMA
+launch, how many column tiles a work item takes before a row block is split,
+and the cluster sizes up to which 32- and 64-row tiles are used (128 above)
+-- times each (median of repeated replays), checks that every point produces
+the same graph, and writes the fastest point to tuning/<workload>.json.
+bench.py reads that table.
 
 Run on the GPU:  python -m paper_2010_11497_amd.autotune --workload n6k_m3.7k
 (each grid axis can be replaced from the command line, e.g. --mfma-min-rows 2,64)
@@ -21,9 +22,10 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_DIR = os.path.join(HERE, "tuning")
 GRID = {
-    "persistent_wgs": [256, 384, 512, 768, 1024],
-    "mfma_min_rows": [2],
-    "group_tiles": [1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 24, 32],
+    "persistent_wgs": [1024],
+    "group_tiles": [2, 4, 8, 16, 32],
+    "tile32_max": [16, 32],
+    "tile64_max": [64, 96],
 }
 
 

@@ -25,7 +25,7 @@ C2_PAD = 0xFFFFFFFF
 FORM_PLAIN = 0
 FORM_BATCHED = 1
 (OP_VALIDATE, OP_CLUSTER, OP_LOCAL_KNN, OP_BUILD, OP_BRUTE_FORCE, OP_FINGERPRINT,
- OP_LOCAL_KNN_ALG2) = range(7)
+ OP_LOCAL_KNN_ALG2, OP_LOCAL_KNN_MIN) = range(8)
 
 # every entry point of include/c2.h
 SYMBOLS = ["c2_last_error", "c2_workspace_bytes", "c2_validate", "c2_hash_items", "c2_frh_keys",
@@ -63,7 +63,7 @@ class Tuning(ctypes.Structure):
                 ("split_rounds", ctypes.c_uint32), ("group_tiles", ctypes.c_uint32),
                 ("cluster_path", ctypes.c_uint32),
                 ("ev_knn_begin", ctypes.c_void_p), ("ev_knn_end", ctypes.c_void_p),
-                ("compact", ctypes.c_uint32)]
+                ("tile32_max", ctypes.c_uint32), ("tile64_max", ctypes.c_uint32)]
 
 
 _lib = None
@@ -171,19 +171,16 @@ def params(t, b, cap, k) -> Params:
 
 
 CLUSTER_AUTO, CLUSTER_GRID, CLUSTER_WORKGROUP = 0, 1, 2
-COMPACT_AUTO, COMPACT_OFF, COMPACT_ON = 0, 1, 2
 
 
 def tuning(mfma_min_rows=0, persistent_wgs=0, split_rounds=0, group_tiles=0,
-           cluster_path=CLUSTER_AUTO, events=None, compact=COMPACT_AUTO) -> Tuning:
-    """Schedule fields of c2_tuning (0 = the library's default; include/c2.h
-    documents each).  compact: COMPACT_AUTO (per-cluster item dictionaries
-    when bit rows reach 512 words), COMPACT_OFF or COMPACT_ON; results are
-    the same either way.  events: optional (begin, end)
-    torch.cuda.Event(enable_timing=True) pair recorded around the local-KNN
-    kernel."""
+           cluster_path=CLUSTER_AUTO, events=None, tile32_max=0, tile64_max=0) -> Tuning:
+    """Schedule and shape fields of c2_tuning (0 = the library's default;
+    include/c2.h documents each); none changes a result.  events: optional
+    (begin, end) torch.cuda.Event(enable_timing=True) pair recorded around the
+    local-KNN kernel."""
     tu = Tuning(int(mfma_min_rows), int(persistent_wgs), int(split_rounds), int(group_tiles),
-                int(cluster_path), None, None, int(compact))
+                int(cluster_path), None, None, int(tile32_max), int(tile64_max))
     if events is not None:
         for ev in events:
             ev.record()           # materialise the underlying hipEvent_t
@@ -203,6 +200,31 @@ def workspace_bytes(P: DeviceProfiles, p: Optional[Params], op: int) -> int:
 
 def workspace(P: DeviceProfiles, p: Optional[Params], op: int) -> torch.Tensor:
     return torch.empty(workspace_bytes(P, p, op), dtype=torch.uint8, device=P.device)
+
+
+C2_E_WORKSPACE = -3
+
+
+def store_need_bytes(ws: torch.Tensor) -> int:
+    """Bytes of dictionary-row store the last local KNN on this workspace
+    needed (the u64 at bytes 8..15 of its header, times 4)."""
+    return 4 * int(ws[8:16].view(torch.int64).item())
+
+
+def _with_ws(call, ws: Optional[torch.Tensor], default) -> torch.Tensor:
+    """Runs call(ws).  When the workspace was allocated here (ws is None) and
+    the partition's dictionary rows did not fit its store, allocates one
+    larger by the store the library reports as needed and runs once more."""
+    owned = ws is None
+    ws = default() if owned else ws
+    st = call(ws)
+    if st == C2_E_WORKSPACE and owned:
+        need = store_need_bytes(ws)
+        if need > 0:
+            ws = torch.empty(ws.numel() + need, dtype=torch.uint8, device=ws.device)
+            st = call(ws)
+    _check(st)
+    return ws
 
 
 def validate(P: DeviceProfiles, ws: Optional[torch.Tensor] = None) -> None:
@@ -262,10 +284,11 @@ def local_knn(P: DeviceProfiles, members, cl_off, cl_cfg_off, p: Params, form=FO
     """Returns (part_id, part_I), int32 views of uint32[n][t][k]."""
     if out is None:
         out = (_u32((P.n, p.t, p.k), P.device), _u32((P.n, p.t, p.k), P.device))
-    ws = workspace(P, p, OP_LOCAL_KNN) if ws is None else ws
-    _check(load().c2_local_knn(ctypes.byref(P.c), _ptr(members), _ptr(cl_off), _ptr(cl_cfg_off),
-                               ctypes.byref(p), form, ctypes.byref(tune) if tune else None,
-                               _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(), _stream()))
+    _with_ws(lambda w: load().c2_local_knn(ctypes.byref(P.c), _ptr(members), _ptr(cl_off),
+                                           _ptr(cl_cfg_off), ctypes.byref(p), form,
+                                           ctypes.byref(tune) if tune else None, _ptr(out[0]),
+                                           _ptr(out[1]), _ptr(w), w.numel(), _stream()),
+             ws, lambda: workspace(P, p, OP_LOCAL_KNN))
     return out
 
 
@@ -298,10 +321,10 @@ def build(P: DeviceProfiles, tab: torch.Tensor, p: Params, form=FORM_PLAIN,
           tune: Optional[Tuning] = None, ws=None, out=None):
     if out is None:
         out = tuple(_u32((P.n, p.k), P.device) for _ in range(3))
-    ws = workspace(P, p, OP_BUILD) if ws is None else ws
-    _check(load().c2_build(ctypes.byref(P.c), _ptr(tab), ctypes.byref(p), form,
-                           ctypes.byref(tune) if tune else None, _ptr(out[0]), _ptr(out[1]),
-                           _ptr(out[2]), _ptr(ws), ws.numel(), _stream()))
+    _with_ws(lambda w: load().c2_build(ctypes.byref(P.c), _ptr(tab), ctypes.byref(p), form,
+                                       ctypes.byref(tune) if tune else None, _ptr(out[0]),
+                                       _ptr(out[1]), _ptr(out[2]), _ptr(w), w.numel(), _stream()),
+             ws, lambda: workspace(P, p, OP_BUILD))
     return out
 
 
@@ -406,9 +429,10 @@ def brute_force(P: DeviceProfiles, k: int, ws=None, out=None):
     if out is None:
         out = tuple(_u32((P.n, k), P.device) for _ in range(3))
     p = params(1, 1, 1, k)
-    ws = workspace(P, p, OP_BRUTE_FORCE) if ws is None else ws
-    _check(load().c2_brute_force(ctypes.byref(P.c), int(k), _ptr(out[0]), _ptr(out[1]),
-                                 _ptr(out[2]), _ptr(ws), ws.numel(), _stream()))
+    _with_ws(lambda w: load().c2_brute_force(ctypes.byref(P.c), int(k), _ptr(out[0]),
+                                             _ptr(out[1]), _ptr(out[2]), _ptr(w), w.numel(),
+                                             _stream()),
+             ws, lambda: workspace(P, p, OP_BRUTE_FORCE))
     return out
 
 
@@ -419,12 +443,12 @@ class Graph:
                  tune: Optional[Tuning] = None):
         self.P, self.tab, self.p = P, tab, p
         self.out = tuple(_u32((P.n, p.k), P.device) for _ in range(3))
-        self.ws = workspace(P, p, OP_BUILD)
         h = ctypes.c_void_p()
-        _check(load().c2_graph_create(ctypes.byref(P.c), _ptr(tab), ctypes.byref(p),
-                                      ctypes.byref(tune) if tune else None, _ptr(self.out[0]),
-                                      _ptr(self.out[1]), _ptr(self.out[2]), _ptr(self.ws),
-                                      self.ws.numel(), _stream(), ctypes.byref(h)))
+        # (creation runs one plain build first, which reports a store overflow)
+        self.ws = _with_ws(lambda w: load().c2_graph_create(
+            ctypes.byref(P.c), _ptr(tab), ctypes.byref(p), ctypes.byref(tune) if tune else None,
+            _ptr(self.out[0]), _ptr(self.out[1]), _ptr(self.out[2]), _ptr(w), w.numel(),
+            _stream(), ctypes.byref(h)), None, lambda: workspace(P, p, OP_BUILD))
         self.h = h
 
     def launch(self):

@@ -61,6 +61,18 @@ c2_status check_profiles(const c2_profiles *P) {
     return C2_OK;
 }
 
+// Brute force: members, cl_off, cl_cfg and the partial lists ahead of the
+// local-KNN region.
+size_t brute_head(uint32_t n, uint32_t k) {
+    return kHeader + al(4 * (size_t)n) + al(4 * ((size_t)n + 1)) + al(8) + 2 * al(4 * (size_t)n * k);
+}
+
+// Smallest workspace a call accepts: the fixed part and a minimal store (the
+// store takes whatever the caller gives beyond the fixed part).
+size_t knn_min_bytes(uint32_t n, uint32_t NE, uint32_t m) {
+    return knn_ws_fixed(n, NE, m, nullptr) + 4096;
+}
+
 ClusterDims cdims(uint32_t n, const c2_params *p) {
     ClusterDims d;
     d.NE = (size_t)p->t * n;
@@ -78,10 +90,10 @@ size_t cluster_scratch_bytes(uint32_t n, const c2_params *p) {
 }
 
 struct BuildLayout {
-    size_t bucket, members, cl_off, cl_cfg, part_id, part_I, scratch, total;
+    size_t bucket, members, cl_off, cl_cfg, part_id, part_I, scratch, knn_fixed, total;
 };
 
-BuildLayout build_layout(uint32_t n, uint32_t m, const c2_params *p) {
+BuildLayout build_layout(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *p) {
     BuildLayout L;
     size_t off = kHeader;
     auto take = [&](size_t b) { size_t o = off; off += al(b); return o; };
@@ -94,9 +106,18 @@ BuildLayout build_layout(uint32_t n, uint32_t m, const c2_params *p) {
     L.part_I = take(4 * NE * p->k);
     L.scratch = off;
     const size_t cw = cluster_scratch_bytes(n, p);
-    const size_t kw = knn_ws_bytes(n, (uint32_t)NE, knn_wmax(m), nullptr);
+    L.knn_fixed = knn_ws_fixed(n, (uint32_t)NE, m, nullptr);
+    const size_t kw = L.knn_fixed + knn_store_default_bytes(n, (uint32_t)NE, m, nnz, p->t);
     L.total = off + (cw > kw ? cw : kw);
     return L;
+}
+
+// Smallest workspace c2_build accepts: the outputs of the stages, then the
+// clustering scratch or the local KNN's fixed part and a minimal store.
+size_t build_min_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *p) {
+    const BuildLayout L = build_layout(n, m, nnz, p);
+    const size_t cw = cluster_scratch_bytes(n, p), kw = L.knn_fixed + 4096;
+    return L.scratch + (cw > kw ? cw : kw);
 }
 
 ClusterPtrs cluster_ptrs(char *base, const ClusterWs &w, uint32_t *members, uint32_t *status) {
@@ -132,11 +153,12 @@ ClusterPtrs cluster_ptrs(char *base, const ClusterWs &w, uint32_t *members, uint
     return c;
 }
 
-KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
+// Pointers into a local-KNN region of `bytes` bytes at base (the store takes
+// what the fixed part leaves); status: the caller's header word for overflow.
+KnnPtrs knn_ptrs(char *base, size_t bytes, const KnnWs &w, uint32_t *status) {
     KnnPtrs k;
     auto u32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
     auto u64 = [&](size_t o) { return reinterpret_cast<uint64_t *>(base + o); };
-    k.rows = u32(w.rows);
     k.rlen = u32(w.rlen);
     k.cnt = u64(w.cnt);
     k.items_m = u64(w.items_m);
@@ -145,23 +167,26 @@ KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
     k.sbase = u32(w.sbase);
     k.rb_done = u32(w.rb_done);
     k.skeys = u64(w.skeys);
-    k.ctmp = u64(w.ctmp);
-    k.csort_key = u64(w.csort_key);
-    k.csort_key_alt = u64(w.csort_key_alt);
-    k.csort_val = u32(w.csort_val);
-    k.csort_val_alt = u32(w.csort_val_alt);
-    k.hist = u32(w.hist);
     k.htmp = u32(w.htmp);
+    k.ctmp = u64(w.ctmp);
     k.ctr = u32(w.ctr);
     k.bmax = u32(w.bmax);
     k.pc = u32(w.pc);
     k.ccls = u32(w.ccls);
     k.cpos = u32(w.cpos);
-    k.cbits = u32(w.cbits);
     k.cw = u32(w.cw);
     k.coff = u64(w.coff);
-    k.ccur = reinterpret_cast<unsigned long long *>(base + w.ccur);
-    k.cbits_words = w.cbits_words;
+    // the allocation cursor of the store sits in the caller's header (bytes
+    // 8..15, after the two status words) when there is one: every cluster adds
+    // its need to it whether or not it fits, so afterwards it holds the store
+    // words the whole partition needs
+    k.ccur = status ? reinterpret_cast<unsigned long long *>(status + 1)
+                    : reinterpret_cast<unsigned long long *>(base + w.ccur);
+    k.dslot = u32(w.dslot);
+    k.dmap = u32(w.dmap);
+    k.store = u32(w.store);
+    k.store_words = bytes > w.store ? (bytes - w.store) / 4 : 0;
+    k.status = status;
     return k;
 }
 
@@ -169,15 +194,15 @@ KnnPtrs knn_ptrs(char *base, const KnnWs &w) {
 // Hyrec kernels read), the rewritten partition, and Hyrec's double-buffered
 // lists over the largest possible cluster.
 struct Alg2Layout {
-    size_t knn, cl_off, cfg, keyA, keyB, IA, IB, upd, total;
+    size_t rows, cl_off, cfg, keyA, keyB, IA, IB, upd, knn, total;
 };
 
-Alg2Layout alg2_layout(uint32_t n, uint32_t m, const c2_params *p) {
+Alg2Layout alg2_layout(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *p) {
     Alg2Layout L;
     size_t off = kHeader;
     auto take = [&](size_t b) { size_t o = off; off += al(b); return o; };
     const size_t NE = (size_t)p->t * n;
-    L.knn = take(knn_ws_bytes(n, (uint32_t)NE, knn_wmax(m), nullptr));
+    L.rows = take((size_t)4 * n * full_row_words(m));
     L.cl_off = take(4 * (NE + 1));
     L.cfg = take(4 * ((size_t)p->t + 1));
     L.keyA = take(8 * (size_t)n * p->k);
@@ -185,7 +210,9 @@ Alg2Layout alg2_layout(uint32_t n, uint32_t m, const c2_params *p) {
     L.IA = take(4 * (size_t)n * p->k);
     L.IB = take(4 * (size_t)n * p->k);
     L.upd = take(256);
-    L.total = off;
+    L.knn = off;
+    L.total = off + knn_ws_fixed(n, (uint32_t)NE, m, nullptr) +
+              knn_store_default_bytes(n, (uint32_t)NE, m, nnz, p->t);
     return L;
 }
 
@@ -195,6 +222,10 @@ uint32_t rounds_from(const c2_tuning *tune) {
 }
 
 // Clustering on an explicit scratch region (clusters of `ws` header status).
+// Header of a workspace: word 0 = split rounds left clusters unsplit
+// (batched clustering), word 1 = the local KNN's store overflowed, bytes
+// 8..15 = the store words the last local KNN needed (u64).  Each stage writes
+// its own words; c2_check_complete reads the two status words.
 c2_status run_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_params *p, int form,
                       const c2_tuning *tune, uint32_t rounds_batched, uint32_t *members, uint32_t *cl_off,
                       uint32_t *cl_cfg_off, char *scratch, uint32_t *status, hipStream_t s,
@@ -253,14 +284,16 @@ c2_status run_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_par
     return C2_OK;
 }
 
+// The local KNN on a region of `bytes` bytes at `scratch`; *status (a header
+// word of the caller's workspace) is set when the store overflows (batched).
 c2_status run_knn(const c2_profiles *P, const uint32_t *members, const uint32_t *cl_off,
                   const uint32_t *cl_cfg_off, uint32_t t, uint32_t k, int form,
                   const c2_tuning *tune, uint32_t *part_id, uint32_t *part_I, char *scratch,
-                  hipStream_t s) {
+                  size_t bytes, uint32_t *status, hipStream_t s) {
     KnnWs w;
     const uint32_t NE = t * P->n;
-    const uint32_t wmax = knn_wmax(P->m);
-    knn_ws_bytes(P->n, NE, wmax, &w);
+    knn_ws_fixed(P->n, NE, P->m, &w);
+    if (bytes < w.total) return fail(C2_E_WORKSPACE, "local knn: workspace too small");
     KnnArgs a;
     a.indptr = P->indptr;
     a.indices = P->indices;
@@ -273,21 +306,27 @@ c2_status run_knn(const c2_profiles *P, const uint32_t *members, const uint32_t 
     a.cl_off = cl_off;
     a.cl_cfg_off = cl_cfg_off;
     a.NE = NE;
-    a.wmax = wmax;
+    a.Wm = dict_words(P->m);
     a.part_id = part_id;
     a.part_I = part_I;
-    const KnnPtrs kp = knn_ptrs(scratch, w);
+    const KnnPtrs kp = knn_ptrs(scratch, bytes, w, status);
     KnnOpts o;
     if (tune) {
         o.persistent_wgs = tune->persistent_wgs;
         o.mfma_min = tune->mfma_min_rows;
         o.group_tiles = tune->group_tiles;
-        o.compact = tune->compact;
+        o.tile32_max = tune->tile32_max;
+        o.tile64_max = tune->tile64_max;
         o.ev_begin = (hipEvent_t)tune->ev_knn_begin;
         o.ev_end = (hipEvent_t)tune->ev_knn_end;
     }
-    if (form == C2_FORM_PLAIN) C2_TRY(knn_plain(a, kp, o, s), "local knn");
-    else C2_TRY(knn_batched(a, kp, o, s), "local knn");
+    hipError_t e = form == C2_FORM_PLAIN ? knn_plain(a, kp, o, s) : knn_batched(a, kp, o, s);
+    if (e == hipErrorOutOfMemory)
+        return fail(C2_E_WORKSPACE,
+                    "local knn: the dictionary rows of this partition need more than the %llu "
+                    "bytes of store the workspace leaves (pass a larger workspace)",
+                    (unsigned long long)kp.store_words * 4);
+    if (e != hipSuccess) return hip_fail(e, "local knn");
     return C2_OK;
 }
 
@@ -313,7 +352,10 @@ constexpr size_t kNoAllocBytes = (size_t)256 << 20;
 constexpr int kNoAllocDevices = 64;
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
-__global__ void k_copy_status(const uint32_t *src, uint32_t *dst) { *dst = *src; }
+// Bit 0: split rounds left clusters unsplit; bit 1: the store overflowed.
+__global__ void k_copy_status(const uint32_t *src, uint32_t *dst) {
+    *dst = (src[0] ? 1u : 0u) | (src[1] ? 2u : 0u);
+}
 
 std::mutex g_noalloc_mu;
 char *g_noalloc_base[kNoAllocDevices] = {};
@@ -352,20 +394,24 @@ size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params 
         return kHeader + cluster_scratch_bytes(n, p);
     case C2_OP_LOCAL_KNN:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
-        return kHeader + knn_ws_bytes(n, p->t * n, knn_wmax(m), nullptr);
+        return kHeader + knn_ws_fixed(n, p->t * n, m, nullptr) +
+               knn_store_default_bytes(n, p->t * n, m, nnz, p->t);
     case C2_OP_BUILD:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
-        return build_layout(n, m, p).total;
+        return build_layout(n, m, nnz, p).total;
     case C2_OP_BRUTE_FORCE: {
         one.k = p ? p->k : 1;
         if (check_sizes(n, m, nnz, &one, true) != C2_OK) return 0;
-        const size_t head = kHeader + al(4 * (size_t)n) + al(4 * ((size_t)n + 1)) + al(8) +
-                            2 * al(4 * (size_t)n * one.k);
-        return head + knn_ws_bytes(n, n, knn_wmax(m), nullptr);
+        // one cluster: its rows over the whole item universe at most
+        return brute_head(n, one.k) + knn_ws_fixed(n, n, m, nullptr) +
+               (size_t)4 * (((size_t)n + 31) / 32 * 32) * full_row_words(m) + 4096;
     }
     case C2_OP_LOCAL_KNN_ALG2:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
-        return alg2_layout(n, m, p).total;
+        return alg2_layout(n, m, nnz, p).total;
+    case C2_OP_LOCAL_KNN_MIN:
+        if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
+        return kHeader + knn_min_bytes(n, p->t * n, m);
     case C2_OP_FINGERPRINT:
         if (check_sizes(n, m, nnz, nullptr, false) != C2_OK) return 0;
         if (!p || p->b < 1 || p->b > kFpMaxBits) {
@@ -511,6 +557,8 @@ c2_status c2_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_para
     if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_CLUSTER))) != C2_OK)
         return st;
     char *base = reinterpret_cast<char *>(ws);
+    C2_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(base) + 1, 0, 1, (hipStream_t)stream),
+           "status");
     return run_cluster(P, bucket, p, form, tune, rounds_from(tune), members, cl_off, cl_cfg_off,
                        base + kHeader, reinterpret_cast<uint32_t *>(base), (hipStream_t)stream,
                        nullptr);
@@ -528,6 +576,8 @@ c2_status c2_cluster_keys(const c2_profiles *P, const uint32_t *keys, const uint
     if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_CLUSTER))) != C2_OK)
         return st;
     char *base = reinterpret_cast<char *>(ws);
+    C2_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(base) + 1, 0, 1, (hipStream_t)stream),
+           "status");
     return run_cluster(P, bucket, p, form, tune, rounds_from(tune), members, cl_off, cl_cfg_off,
                        base + kHeader, reinterpret_cast<uint32_t *>(base), (hipStream_t)stream,
                        nullptr, keys);
@@ -535,11 +585,14 @@ c2_status c2_cluster_keys(const c2_profiles *P, const uint32_t *keys, const uint
 
 c2_status c2_check_complete(const void *ws, void *stream) {
     if (!ws) return fail(C2_E_ARG, "workspace is NULL");
-    uint32_t h = 0;
+    uint32_t h[2] = {0, 0};
     hipStream_t s = (hipStream_t)stream;
-    C2_TRY(hipMemcpyAsync(&h, ws, 4, hipMemcpyDeviceToHost, s), "status copy");
+    C2_TRY(hipMemcpyAsync(h, ws, 8, hipMemcpyDeviceToHost, s), "status copy");
     C2_TRY(hipStreamSynchronize(s), "status sync");
-    if (h) return fail(C2_E_INCOMPLETE, "batched clustering needs more split rounds");
+    if (h[0]) return fail(C2_E_INCOMPLETE, "batched clustering needs more split rounds");
+    if (h[1])
+        return fail(C2_E_WORKSPACE, "the workspace's store could not hold every cluster's "
+                                    "dictionary rows (pass a larger workspace)");
     return C2_OK;
 }
 
@@ -552,10 +605,13 @@ c2_status c2_local_knn(const c2_profiles *P, const uint32_t *members, const uint
     if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
     if ((st = check_form(form)) != C2_OK) return st;
     if (!members || !cl_off || !cl_cfg_off || !part_id || !part_I) return fail(C2_E_ARG, "NULL pointer");
-    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_LOCAL_KNN))) != C2_OK)
+    if ((st = check_ws(ws, ws_bytes, kHeader + knn_min_bytes(P->n, p->t * P->n, P->m))) != C2_OK)
         return st;
+    char *base = reinterpret_cast<char *>(ws);
+    C2_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(base), 0, 1, (hipStream_t)stream), "status");
     return run_knn(P, members, cl_off, cl_cfg_off, p->t, p->k, form, tune, part_id, part_I,
-                   reinterpret_cast<char *>(ws) + kHeader, (hipStream_t)stream);
+                   base + kHeader, ws_bytes - kHeader, reinterpret_cast<uint32_t *>(base) + 1,
+                   (hipStream_t)stream);
 }
 
 c2_status c2_local_knn_alg2(const c2_profiles *P, const uint32_t *members, const uint32_t *cl_off,
@@ -568,11 +624,12 @@ c2_status c2_local_knn_alg2(const c2_profiles *P, const uint32_t *members, const
     if (!members || !cl_off || !cl_cfg_off || !part_id || !part_I || !hy)
         return fail(C2_E_ARG, "NULL pointer");
     if (hy->rho < 1) return fail(C2_E_ARG, "rho must be >= 1");
-    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_LOCAL_KNN_ALG2))) != C2_OK)
+    const Alg2Layout L = alg2_layout(P->n, P->m, P->nnz, p);
+    if ((st = check_ws(ws, ws_bytes, L.knn + knn_min_bytes(P->n, p->t * P->n, P->m))) != C2_OK)
         return st;
     hipStream_t s = (hipStream_t)stream;
     char *base = reinterpret_cast<char *>(ws);
-    const Alg2Layout L = alg2_layout(P->n, P->m, p);
+    uint32_t *status = reinterpret_cast<uint32_t *>(base) + 1;
     const uint32_t t = p->t, k = p->k, n = P->n;
     const uint64_t NE = (uint64_t)t * n;
     // the partition on the host: which clusters take Hyrec
@@ -593,7 +650,7 @@ c2_status c2_local_knn_alg2(const c2_profiles *P, const uint32_t *members, const
     }
     if (big.empty())
         return run_knn(P, members, cl_off, cl_cfg_off, t, k, C2_FORM_PLAIN, tune, part_id, part_I,
-                       base + L.knn, s);
+                       base + L.knn, ws_bytes - L.knn, status, s);
     if (ncl >= (1u << 24) || n >= (1u << 28))
         return fail(C2_E_UNSUPPORTED, "Hyrec needs fewer than 2^24 clusters and 2^28 users");
     {   // exact keys need |P_u| + |P_v| < 2^16
@@ -627,14 +684,17 @@ c2_status c2_local_knn_alg2(const c2_profiles *P, const uint32_t *members, const
     C2_TRY(hipMemcpyAsync(d_off2, off2.data(), 4 * off2.size(), hipMemcpyHostToDevice, s), "copy");
     C2_TRY(hipMemcpyAsync(d_cfg2, cfg2.data(), 4 * ((size_t)t + 1), hipMemcpyHostToDevice, s), "copy");
     st = run_knn(P, members, d_off2, d_cfg2, t, k, C2_FORM_PLAIN, tune, part_id, part_I,
-                 base + L.knn, s);
+                 base + L.knn, ws_bytes - L.knn, status, s);
     C2_TRY(hipStreamSynchronize(s), "sync");  // off2 / cfg2 copied before they go
     if (st != C2_OK) return st;
-    // Hyrec on the big clusters, reading the bit rows the local KNN left
+    // Hyrec on the big clusters, over full bit rows and the profile lengths the
+    // local KNN left
+    const uint32_t wmax = full_row_words(P->m);
+    uint32_t *rows = reinterpret_cast<uint32_t *>(base + L.rows);
+    C2_TRY(launch_user_bits(P->indptr, P->indices, P->nnz, n, P->m, rows, s), "hyrec rows");
     KnnWs kw;
-    const uint32_t wmax = knn_wmax(P->m);
-    knn_ws_bytes(n, (uint32_t)NE, wmax, &kw);
-    const KnnPtrs kp = knn_ptrs(base + L.knn, kw);
+    knn_ws_fixed(n, (uint32_t)NE, P->m, &kw);
+    const KnnPtrs kp = knn_ptrs(base + L.knn, ws_bytes - L.knn, kw, nullptr);
     uint64_t *kA = reinterpret_cast<uint64_t *>(base + L.keyA);
     uint64_t *kB = reinterpret_cast<uint64_t *>(base + L.keyB);
     uint32_t *iA = reinterpret_cast<uint32_t *>(base + L.IA);
@@ -645,12 +705,12 @@ c2_status c2_local_knn_alg2(const c2_profiles *P, const uint32_t *members, const
         while (cfg[j + 1] <= c) ++j;
         const uint32_t *S = members + off[c];
         const uint32_t sz = off[c + 1] - off[c];
-        C2_TRY(launch_hyrec_step(kp.rows, kp.rlen, wmax, S, sz, k, c, hy->seed, true, nullptr, kA,
+        C2_TRY(launch_hyrec_step(rows, kp.rlen, wmax, S, sz, k, c, hy->seed, true, nullptr, kA,
                                  iA, upd, s),
                "hyrec init");
         for (uint32_t it = 0; it < hy->max_iter; ++it) {
             C2_TRY(launch_fill_u32(upd, 0, 1, s), "hyrec");
-            C2_TRY(launch_hyrec_step(kp.rows, kp.rlen, wmax, S, sz, k, c, hy->seed, false, kA, kB,
+            C2_TRY(launch_hyrec_step(rows, kp.rlen, wmax, S, sz, k, c, hy->seed, false, kA, kB,
                                      iB, upd, s),
                    "hyrec step");
             uint32_t h = 0;
@@ -681,8 +741,8 @@ c2_status c2_merge(const c2_profiles *P, const uint32_t *part_id, const uint32_t
 static c2_status build_impl(const c2_profiles *P, const uint64_t *tab, const c2_params *p,
                             int form, const c2_tuning *tune, uint32_t rounds_batched,
                             uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U, char *base,
-                            hipStream_t s, uint32_t *rounds_used) {
-    const BuildLayout L = build_layout(P->n, P->m, p);
+                            size_t ws_bytes, hipStream_t s, uint32_t *rounds_used) {
+    const BuildLayout L = build_layout(P->n, P->m, P->nnz, p);
     uint32_t *bucket = reinterpret_cast<uint32_t *>(base + L.bucket);
     uint32_t *members = reinterpret_cast<uint32_t *>(base + L.members);
     uint32_t *cl_off = reinterpret_cast<uint32_t *>(base + L.cl_off);
@@ -694,7 +754,8 @@ static c2_status build_impl(const c2_profiles *P, const uint64_t *tab, const c2_
                                base + L.scratch, reinterpret_cast<uint32_t *>(base), s,
                                rounds_used);
     if (st != C2_OK) return st;
-    st = run_knn(P, members, cl_off, cl_cfg, p->t, p->k, form, tune, pid, pI, base + L.scratch, s);
+    st = run_knn(P, members, cl_off, cl_cfg, p->t, p->k, form, tune, pid, pI, base + L.scratch,
+                 ws_bytes - L.scratch, reinterpret_cast<uint32_t *>(base) + 1, s);
     if (st != C2_OK) return st;
     C2_TRY(launch_merge(P->indptr, P->nnz, P->n, p->t, p->k, pid, pI, knn_id, knn_I, knn_U, s),
            "merge");
@@ -709,10 +770,9 @@ c2_status c2_build(const c2_profiles *P, const uint64_t *tab, const c2_params *p
     if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
     if ((st = check_form(form)) != C2_OK) return st;
     if (!tab || !knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
-    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_BUILD))) != C2_OK)
-        return st;
+    if ((st = check_ws(ws, ws_bytes, build_min_bytes(P->n, P->m, P->nnz, p))) != C2_OK) return st;
     return build_impl(P, tab, p, form, tune, rounds_from(tune), knn_id, knn_I, knn_U,
-                      reinterpret_cast<char *>(ws), (hipStream_t)stream, nullptr);
+                      reinterpret_cast<char *>(ws), ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 c2_status c2_build_noalloc(const c2_profiles *P, const uint64_t *tab, const c2_params *p,
@@ -732,8 +792,8 @@ c2_status c2_build_noalloc(const c2_profiles *P, const uint64_t *tab, const c2_p
     char *base = nullptr;
     if ((st = noalloc_base(&base)) != C2_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    st = build_impl(P, tab, p, form, tune, rounds_from(tune), knn_id, knn_I, knn_U, base, s,
-                    nullptr);
+    st = build_impl(P, tab, p, form, tune, rounds_from(tune), knn_id, knn_I, knn_U, base,
+                    kNoAllocBytes, s, nullptr);
     if (st != C2_OK) return st;
     if (status_out) {
         hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, s,
@@ -750,7 +810,7 @@ c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uin
     if ((st = check_profiles(P)) != C2_OK) return st;
     if ((st = check_sizes(P->n, P->m, P->nnz, &one, true)) != C2_OK) return st;
     if (!knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
-    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, &one, C2_OP_BRUTE_FORCE))) != C2_OK)
+    if ((st = check_ws(ws, ws_bytes, brute_head(P->n, k) + knn_min_bytes(P->n, P->n, P->m))) != C2_OK)
         return st;
     hipStream_t s = (hipStream_t)stream;
     char *base = reinterpret_cast<char *>(ws);
@@ -765,13 +825,15 @@ c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uin
     off += al(4 * (size_t)P->n * k);
     uint32_t *pI = reinterpret_cast<uint32_t *>(base + off);
     off += al(4 * (size_t)P->n * k);
+    C2_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(base), 0, 1, s), "status");
     // one cluster holding every user: members = 0..n-1, cl_off = {0, n}, cl_cfg = {0, 1}
     C2_TRY(launch_iota(members, P->n, s), "brute force setup");
     C2_TRY(launch_fill_u32(cl_off, 0, 1, s), "brute force setup");
     C2_TRY(launch_fill_u32(cl_off + 1, P->n, 1, s), "brute force setup");
     C2_TRY(launch_fill_u32(cl_cfg, 0, 1, s), "brute force setup");
     C2_TRY(launch_fill_u32(cl_cfg + 1, 1, 1, s), "brute force setup");
-    st = run_knn(P, members, cl_off, cl_cfg, 1, k, C2_FORM_BATCHED, nullptr, pid, pI, base + off, s);
+    st = run_knn(P, members, cl_off, cl_cfg, 1, k, C2_FORM_BATCHED, nullptr, pid, pI, base + off,
+                 ws_bytes - off, reinterpret_cast<uint32_t *>(base) + 1, s);
     if (st != C2_OK) return st;
     C2_TRY(launch_merge(P->indptr, P->nnz, P->n, 1, k, pid, pI, knn_id, knn_I, knn_U, s), "merge");
     return C2_OK;
@@ -793,13 +855,13 @@ c2_status c2_graph_create(const c2_profiles *P, const uint64_t *tab, const c2_pa
     if ((st = check_profiles(P)) != C2_OK) return st;
     if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
     if (!tab || !knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
-    if ((st = check_ws(ws, ws_bytes, c2_workspace_bytes(P->n, P->m, P->nnz, p, C2_OP_BUILD))) != C2_OK)
-        return st;
+    if ((st = check_ws(ws, ws_bytes, build_min_bytes(P->n, P->m, P->nnz, p))) != C2_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     char *base = reinterpret_cast<char *>(ws);
     // plain build once: learns the number of split rounds and loads the kernels
     uint32_t rounds = 0;
-    st = build_impl(P, tab, p, C2_FORM_PLAIN, tune, 0, knn_id, knn_I, knn_U, base, s, &rounds);
+    st = build_impl(P, tab, p, C2_FORM_PLAIN, tune, 0, knn_id, knn_I, knn_U, base, ws_bytes, s,
+                    &rounds);
     if (st != C2_OK) return st;
     C2_TRY(hipStreamSynchronize(s), "graph warm-up");
     hipStream_t cap;
@@ -810,7 +872,7 @@ c2_status c2_graph_create(const c2_profiles *P, const uint64_t *tab, const c2_pa
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         st = build_impl(P, tab, p, C2_FORM_BATCHED, tune, g->rounds, knn_id, knn_I, knn_U, base,
-                        cap, nullptr);
+                        ws_bytes, cap, nullptr);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &graph);
         if (st == C2_OK && e2 != hipSuccess) st = hip_fail(e2, "end capture");

@@ -10,7 +10,7 @@
 namespace c2 {
 
 constexpr uint32_t kPad = 0xFFFFFFFFu;
-constexpr uint32_t kMaxItems = 131072;  // LDS dictionary limit
+constexpr uint32_t kMaxItems = 1u << 19;  // LDS dictionary bitmaps (two of m bits)
 constexpr uint32_t kMaxK = 32;
 
 // Cluster state stored at a segment's first position during splitting.

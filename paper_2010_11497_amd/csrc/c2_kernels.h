@@ -94,40 +94,47 @@ struct KnnArgs {
     uint64_t nnz;
     uint32_t n, m, t, k;
     const uint32_t *members, *cl_off, *cl_cfg_off;
-    uint32_t NE;    // t*n member slots
-    uint32_t wmax;  // words per user bit row (item universe padded to 64)
+    uint32_t NE;  // t*n member slots
+    uint32_t Wm;  // words of an item bitmap (m bits): the dictionary maps
     uint32_t *part_id, *part_I;
 };
-struct KnnWs {
-    size_t rows, rlen, cnt, items_m, items_b, slots, sbase, rb_done, skeys, csort_key,
-        csort_key_alt, csort_val, csort_val_alt, hist, htmp, ctmp, ctr, bmax, pc, ccls, cpos,
-        cbits, cw, coff, ccur, total;
-    size_t cbits_words;  // capacity of the compacted-row region
+struct KnnWs {  // byte offsets; the store takes the rest of the region
+    size_t rlen, cnt, items_m, items_b, slots, sbase, rb_done, skeys, htmp, ctmp, ctr, bmax, pc,
+        ccls, cpos, cw, coff, ccur, dslot, dmap, store, total;
 };
 struct KnnPtrs {
-    uint32_t *rows, *rlen;
+    uint32_t *rlen;
     uint64_t *cnt, *items_m, *items_b;
     uint32_t *slots, *sbase, *rb_done;
     uint64_t *skeys;
-    uint64_t *csort_key, *csort_key_alt;
-    uint32_t *csort_val, *csort_val_alt, *hist, *htmp;
+    uint32_t *htmp;
     uint64_t *ctmp;
     uint32_t *ctr, *bmax, *pc, *ccls, *cpos;
-    uint32_t *cbits, *cw;          // compacted rows, words per compacted row of each cluster
-    uint64_t *coff;                // first word of each compacted cluster in cbits
-    unsigned long long *ccur;      // allocation cursor of cbits
-    uint64_t cbits_words;
+    uint32_t *cw;                  // words per dictionary row of each cluster, 0 = not staged
+    uint64_t *coff;                // first word of each cluster's rows in the store
+    unsigned long long *ccur;      // allocation cursor of the store
+    uint32_t *dslot, *dmap;        // dictionary maps of the clusters larger than kBigS
+    uint32_t *store;               // the rows of every cluster over its dictionary
+    uint64_t store_words;          // capacity of the store
+    uint32_t *status;              // set to 1 when the store is too small (caller's header word)
 };
-size_t knn_ws_bytes(uint32_t n, uint32_t NE, uint32_t wmax, KnnWs *w);
-uint32_t knn_wmax(uint32_t m);
-size_t knn_stage_lds_bytes(uint32_t m, uint32_t wmax);
+// Workspace of the local KNN without the store, and the store's default size.
+size_t knn_ws_fixed(uint32_t n, uint32_t NE, uint32_t m, KnnWs *w);
+size_t knn_store_default_bytes(uint32_t n, uint32_t NE, uint32_t m, uint64_t nnz, uint32_t t);
+uint32_t dict_words(uint32_t m);
+// Full bit rows over all items (words per row), for the Hyrec branch.
+uint32_t full_row_words(uint32_t m);
+hipError_t launch_user_bits(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                            uint32_t n, uint32_t m, uint32_t *rows, hipStream_t s);
 struct KnnOpts {
     uint32_t persistent_wgs = 0;
     uint32_t mfma_min = 0;
     uint32_t group_tiles = 0;
-    uint32_t compact = 0;  // 0 automatic, 1 off, 2 on
+    uint32_t tile32_max = 0, tile64_max = 0;  // cluster sizes up to which 32- / 64-row tiles are used
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
+// Both return hipErrorOutOfMemory (plain form) when the store cannot hold the
+// partition's dictionary rows; the batched form sets *status instead.
 hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s);
 hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipStream_t s);
 

@@ -48,7 +48,12 @@ def test_workspace_queries_host_only(lib):
     bad = c2.params(8, 1024, 2000, 33)          # k > 32
     assert lib.c2_workspace_bytes(n, m, nnz, ctypes.byref(bad), c2.OP_BUILD) == 0
     assert b"k = 33" in lib.c2_last_error()
-    assert lib.c2_workspace_bytes(n, 200000, nnz, ctypes.byref(p), c2.OP_BUILD) == 0   # m too big
+    assert lib.c2_workspace_bytes(n, 200000, nnz, ctypes.byref(p), c2.OP_BUILD) > 0    # DBLP-sized
+    assert lib.c2_workspace_bytes(n, (1 << 19) + 1, nnz, ctypes.byref(p), c2.OP_BUILD) == 0
+    assert b"m = 524289" in lib.c2_last_error()
+    # the store takes what is left: the default holds more than the minimum
+    assert (lib.c2_workspace_bytes(n, m, nnz, ctypes.byref(p), c2.OP_LOCAL_KNN) >
+            lib.c2_workspace_bytes(n, m, nnz, ctypes.byref(p), c2.OP_LOCAL_KNN_MIN) > 0)
     assert lib.c2_workspace_bytes(n, m, nnz, ctypes.byref(p), 99) == 0
     fp = c2.params(1, 1024, 1, 1)                # fingerprint: p->b is the width in bits
     assert lib.c2_workspace_bytes(n, m, nnz, ctypes.byref(fp), c2.OP_FINGERPRINT) >= n * 128

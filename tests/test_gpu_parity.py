@@ -475,20 +475,26 @@ def test_brute_force_sampled_large(orc, name):
 
 # ------------------------------------------- per-cluster dictionaries ----
 
+SHAPES = {"default": {}, "all128": dict(tile32_max=1, tile64_max=1),
+          "all64": dict(tile32_max=1, tile64_max=1 << 30), "all32": dict(tile32_max=1 << 30)}
+
+
+@pytest.mark.parametrize("shape", list(SHAPES))
 @pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
 @pytest.mark.parametrize("name,P,tab,b,cap,k", CASES + [
     ("sparse", synth.random_profiles(9600, 3000, 20000, 5, 120, 1.0), synth.hash_tables(4, 9601),
      64, 400, 16)], ids=[c[0] for c in CASES] + ["sparse"])
-def test_local_knn_compacted(orc, name, P, tab, b, cap, k, form):
-    """The local KNN over per-cluster dictionaries (forced on) against the
-    oracle on the oracle's partition: the compaction must not change a bit."""
-    say("local_knn compact", name, form)
+def test_local_knn_tile_shapes(orc, name, P, tab, b, cap, k, form, shape):
+    """The local KNN with each MFMA tile shape forced on every cluster (32-,
+    64- and 128-row tiles: short row pieces, partial blocks and tiles that
+    overhang the cluster) against the oracle on the oracle's partition."""
+    say("local_knn shape", name, form, shape)
     t = tab.shape[0]
     om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, orc.hash_items(tab, b, P.m), cap)
     dP = c2.DeviceProfiles.from_synth(P)
     dev = lambda a: torch.as_tensor(a.astype(np.uint32).view(np.int32)).cuda()
     pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), c2.params(t, b, cap, k), form,
-                           c2.tuning(compact=c2.COMPACT_ON))
+                           c2.tuning(**SHAPES[shape]))
     wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
     assert np.array_equal(u32(pid), wid)
     assert np.array_equal(u32(pI), wI)
@@ -509,69 +515,105 @@ def _blocks_partition(n, t, size, seed):
             np.asarray(cfg, np.uint32))
 
 
-@pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
-def test_local_knn_compaction_store_overflow(orc, form):
-    """More clusters want compacted rows than the store holds (it reserves
-    half of every member slot's full row): those past the end keep their full
-    rows.  Rows of 512 words; clusters of 400 users with 70-95 uniform items
-    each hold about 2 copies of an average item, so about 60 % of the items
-    are shared and every cluster's compacted width (~312 words) is below the
-    three-quarter limit while their total exceeds the store."""
-    n, m, t, k, size = 4000, 16384, 2, 10, 400
-    P = synth.random_profiles(77, n, m, 70, 95)
-    om, ooff, ocfg = _blocks_partition(n, t, size, 78)
-    W = (m + 255) // 256 * 8
+def _store_words(P, om, ooff):
+    """Words of dictionary rows the partition needs: rows padded to 32 (or s
+    below 32), 8 words per 256 dictionary items (at least 8)."""
     ip = np.asarray(P.indptr)
-    want_words = 0
+    need = 0
     for c in range(len(ooff) - 1):
         mem = om[ooff[c]:ooff[c + 1]]
+        if len(mem) < 2:
+            continue
         items = np.concatenate([P.indices[ip[u]:ip[u + 1]] for u in mem])
-        D = int((np.bincount(items, minlength=m) >= 2).sum())
-        wc = (max(D, 1) + 255) // 256 * 8
-        assert 4 * wc <= 3 * W               # every cluster qualifies
-        want_words += len(mem) * wc
-    assert want_words > t * n * W // 2       # and together they overflow the store
-    say("local_knn compact overflow", form)
+        D = int((np.bincount(items, minlength=P.m) >= 2).sum())
+        rows = len(mem) if len(mem) < 32 else (len(mem) + 31) // 32 * 32
+        need += rows * 8 * max(1, (D + 255) // 256)
+    return need
+
+
+@pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
+def test_local_knn_store_sizes(orc, form):
+    """The store takes whatever workspace the caller passes beyond the fixed
+    part: exactly the partition's dictionary rows suffice and give the
+    oracle's lists; one 256-word row block less is reported (plain form:
+    C2_E_WORKSPACE from the call; batched form: from c2_check_complete)."""
+    n, m, t, k, size = 3000, 16384, 2, 10, 400
+    P = synth.random_profiles(77, n, m, 70, 95)
+    om, ooff, ocfg = _blocks_partition(n, t, size, 78)
+    need = _store_words(P, om, ooff)
+    say("local_knn store sizes", form, need)
     dP = c2.DeviceProfiles.from_synth(P)
     dev = lambda a: torch.as_tensor(a.astype(np.uint32).view(np.int32)).cuda()
     p = c2.params(t, 64, size, k)
+    fixed = c2.workspace_bytes(dP, p, c2.OP_LOCAL_KNN_MIN) - 4096
     wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
-    for mode in (c2.COMPACT_ON, c2.COMPACT_AUTO):
-        pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, c2.tuning(compact=mode))
-        assert np.array_equal(u32(pid), wid)
-        assert np.array_equal(u32(pI), wI)
+    ws = torch.empty(fixed + 4 * need, dtype=torch.uint8, device="cuda")
+    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, ws=ws)
+    if form == c2.FORM_BATCHED:
+        c2.check_complete(ws)
+    assert np.array_equal(u32(pid), wid)
+    assert np.array_equal(u32(pI), wI)
+    assert c2.store_need_bytes(ws) == 4 * need
+    small = torch.empty(fixed + 4 * (need - 256), dtype=torch.uint8, device="cuda")
+    with pytest.raises(c2.C2Error) as e:
+        c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, ws=small)
+        c2.check_complete(small)
+    assert e.value.status == -3
+    assert c2.store_need_bytes(small) == 4 * need
+    # the binding grows a workspace it allocated itself and runs again
+    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, c2.FORM_PLAIN)
+    assert np.array_equal(u32(pid), wid)
 
 
+@pytest.mark.parametrize("m", [200000, 1 << 19])
 @pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
-def test_local_knn_compacted_widest_rows(orc, form):
-    """The largest item universe (m = 131072: rows of 4096 words, where the
-    dictionary pass runs with 256 threads and its LDS is largest), dictionaries
-    forced on and automatic, against the oracle on the oracle's partition."""
-    n, m, t, b, cap, k = 1500, 131072, 3, 16, 300, 12
+def test_local_knn_wide_item_universe(orc, form, m):
+    """Item universes beyond the 131,072 of the previous bit-row design: a
+    DBLP-sized one (Table 1: 203,030 items) and the library's limit 2^19
+    (dictionary bitmaps of 64 KiB each in LDS), against the oracle on the
+    oracle's partition, and the whole build."""
+    n, t, b, cap, k = 1500, 3, 16, 300, 12
     P = synth.random_profiles(91, n, m, 20, 400, 0.9)
     tab = synth.hash_tables(t, 92)
     om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, orc.hash_items(tab, b, P.m), cap)
-    say("local_knn compact widest", form)
+    say("local_knn wide", form, m)
     dP = c2.DeviceProfiles.from_synth(P)
     dev = lambda a: torch.as_tensor(a.astype(np.uint32).view(np.int32)).cuda()
     wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
-    for mode in (c2.COMPACT_ON, c2.COMPACT_AUTO):
-        pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), c2.params(t, b, cap, k), form,
-                               c2.tuning(compact=mode))
-        assert np.array_equal(u32(pid), wid)
-        assert np.array_equal(u32(pI), wI)
+    p = c2.params(t, b, cap, k)
+    # long profiles over a wide universe need more store than the default: the
+    # plain form reports the need (the binding then grows its workspace); the
+    # batched form is given a workspace of that size and checked afterwards
+    ws = torch.empty(c2.workspace_bytes(dP, p, c2.OP_LOCAL_KNN_MIN) + 4 * _store_words(P, om, ooff),
+                     dtype=torch.uint8, device="cuda")
+    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form,
+                           ws=None if form == c2.FORM_PLAIN else ws)
+    if form == c2.FORM_BATCHED:
+        c2.check_complete(ws)
+    assert np.array_equal(u32(pid), wid)
+    assert np.array_equal(u32(pI), wI)
+    wsb = torch.empty(c2.workspace_bytes(dP, p, c2.OP_BUILD) + 4 * _store_words(P, om, ooff),
+                      dtype=torch.uint8, device="cuda")
+    got = c2.build(dP, c2.tables_to_device(tab), p, form, c2.tuning(split_rounds=64),
+                   ws=None if form == c2.FORM_PLAIN else wsb)
+    if form == c2.FORM_BATCHED:
+        c2.check_complete(wsb)
+    r = orc.build_graph(P.indptr, P.indices, P.n, P.m, tab, b, cap, k, THREADS)
+    for g, w in zip(got, (r.knn_id, r.knn_I, r.knn_U)):
+        assert np.array_equal(u32(g), w)
 
 
-def test_compaction_on_equals_off_n6k():
+def test_tile_shapes_agree_n6k():
     w = synth.WORKLOADS["n6k_m3.7k"]
     P = synth.make_profiles(w)
     dP, dtab = gpu_inputs(P, synth.hash_tables(w.t, w.hash_seed))
     p = c2.params(w.t, w.b, w.cap, w.k)
-    on = c2.build(dP, dtab, p, c2.FORM_BATCHED, c2.tuning(split_rounds=16, compact=c2.COMPACT_ON))
-    off = c2.build(dP, dtab, p, c2.FORM_BATCHED, c2.tuning(split_rounds=16, compact=c2.COMPACT_OFF))
-    torch.cuda.synchronize()
-    for a, b2 in zip(on, off):
-        assert torch.equal(a, b2)
+    ref = c2.build(dP, dtab, p, c2.FORM_BATCHED, c2.tuning(split_rounds=16))
+    for shape in ("all128", "all32"):
+        got = c2.build(dP, dtab, p, c2.FORM_BATCHED, c2.tuning(split_rounds=16, **SHAPES[shape]))
+        torch.cuda.synchronize()
+        for a, b2 in zip(ref, got):
+            assert torch.equal(a, b2)
 
 
 @pytest.mark.parametrize("name", ["n140k_m27k", "n500k_m50k"])
