@@ -17,14 +17,16 @@
 //
 // Pairwise counts.  |P_u & P_v| is the dot product of two rows over D_C and
 // |P_u | P_v| = |P_u| + |P_v| - |P_u & P_v|.  A work item is one row block of
-// TR = 32 * NB members of a cluster (NB = 1, 2 or 4, chosen per cluster size)
-// taken against the cluster's column tiles of TR members, by one wave.  Per
-// 64-position chunk the wave expands the bits of its NB column-member and NB
-// row-member fragments to fp4 (e2m1) nibbles in registers (0x2 = 1.0 for a
-// set bit) and issues NB x NB v_mfma_scale_f32_32x32x64_f8f6f4 at unit block
-// scale; the fp32 sums are integer counts below 2^24, hence exact.  The
-// accumulators (up to 16 x 16 values per lane) stay in registers: lane l
-// holds row member 32*bj + l % 32 of every block (bi, bj) against 16 column
+// a cluster's members taken against its column tiles, by one wave, in one of
+// three tile shapes chosen per cluster size (tunable): 32 x 32, 64 x 64, or
+// 64 rows x 128 columns.  Per 64-position chunk the wave expands the bits of
+// its column-member and row-member fragments to fp4 (e2m1) nibbles in
+// registers (0x2 = 1.0 for a set bit) and issues one
+// v_mfma_scale_f32_32x32x64_f8f6f4 per 32 x 32 block at unit block scale;
+// the fp32 sums are integer counts below 2^24, hence exact.  The accumulators
+// (up to 8 x 16 values per lane) stay in registers, two waves per SIMD so
+// that one wave's selection runs beside the other's products: lane l holds
+// row member 32 * bj + l % 32 of every block (bi, bj) against 16 column
 // members, so selection reads its candidates straight from the accumulators.
 //
 // Selection.  Each row member keeps a bounded heap of its k best candidates
@@ -44,15 +46,16 @@ namespace c2 {
 
 constexpr uint32_t kRowBlock = 64;   // rows (members) per bitmap work item
 constexpr int kWordChunk = 16;       // row words staged per step (bitmap path)
-constexpr uint32_t kTR = 128;        // rows of the largest MFMA tile (NB = 4)
+constexpr uint32_t kRows = 64;       // rows of the largest MFMA tile (row members of a work item)
+constexpr uint32_t kCols = 128;      // columns of the largest MFMA tile
 constexpr uint32_t kDefaultMfmaMin = 2;
 constexpr uint32_t kDefaultTile32 = 32;   // clusters up to this size: 32-row tiles
 constexpr uint32_t kDefaultTile64 = 64;   // up to this size: 64-row tiles, else 128
-constexpr uint32_t kGroupTiles = 4;  // column tiles per work item before a row block is split
+constexpr uint32_t kGroupTiles = 16; // column tiles per work item before a row block is split
 constexpr uint32_t kMaxGroups = 4;   // column groups a row block is split into at most
 constexpr uint32_t kLensGrid = 2048;  // blocks of k_lens at most
 constexpr uint32_t kBitmapPersistent = 256;  // persistent bitmap-path workgroups (batched form)
-constexpr uint32_t kDefaultWaves = 1024;     // persistent MFMA waves (4 per CU)
+constexpr uint32_t kDefaultWaves = 2048;     // persistent MFMA waves (8 per CU, 2 per SIMD)
 // batched planning counters: kCostClasses item counts, then scratch slots and
 // bitmap items
 constexpr uint32_t kCostClasses = 64;
@@ -150,6 +153,10 @@ struct StoreView {
 C2_DEV uint64_t mfma_item_code(uint32_t c, uint32_t rb, uint32_t nbc, uint32_t g, uint32_t ng) {
     return ((uint64_t)c << 32) | ((uint64_t)rb << 8) | (nbc << 6) | (g << 4) | (ng - 1);
 }
+// Tile shapes: 0 = 32 rows x 32 columns, 1 = 64 x 64, 2 = 64 x 128.
+C2_DEV uint32_t shape_rows(uint32_t tc) { return tc == 0 ? 32u : 64u; }
+C2_DEV uint32_t shape_cols(uint32_t tc) { return 32u << tc; }
+
 // The first item of a cluster: row block 0, column group 0.
 C2_DEV bool first_item(uint64_t code) {
     return ((uint32_t)code >> 8) == 0 && (((uint32_t)code >> 4) & 3u) == 0;
@@ -366,7 +373,7 @@ __global__ __launch_bounds__(kStageThreads) void k_rows(KnnArgs a, const uint64_
             loaded = c;
             __syncthreads();
         }
-        const uint32_t nb = 1u << ((uint32_t)code >> 6 & 3u), rb = (uint32_t)code >> 8;
+        const uint32_t nb = shape_rows((uint32_t)code >> 6 & 3u) / 32, rb = (uint32_t)code >> 8;
         const uint32_t u0 = rb * nb, nblk = (cv.s + 31) / 32;
         const uint32_t u1 = u0 + nb < nblk ? u0 + nb : nblk;
         write_rows<NT>(a, cv, u0, u1, st.cw[c] / 8, st.bits + st.coff[c], twice, pre, win);
@@ -629,14 +636,14 @@ C2_DEV uint32_t key_to_I(uint32_t key, uint32_t S) {
     return (uint32_t)(x + 0.5f);
 }
 
-// Bounded heap of one row's k best keys in LDS, hk[slot * kTR + row].
+// Bounded heap of one row's k best keys in LDS, hk[slot * kRows + row].
 struct KeyHeap {
     uint64_t *hk;
     uint32_t me, k, cnt;
     uint64_t root;  // valid once full
 
-    C2_DEV uint64_t get(uint32_t i) const { return hk[i * kTR + me]; }
-    C2_DEV void put(uint32_t i, uint64_t v) { hk[i * kTR + me] = v; }
+    C2_DEV uint64_t get(uint32_t i) const { return hk[i * kRows + me]; }
+    C2_DEV void put(uint32_t i, uint64_t v) { hk[i * kRows + me] = v; }
     // 4-ary min-heap: the children of p are 4p+1 .. 4p+4.  The four child
     // slots are read together (an index past the end reads the last entry
     // again, which never wins the strict comparisons), so each level costs one
@@ -703,16 +710,16 @@ C2_DEV float sigma_of(uint64_t root) {
 }
 
 struct MfmaScratch {
-    uint64_t *keys;         // [slot][kTR][kMaxK]
+    uint64_t *keys;         // [slot][kRows][kMaxK]
     uint32_t *rb_done;      // per (cluster, row block) of a split row block
     const uint32_t *sbase;  // first slot of each cluster
 };
 
 struct __attribute__((aligned(16))) WaveLds {
-    uint64_t hk[kMaxK * kTR];  // heaps, [slot][row]
-    uint32_t hcnt[kTR];        // entries per heap
-    uint32_t cuid[kTR], clen[kTR];
-    uint32_t scr[64 * 8];      // 16 counts (u16) per lane
+    uint64_t hk[kMaxK * kRows];  // heaps, [slot][row]
+    uint32_t hcnt[kRows];        // entries per heap
+    uint32_t cuid[kCols], clen[kCols];
+    uint32_t scr[64 * 8];        // 16 counts (u16) per lane
 };
 
 // Column member of the accumulator value r of block bi in lane half hh.
@@ -734,32 +741,31 @@ C2_DEV uint4 buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
-// The NB column-member and NB row-member fragments of one group.
-template <int NB>
-C2_DEV void load_group(const __amdgpu_buffer_rsrc_t (&rA)[NB], const __amdgpu_buffer_rsrc_t (&rB)[NB],
-                       uint32_t off, uint4 (&xa)[NB], uint4 (&xb)[NB]) {
+// The NC column-member and NR row-member fragments of one group.
+template <int NR, int NC>
+C2_DEV void load_group(const __amdgpu_buffer_rsrc_t (&rA)[NC], const __amdgpu_buffer_rsrc_t (&rB)[NR],
+                       uint32_t off, uint4 (&xa)[NC], uint4 (&xb)[NR]) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        xa[i] = buf_load16(rA[i], off);
-        xb[i] = buf_load16(rB[i], off);
-    }
+    for (int i = 0; i < NC; ++i) xa[i] = buf_load16(rA[i], off);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) xb[i] = buf_load16(rB[i], off);
 }
 
 // acc[bi][bj] += the counts of one group (four 64-position chunks): the
 // row-member operands of a chunk are expanded first, the column-member ones
-// one at a time, each feeding NB MFMAs.
-template <int NB>
-C2_DEV void mult_group(const uint4 (&xa)[NB], const uint4 (&xb)[NB], v16f (&acc)[NB][NB]) {
+// one at a time, each feeding NR MFMAs.
+template <int NR, int NC>
+C2_DEV void mult_group(const uint4 (&xa)[NC], const uint4 (&xb)[NR], v16f (&acc)[NC][NR]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        v4i B[NB];
+        v4i B[NR];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) B[i] = nibbles32(u4get(xb[i], q));
+        for (int i = 0; i < NR; ++i) B[i] = nibbles32(u4get(xb[i], q));
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi) {
+        for (int bi = 0; bi < NC; ++bi) {
             const v4i A = nibbles32(u4get(xa[bi], q));
 #pragma unroll
-            for (int bj = 0; bj < NB; ++bj) acc[bi][bj] = mfma_fp4(A, B[bj], acc[bi][bj]);
+            for (int bj = 0; bj < NR; ++bj) acc[bi][bj] = mfma_fp4(A, B[bj], acc[bi][bj]);
         }
     }
 }
@@ -793,6 +799,21 @@ C2_DEV void select_round(const v16f &acc, uint32_t Lr, bool act, const SelCtx &c
         else pk[r >> 1] = I;
     }
     if (!__any(mask != 0u)) return;
+    // with a full heap, the exact key of every candidate that passed the fp32
+    // test is compared with the root (equal similarities pass that test)
+    if (full) {
+        const uint64_t root = L.hk[R];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if ((mask >> r) & 1u) {
+                const uint32_t I = (pk[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+                const uint32_t col = acc_col(BI, r, cx.hh);
+                const uint32_t U = Lr + L.clen[col] - I, uid = L.cuid[col];
+                if ((((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid)) <= root) mask &= ~(1u << r);
+            }
+        }
+        if (!__any(mask != 0u)) return;
+    }
 #pragma unroll
     for (int q = 0; q < 8; ++q) L.scr[cx.lane * 8 + q] = pk[q];
     wave_sync();
@@ -814,7 +835,8 @@ C2_DEV void select_round(const v16f &acc, uint32_t Lr, bool act, const SelCtx &c
                 const uint32_t I = (L.scr[cx.lane * 8 + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
                 const uint32_t col = acc_col(BI, r, cx.hh);
                 const uint32_t U = Lr + L.clen[col] - I, uid = L.cuid[col];
-                h.insert(((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid));
+                const uint64_t v = ((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid);
+                h.insert(v);
             }
         }
         if (cx.hh == pass && mask) L.hcnt[R] = h.cnt;
@@ -822,27 +844,126 @@ C2_DEV void select_round(const v16f &acc, uint32_t Lr, bool act, const SelCtx &c
     }
 }
 
-// The NB x NB rounds with compile-time block indices (the accumulators stay
-// in registers only if every index into them is a constant).
-template <int NB, int IDX>
-struct Rounds {
-    static C2_DEV void run(v16f (&acc)[NB][NB], const uint32_t (&Lr)[NB], const bool (&act)[NB],
-                           const SelCtx &cx, WaveLds &L) {
-        constexpr int BJ = IDX / NB, BI = IDX % NB;
-        select_round<BJ, BI>(acc[BI][BJ], Lr[BJ], act[BJ], cx, L);
-        Rounds<NB, IDX + 1>::run(acc, Lr, act, cx, L);
+// Row ownership for two row blocks: after the swap, lane (lr, hh) holds in
+// acc[bi][h] the counts of its own row member 32 * hh + lr against the
+// columns of lane half h (v_permlane32_swap exchanges the upper 32 lanes of
+// its first operand with the lower 32 lanes of its second), so that each row
+// is selected by one lane and no two lanes touch one heap.
+// (Whole vectors in and out: writing single elements of the accumulator
+// vectors in place compiled to wrong code.)
+typedef uint32_t v16u __attribute__((ext_vector_type(16)));
+template <int NC>
+C2_DEV void own_rows(v16f (&acc)[NC][2]) {
+#pragma unroll
+    for (int bi = 0; bi < NC; ++bi) {
+        const v16u x = __builtin_bit_cast(v16u, acc[bi][0]), y = __builtin_bit_cast(v16u, acc[bi][1]);
+        v16u nx, ny;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const auto p = __builtin_amdgcn_permlane32_swap(x[r], y[r], false, false);
+            nx[r] = p[0];
+            ny[r] = p[1];
+        }
+        acc[bi][0] = __builtin_bit_cast(v16f, nx);
+        acc[bi][1] = __builtin_bit_cast(v16f, ny);
+    }
+}
+
+// One selection round on owned rows: the 16 candidates of column block BI,
+// lane half H, for the lane's own row member 32 * hh + lr.
+template <int H, int BI>
+C2_DEV void select_own(const v16f &acc, uint32_t Lr, bool act, const SelCtx &cx, WaveLds &L) {
+    const uint32_t R = 32 * cx.hh + cx.lr;
+    const uint32_t self = cx.rowpos + 32 * cx.hh;
+    const uint32_t cnt0 = L.hcnt[R];
+    const bool full = cnt0 >= cx.k;
+    const uint64_t root = full ? L.hk[R] : 0ull;
+    const float sigma = full ? sigma_of(root) : 0.0f;
+    uint32_t mask = 0;
+    uint32_t pk[8];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const uint32_t col = acc_col(BI, r, H);
+        const uint32_t I = (uint32_t)acc[r];
+        const bool ok = act & (col < cx.ncol) & (col != self) &
+                        (!full || may_beat(I, Lr + L.clen[col], sigma));
+        mask |= (ok ? 1u : 0u) << r;
+        if (r & 1) pk[r >> 1] |= I << 16;
+        else pk[r >> 1] = I;
+    }
+    if (!__any(mask != 0u)) return;
+    if (full) {  // exact keys of the candidates that passed the fp32 test
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if ((mask >> r) & 1u) {
+                const uint32_t I = (pk[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+                const uint32_t col = acc_col(BI, r, H);
+                const uint32_t U = Lr + L.clen[col] - I, uid = L.cuid[col];
+                if ((((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid)) <= root) mask &= ~(1u << r);
+            }
+        }
+        if (!__any(mask != 0u)) return;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) L.scr[cx.lane * 8 + q] = pk[q];
+    wave_sync();
+    KeyHeap h;
+    h.hk = L.hk;
+    h.me = R;
+    h.k = cx.k;
+    h.cnt = cnt0;
+    h.root = root;
+    uint32_t m = mask;
+    while (__any(m != 0u)) {
+        if (m) {
+            const uint32_t r = __ffs(m) - 1;
+            m &= m - 1;
+            const uint32_t I = (L.scr[cx.lane * 8 + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
+            const uint32_t col = acc_col(BI, r, H);
+            const uint32_t U = Lr + L.clen[col] - I, uid = L.cuid[col];
+            h.insert(((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid));
+        }
+    }
+    if (mask) L.hcnt[R] = h.cnt;
+    wave_sync();
+}
+
+template <int NC, int IDX>
+struct OwnRounds {
+    static C2_DEV void run(v16f (&acc)[NC][2], uint32_t Lr, bool act, const SelCtx &cx, WaveLds &L) {
+        constexpr int H = IDX / NC, BI = IDX % NC;
+        select_own<H, BI>(acc[BI][H], Lr, act, cx, L);
+        OwnRounds<NC, IDX + 1>::run(acc, Lr, act, cx, L);
     }
 };
-template <int NB>
-struct Rounds<NB, NB * NB> {
-    static C2_DEV void run(v16f (&)[NB][NB], const uint32_t (&)[NB], const bool (&)[NB],
+template <int NC>
+struct OwnRounds<NC, 2 * NC> {
+    static C2_DEV void run(v16f (&)[NC][2], uint32_t, bool, const SelCtx &, WaveLds &) {}
+};
+
+// The NR x NC rounds with compile-time block indices (the accumulators stay
+// in registers only if every index into them is a constant).
+template <int NR, int NC, int IDX>
+struct Rounds {
+    static C2_DEV void run(v16f (&acc)[NC][NR], const uint32_t (&Lr)[NR], const bool (&act)[NR],
+                           const SelCtx &cx, WaveLds &L) {
+        constexpr int BJ = IDX / NC, BI = IDX % NC;
+        select_round<BJ, BI>(acc[BI][BJ], Lr[BJ], act[BJ], cx, L);
+        Rounds<NR, NC, IDX + 1>::run(acc, Lr, act, cx, L);
+    }
+};
+template <int NR, int NC>
+struct Rounds<NR, NC, NR * NC> {
+    static C2_DEV void run(v16f (&)[NC][NR], const uint32_t (&)[NR], const bool (&)[NR],
                            const SelCtx &, WaveLds &) {}
 };
 
-template <int NB>
+// Work item of one wave: the TRR = 32 * NR row members of row block rb against
+// the cluster's column tiles of TRC = 32 * NC members in column group g.
+template <int NR, int NC>
 C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ulen,
                       const MfmaScratch &sc, uint64_t code, WaveLds &L) {
-    constexpr uint32_t TR = 32 * NB;
+    constexpr uint32_t TRR = 32 * NR, TRC = 32 * NC;
     const uint32_t lane = threadIdx.x & 63, lr = lane & 31, hh = lane >> 5;
     const uint32_t c = (uint32_t)(code >> 32), rb = (uint32_t)code >> 8;
     const uint32_t g = ((uint32_t)code >> 4) & 3u, ng = ((uint32_t)code & 15u) + 1;
@@ -857,72 +978,76 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
     // >= G, lanes beyond a short piece, blocks >= nblk) the loads return 0.
     const uint4 *frag = reinterpret_cast<const uint4 *>(sv.bits + sv.coff[c]);
     const uint32_t voff = (hh * P + lr) * 16, gbytes = 2 * P * 16, xbytes = G * gbytes;
-    // row members of this lane: position rb * TR + 32 * bj + lr
-    uint32_t Lr[NB];
-    bool act[NB];
+    // row members of this lane: position rb * TRR + 32 * bj + lr
+    uint32_t Lr[NR];
+    bool act[NR];
 #pragma unroll
-    for (int bj = 0; bj < NB; ++bj) {
-        const uint32_t p = rb * TR + 32 * bj + lr;
+    for (int bj = 0; bj < NR; ++bj) {
+        const uint32_t p = rb * TRR + 32 * bj + lr;
         act[bj] = p < s;
         Lr[bj] = act[bj] ? ulen[a.members[cv.o + p]] : 0u;
     }
-    for (uint32_t q = lane; q < TR; q += 64) L.hcnt[q] = 0;
-    const uint32_t xb0 = rb * NB;  // first 32-row block of the row members
-    __amdgpu_buffer_rsrc_t rB[NB];
+    for (uint32_t q = lane; q < TRR; q += 64) L.hcnt[q] = 0;
+    __amdgpu_buffer_rsrc_t rB[NR];
 #pragma unroll
-    for (int bj = 0; bj < NB; ++bj) rB[bj] = block_rsrc(frag, xb0 + bj, nblk, G * 2 * P, xbytes);
-    const uint32_t tiles = (s + TR - 1) / TR, per = (tiles + ng - 1) / ng;
+    for (int bj = 0; bj < NR; ++bj) rB[bj] = block_rsrc(frag, rb * NR + bj, nblk, G * 2 * P, xbytes);
+    const uint32_t tiles = (s + TRC - 1) / TRC, per = (tiles + ng - 1) / ng;
     const uint32_t cb_end = (g + 1) * per < tiles ? (g + 1) * per : tiles;
     for (uint32_t cb = g * per; cb < cb_end; ++cb) {
         wave_sync();
-        for (uint32_t q = lane; q < TR; q += 64) {
-            const uint32_t p = cb * TR + q;
+        for (uint32_t q = lane; q < TRC; q += 64) {
+            const uint32_t p = cb * TRC + q;
             const uint32_t u = p < s ? a.members[cv.o + p] : kPad;
             L.cuid[q] = u;
             L.clen[q] = p < s ? ulen[u] : 0u;
         }
-        __amdgpu_buffer_rsrc_t rA[NB];
+        __amdgpu_buffer_rsrc_t rA[NC];
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi) rA[bi] = block_rsrc(frag, cb * NB + bi, nblk, G * 2 * P, xbytes);
-        v16f acc[NB][NB];
+        for (int bi = 0; bi < NC; ++bi) rA[bi] = block_rsrc(frag, cb * NC + bi, nblk, G * 2 * P, xbytes);
+        v16f acc[NC][NR];
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi)
+        for (int bi = 0; bi < NC; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < NB; ++bj) acc[bi][bj] = v16f{};
+            for (int bj = 0; bj < NR; ++bj) acc[bi][bj] = v16f{};
         // K loop, two groups per step: group gg + 1 is in flight while group
         // gg is multiplied, and the loads of gg + 2 and gg + 3 follow
-        uint4 xa0[NB], xb0[NB], xa1[NB], xb1[NB];
-        load_group<NB>(rA, rB, voff, xa0, xb0);
-        load_group<NB>(rA, rB, voff + gbytes, xa1, xb1);
+        uint4 xa0[NC], xb0[NR], xa1[NC], xb1[NR];
+        load_group<NR, NC>(rA, rB, voff, xa0, xb0);
+        load_group<NR, NC>(rA, rB, voff + gbytes, xa1, xb1);
         // (G >= 1: written as a do-while so that no zero-trip path keeps a
         // second copy of the zero accumulators alive across the loop)
         uint32_t gg = 0;
         do {
-            mult_group<NB>(xa0, xb0, acc);
-            load_group<NB>(rA, rB, voff + (gg + 2) * gbytes, xa0, xb0);
-            if (gg + 1 < G) mult_group<NB>(xa1, xb1, acc);
-            load_group<NB>(rA, rB, voff + (gg + 3) * gbytes, xa1, xb1);
+            mult_group<NR, NC>(xa0, xb0, acc);
+            load_group<NR, NC>(rA, rB, voff + (gg + 2) * gbytes, xa0, xb0);
+            if (gg + 1 < G) mult_group<NR, NC>(xa1, xb1, acc);
+            load_group<NR, NC>(rA, rB, voff + (gg + 3) * gbytes, xa1, xb1);
             gg += 2;
         } while (gg < G);
         wave_sync();
-        // selection: NB x NB rounds of 16 candidates, one per accumulator block
+        // selection: NR x NC rounds of 16 candidates, one per accumulator block
         SelCtx cx;
         cx.k = a.k;
         cx.lane = lane;
         cx.lr = lr;
         cx.hh = hh;
-        cx.ncol = s - cb * TR < TR ? s - cb * TR : TR;
-        cx.rowpos = rb * TR + lr - cb * TR;  // column of the lane's row member in block bj = 0
-        Rounds<NB, 0>::run(acc, Lr, act, cx, L);
+        cx.ncol = s - cb * TRC < TRC ? s - cb * TRC : TRC;
+        cx.rowpos = rb * TRR + lr - cb * TRC;  // column of the lane's row member in block bj = 0
+        if constexpr (NR == 2) {
+            own_rows<NC>(acc);
+            OwnRounds<NC, 0>::run(acc, hh ? Lr[NR - 1] : Lr[0], hh ? act[NR - 1] : act[0], cx, L);
+        } else {
+            Rounds<NR, NC, 0>::run(acc, Lr, act, cx, L);
+        }
     }
     // The rows' entries, best first, by rank: the lane of half bj % 2 drains
-    // row 32 * bj + lr (for NB = 1 the lower lanes drain the one row).
+    // row 32 * bj + lr (for NR = 1 the lower lanes drain the one row).
     const uint32_t slot0 = ng > 1 ? sc.sbase[c] + rb * ng : 0u;
-    const uint32_t bj0 = NB > 1 ? hh : 0u, bstep = NB > 1 ? 2u : 1u;
-    const uint32_t bjn = NB > 1 || hh == 0 ? NB : 0u;
+    const uint32_t bj0 = NR > 1 ? hh : 0u, bstep = NR > 1 ? 2u : 1u;
+    const uint32_t bjn = NR > 1 || hh == 0 ? NR : 0u;
 #pragma unroll 1
     for (uint32_t bj = bj0; bj < bjn; bj += bstep) {
-        const uint32_t R = 32 * bj + lr, p = rb * TR + R;
+        const uint32_t R = 32 * bj + lr, p = rb * TRR + R;
         if (p >= s) continue;
         const uint32_t u = a.members[cv.o + p], Lu = ulen[u];
         const uint32_t cnt = L.hcnt[R];
@@ -930,7 +1055,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
         uint32_t rk[kMaxK];
 #pragma unroll
         for (uint32_t i = 0; i < kMaxK; ++i) {
-            ent[i] = i < cnt ? L.hk[i * kTR + R] : 0ull;
+            ent[i] = i < cnt ? L.hk[i * kRows + R] : 0ull;
             rk[i] = 0;
         }
 #pragma unroll
@@ -952,7 +1077,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
                 a.part_I[base + q] = 0;
             }
         } else {
-            uint64_t *out = sc.keys + ((size_t)(slot0 + g) * kTR + R) * kMaxK;
+            uint64_t *out = sc.keys + ((size_t)(slot0 + g) * kRows + R) * kMaxK;
 #pragma unroll
             for (uint32_t i = 0; i < kMaxK; ++i)
                 if (i < cnt) out[rk[i]] = ent[i];
@@ -970,16 +1095,16 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
     __threadfence();
 #pragma unroll 1
     for (uint32_t bj = bj0; bj < bjn; bj += bstep) {
-        const uint32_t R = 32 * bj + lr, p = rb * TR + R;
+        const uint32_t R = 32 * bj + lr, p = rb * TRR + R;
         if (p >= s) continue;
         const uint32_t u = a.members[cv.o + p], Lu = ulen[u];
-        const uint64_t *in = sc.keys + ((size_t)slot0 * kTR + R) * kMaxK;
+        const uint64_t *in = sc.keys + ((size_t)slot0 * kRows + R) * kMaxK;
         uint32_t ptr[kMaxGroups];
         uint64_t head[kMaxGroups];
 #pragma unroll
         for (uint32_t q = 0; q < kMaxGroups; ++q) {
             ptr[q] = 0;
-            head[q] = q < ng ? in[(size_t)q * kTR * kMaxK] : 0;
+            head[q] = q < ng ? in[(size_t)q * kRows * kMaxK] : 0;
         }
         const size_t base = ((size_t)u * a.t + cv.j) * a.k;
         for (uint32_t r = 0; r < a.k; ++r) {
@@ -993,7 +1118,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
                 if (q == best) {
                     v = head[q];
                     ++ptr[q];
-                    head[q] = (v != 0 && ptr[q] < a.k) ? in[(size_t)q * kTR * kMaxK + ptr[q]] : 0;
+                    head[q] = (v != 0 && ptr[q] < a.k) ? in[(size_t)q * kRows * kMaxK + ptr[q]] : 0;
                 }
             if (v == 0) {
                 a.part_id[base + r] = kPad;
@@ -1010,28 +1135,34 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
 C2_DEV void mfma_dispatch(const KnnArgs &a, const StoreView &sv, const uint32_t *ulen,
                           const MfmaScratch &sc, uint64_t code, WaveLds &L) {
     switch ((uint32_t)code >> 6 & 3u) {
-    case 0: mfma_item<1>(a, sv, ulen, sc, code, L); break;
-    case 1: mfma_item<2>(a, sv, ulen, sc, code, L); break;
-    default: mfma_item<4>(a, sv, ulen, sc, code, L); break;
+    case 0: mfma_item<1, 1>(a, sv, ulen, sc, code, L); break;
+    case 1: mfma_item<2, 2>(a, sv, ulen, sc, code, L); break;
+    default: mfma_item<2, 4>(a, sv, ulen, sc, code, L); break;
     }
 }
 
-// One wave per block; each wave holds up to 16 x 16 accumulator values per
-// lane, so one wave runs per SIMD (512 registers).  Plain form: block b takes
-// items[b]; batched form: persistent waves take items from a device cursor.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// Four waves per block, each with its own work item and LDS; two waves per
+// SIMD (each up to 8 x 16 accumulator values per lane in 256 registers), so
+// that one wave's selection runs beside the other's matrix products.  The
+// waves of a block take consecutive items, which the plan orders so that
+// they share their column tiles (the same column group of consecutive row
+// blocks), read at about the same time through the CU's caches.  Plain form:
+// wave w of block b takes items[4b + w]; batched form: persistent waves take
+// items from a device cursor.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_knn_mfma(KnnArgs a, StoreView sv, const uint32_t *ulen, MfmaScratch sc,
                 const uint64_t *items, const uint32_t *n_items, uint32_t *cursor) {
-    __shared__ WaveLds L;
+    __shared__ WaveLds Ls[4];
+    WaveLds &L = Ls[threadIdx.x >> 6];
     const uint32_t total = *n_items;
-    // the next item: the block's own (plain form) or the cursor's (batched);
+    // the next item: the wave's own (plain form) or the cursor's (batched);
     // wave-uniform, so the item and everything derived from it live in SGPRs
     auto next = [&]() -> uint32_t {
         uint32_t i = 0;
-        if (threadIdx.x == 0) i = atomicAdd(cursor, 1u);
+        if ((threadIdx.x & 63) == 0) i = atomicAdd(cursor, 1u);
         return __builtin_amdgcn_readfirstlane(__shfl(i, 0));
     };
-    uint32_t i = cursor ? next() : blockIdx.x;
+    uint32_t i = cursor ? next() : __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     while (i < total) {
         mfma_dispatch(a, sv, ulen, sc, items[i], L);
         if (!cursor) break;
@@ -1047,11 +1178,12 @@ C2_DEV uint32_t tile_code(uint32_t s, uint32_t t32, uint32_t t64) {
     return s <= t32 ? 0u : s <= t64 ? 1u : 2u;
 }
 
-// Column groups of an MFMA cluster of s members with tiles of TR rows.  Only
-// 128-row tiles are split (their scratch slots number fewer than s / 16).
-C2_DEV uint32_t mfma_groups(uint32_t s, uint32_t TR, uint32_t group_tiles) {
-    if (TR < kTR) return 1;
-    const uint32_t tiles = (s + TR - 1) / TR;
+// Column groups of an MFMA cluster of s members in tile shape tc.  Only the
+// largest shape's row blocks are split (their scratch slots then number at
+// most (s/64 + 1) * 4 < s / 8).
+C2_DEV uint32_t mfma_groups(uint32_t s, uint32_t tc, uint32_t group_tiles) {
+    if (tc < 2) return 1;
+    const uint32_t tiles = (s + kCols - 1) / kCols;
     if (tiles <= group_tiles) return 1;
     const uint32_t ng = (tiles + group_tiles - 1) / group_tiles;
     return ng < kMaxGroups ? ng : kMaxGroups;
@@ -1076,9 +1208,9 @@ __global__ __launch_bounds__(256) void k_plan_count(KnnArgs a, PlanOpts po, cons
     uint64_t v = 0;
     uint32_t sl = 0;
     if (cv.s >= mfma_min && cv.s >= 2) {
-        const uint32_t TR = 32u << tile_code(cv.s, po.t32, po.t64);
-        const uint32_t ng = mfma_groups(cv.s, TR, po.group_tiles);
-        v = (uint64_t)((cv.s + TR - 1) / TR) * ng;
+        const uint32_t tc = tile_code(cv.s, po.t32, po.t64), TRR = shape_rows(tc);
+        const uint32_t ng = mfma_groups(cv.s, tc, po.group_tiles);
+        v = (uint64_t)((cv.s + TRR - 1) / TRR) * ng;
         sl = ng > 1 ? (uint32_t)v : 0;
     } else if (cv.s >= 2) {
         v = (uint64_t)((cv.s + kRowBlock - 1) / kRowBlock) << 32;
@@ -1116,11 +1248,11 @@ __global__ __launch_bounds__(256) void k_plan_fill(KnnArgs a, PlanOpts po, const
     const uint32_t bb = (uint32_t)(o0 >> 32), nbm = (uint32_t)(o1 >> 32) - bb;
     if (nm) {
         const uint32_t s = a.cl_off[q + 1] - a.cl_off[q];
-        const uint32_t tc = tile_code(s, po.t32, po.t64), TR = 32u << tc;
-        const uint32_t ng = mfma_groups(s, TR, po.group_tiles), nrb = nm / ng;
+        const uint32_t tc = tile_code(s, po.t32, po.t64);
+        const uint32_t ng = mfma_groups(s, tc, po.group_tiles), nrb = nm / ng;
         sbase[q] = slot_off[q];
         for (uint32_t r = 0; r < nrb; ++r) {
-            for (uint32_t g = 0; g < ng; ++g) items_m[bm + r * ng + g] = mfma_item_code(q, r, tc, g, ng);
+            for (uint32_t g = 0; g < ng; ++g) items_m[bm + g * nrb + r] = mfma_item_code(q, r, tc, g, ng);
             if (ng > 1) rb_done[slot_off[q] + r * ng] = 0;
         }
     }
@@ -1151,12 +1283,13 @@ __global__ __launch_bounds__(256) void k_plan_classes(KnnArgs a, PlanOpts po, co
     if (live) {
         const ClusterView cv = view(a, c);
         if (cv.s >= mfma_min && cv.s >= 2) {
-            const uint32_t tc = tile_code(cv.s, po.t32, po.t64), TR = 32u << tc;
-            const uint32_t ng = mfma_groups(cv.s, TR, po.group_tiles);
-            const uint32_t tiles = (cv.s + TR - 1) / TR, per = (tiles + ng - 1) / ng;
-            const uint32_t nit = ((cv.s + TR - 1) / TR) * ng;
-            // work of one item in 32 x 32 blocks: per * (TR / 32)^2, log scale
-            const uint32_t work = per << (2 * tc);
+            const uint32_t tc = tile_code(cv.s, po.t32, po.t64);
+            const uint32_t TRR = shape_rows(tc), TRC = shape_cols(tc);
+            const uint32_t ng = mfma_groups(cv.s, tc, po.group_tiles);
+            const uint32_t tiles = (cv.s + TRC - 1) / TRC, per = (tiles + ng - 1) / ng;
+            const uint32_t nit = ((cv.s + TRR - 1) / TRR) * ng;
+            // work of one item in 32 x 32 blocks: per * (TRR / 32) * (TRC / 32), log scale
+            const uint32_t work = per * (TRR / 32) * (TRC / 32);
             const uint32_t lv = 4 * bit_width_dev(work);
             cls = kCostClasses - 1 - (lv < kCostClasses - 1 ? lv : kCostClasses - 1);
             ctr = cls;
@@ -1214,11 +1347,11 @@ __global__ __launch_bounds__(256) void k_plan_items(KnnArgs a, PlanOpts po, cons
     const uint32_t cls = ccls[c];
     if (cls < kCostClasses) {
         const uint32_t s = a.cl_off[c + 1] - a.cl_off[c];
-        const uint32_t tc = tile_code(s, po.t32, po.t64), TR = 32u << tc;
-        const uint32_t ng = mfma_groups(s, TR, po.group_tiles), nrb = (s + TR - 1) / TR;
+        const uint32_t tc = tile_code(s, po.t32, po.t64), TRR = shape_rows(tc);
+        const uint32_t ng = mfma_groups(s, tc, po.group_tiles), nrb = (s + TRR - 1) / TRR;
         const uint32_t b0 = cbase[cls] + cpos[c];
         for (uint32_t r = 0; r < nrb; ++r) {
-            for (uint32_t g = 0; g < ng; ++g) items_m[b0 + r * ng + g] = mfma_item_code(c, r, tc, g, ng);
+            for (uint32_t g = 0; g < ng; ++g) items_m[b0 + g * nrb + r] = mfma_item_code(c, r, tc, g, ng);
             if (ng > 1) rb_done[sbase[c] + r * ng] = 0;
         }
     } else if (cls == kCostClasses) {
@@ -1278,9 +1411,9 @@ hipError_t launch_user_bits(const int64_t *indptr, const uint32_t *indices, uint
 // --------------------------------------------------------------- host side
 
 // Scratch slots of split row blocks: a cluster is split only when it spans
-// more than one column tile of 128 (s > 128, with 128-row tiles), and then
-// takes ceil(s/128) * ng <= (s/128 + 1) * 4 < s/16 slots.
-size_t knn_max_slots(uint32_t NE) { return (size_t)NE / 16 + 8; }
+// more than one column tile of 128 (s > 128, 64-row blocks), and then takes
+// ceil(s/64) * ng <= (s/64 + 1) * 4 < s/8 slots.
+size_t knn_max_slots(uint32_t NE) { return (size_t)NE / 8 + 8; }
 
 // Map slots: clusters of more than kBigS members.
 static size_t knn_max_maps(uint32_t NE) { return (size_t)NE / (kBigS + 1) + 1; }
@@ -1300,7 +1433,7 @@ size_t knn_ws_fixed(uint32_t n, uint32_t NE, uint32_t m, KnnWs *w) {
     x.sbase = take(4 * (size_t)NE);
     const size_t nslot = knn_max_slots(NE);
     x.rb_done = take(4 * nslot);
-    x.skeys = take(8 * nslot * kTR * kMaxK);
+    x.skeys = take(8 * nslot * kRows * kMaxK);
     x.items_b = take(8 * (size_t)NE);
     x.ctmp = take(8 * scan_tmp_elems(NE + 1));
     x.htmp = take(4 * scan_tmp_elems(NE + 1));
@@ -1417,8 +1550,8 @@ static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts
     // the events bracket the MFMA kernel, which carries the large clusters
     if (o.ev_begin && (e = hipEventRecord(o.ev_begin, s)) != hipSuccess) return e;
     if (grid_m)
-        hipLaunchKernelGGL(k_knn_mfma, dim3(grid_m), dim3(64), 0, s, a, sv, w.rlen, sc, w.items_m,
-                           w.ctr, batched ? w.ctr + 2 : nullptr);
+        hipLaunchKernelGGL(k_knn_mfma, dim3((uint32_t)div_up(grid_m, 4)), dim3(256), 0, s, a, sv,
+                           w.rlen, sc, w.items_m, w.ctr, batched ? w.ctr + 2 : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (o.ev_end && (e = hipEventRecord(o.ev_end, s)) != hipSuccess) return e;
     if (grid_b)
