@@ -203,7 +203,7 @@ def time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf,
         dtab = c2.tables_to_device(synth.hash_tables(t, w.hash_seed))
         for cap in caps:
             p = c2.params(t, w.b, cap, w.k)
-            ws = c2.workspace(dP, p, c2.OP_BUILD)
+            ws = c2.build_workspace(dP, dtab, p)
             out = c2.build(dP, dtab, p, c2.FORM_PLAIN, ws=ws)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -482,7 +482,7 @@ def main():
 
     # batched (eager) and plain forms, same arithmetic
     def timed(form):
-        ws = c2.workspace(dP, p, c2.OP_BUILD)
+        ws = torch.empty_like(g.ws)
         tu = c2.tuning(**tuned)
         out = None
         for _ in range(args.warmup):
@@ -499,7 +499,7 @@ def main():
     # dominant kernel: HIP events that the library records on its stream right
     # before and after the pairwise local-KNN kernel, over K batched builds
     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    ws = c2.workspace(dP, p, c2.OP_BUILD)
+    ws = torch.empty_like(g.ws)
     tu = c2.tuning(events=ev, **tuned)
     out = None
     knn = []

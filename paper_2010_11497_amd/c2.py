@@ -205,6 +205,18 @@ def workspace(P: DeviceProfiles, p: Optional[Params], op: int) -> torch.Tensor:
 C2_E_WORKSPACE = -3
 
 
+def build_workspace(P: DeviceProfiles, tab: torch.Tensor, p: Params,
+                    tune: Optional[Tuning] = None) -> torch.Tensor:
+    """A c2_build workspace whose store holds this input's dictionary rows:
+    the default size, grown by what one plain build reports as missing."""
+    out = tuple(_u32((P.n, p.k), P.device) for _ in range(3))
+    return _with_ws(lambda w: load().c2_build(ctypes.byref(P.c), _ptr(tab), ctypes.byref(p),
+                                              FORM_PLAIN, ctypes.byref(tune) if tune else None,
+                                              _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(w),
+                                              w.numel(), _stream()),
+                    None, lambda: workspace(P, p, OP_BUILD))
+
+
 def store_need_bytes(ws: torch.Tensor) -> int:
     """Bytes of dictionary-row store the last local KNN on this workspace
     needed (the u64 at bytes 8..15 of its header, times 4)."""
