@@ -93,3 +93,85 @@ def keys(h, W2, b2, t, b):
         top2 = np.partition(zj, b - 2, axis=1)[:, b - 2:]
         gap[j] = top2[:, 1] - top2[:, 0]
     return key, gap, z
+
+
+# ------------------------------------------------------------------ training
+#
+# The training objective of the assigner (the library's own; the paper has
+# none).  A batch is R = 2B profile rows: rows 0..B-1 are users u_i, rows
+# B..2B-1 their exact neighbours v_i, and w_i = v_{i-1 mod B} serves as u_i's
+# non-neighbour.  With p_r = softmax over head j of z_r (the logits of row r,
+# the forward above with e and h rounded to bf16 at the same points):
+#
+#   s_ij  = <p_{u_i,j}, p_{v_i,j}>,   n_ij = <p_{u_i,j}, p_{w_i,j}>
+#   q_j   = mean_r p_{r,j}
+#   L = - mean_{i,j} log max(s_ij, 1e-12)
+#       - w_neg mean_{i,j} log(1 - clip(n_ij, 0, 1 - 1e-6))
+#       + w_bal mean_j sum_c q_jc log(q_jc b + 1e-12)
+#       + w_ent mean_{r,j} H(p_{r,j})
+#
+# The gradients are those of L in float64, with the two bf16 roundings taken
+# as the identity (their derivative is zero almost everywhere), and with the
+# ReLU's and the clips' derivatives 1 on their closed active ranges.
+
+def train_forward_backward(indptr, indices, m, rows, E, W1, b1, W2, b2, t, b, w_neg=1.0,
+                           w_bal=1.0, w_ent=1.0, rounding=True):
+    """Loss parts and gradients of one training step from the definition above.
+    E, W1, W2 hold the (bf16) values the forward multiplies with; b1, b2 the
+    biases.  Returns (loss dict, grads dict with dE, dW1, db1, dW2, db2, and
+    the intermediates dict: e, pre, h, z, p, dz, dpre, de).  rounding=False
+    drops the two bf16 roundings (for finite-difference checks)."""
+    rnd = bf16_round if rounding else (lambda x: np.asarray(x, dtype=np.float64))
+    rows = np.asarray(rows, dtype=np.int64)
+    R = len(rows)
+    B = R // 2
+    e = rnd(embag(indptr, indices, E, rows))
+    pre = e @ W1.T + b1
+    h = rnd(np.maximum(pre, 0.0))
+    z = (h @ W2.T + b2).reshape(R, t, b)
+    zmax = z.max(axis=-1, keepdims=True)
+    ex = np.exp(z - zmax)
+    S = ex.sum(axis=-1, keepdims=True)
+    p = ex / S
+    logp = z - zmax - np.log(S)
+    H = -(p * logp).sum(axis=-1)                          # [R, t]
+    pu, pv = p[:B], p[B:]
+    pw = np.roll(pv, 1, axis=0)                           # row i: v_{i-1}
+    s = (pu * pv).sum(axis=-1)
+    sn = (pu * pw).sum(axis=-1)                           # [B, t]
+    sc = np.maximum(s, 1e-12)
+    snc = np.clip(sn, 0.0, 1.0 - 1e-6)
+    q = p.mean(axis=0)                                    # [t, b]
+    loss = {"pos": float(-np.log(sc).mean()),
+            "neg": float(-w_neg * np.log1p(-snc).mean()),
+            "bal": float(w_bal * (q * np.log(q * b + 1e-12)).sum(axis=-1).mean()),
+            "ent": float(w_ent * H.mean())}
+    loss["total"] = loss["pos"] + loss["neg"] + loss["bal"] + loss["ent"]
+    # dL/dp
+    ds = np.where(s >= 1e-12, -1.0 / (sc * B * t), 0.0)
+    dsn = np.where((sn >= 0.0) & (sn <= 1.0 - 1e-6), w_neg / ((1.0 - snc) * B * t), 0.0)
+    g = np.zeros_like(p)
+    g[:B] += ds[..., None] * pv + dsn[..., None] * pw
+    g[B:] += ds[..., None] * pu + np.roll(dsn[..., None] * pu, -1, axis=0)
+    g += (w_bal / t * (np.log(q * b + 1e-12) + q * b / (q * b + 1e-12)))[None] / R
+    # through the softmax; the entropy's own derivative is -p (log p + H)
+    dz = p * (g - (p * g).sum(axis=-1, keepdims=True))
+    dz -= w_ent / (R * t) * p * (logp + H[..., None])
+    dz = dz.reshape(R, t * b)
+    dpre = (dz @ W2) * (pre > 0.0)
+    de = dpre @ W1
+    grads = {"dW2": dz.T @ h, "db2": dz.sum(axis=0), "dW1": dpre.T @ e, "db1": dpre.sum(axis=0),
+             "dE": embag_backward(indptr, indices, m, de, rows)}
+    inter = {"e": e, "pre": pre, "h": h, "z": z.reshape(R, t * b), "p": p, "dz": dz,
+             "dpre": dpre, "de": de}
+    return loss, grads, inter
+
+
+def adam_step(param, grad, m1, m2, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, Algorithm 1) in float64, step counted
+    from 1: returns (param, m1, m2)."""
+    m1 = beta1 * m1 + (1.0 - beta1) * grad
+    m2 = beta2 * m2 + (1.0 - beta2) * grad * grad
+    mhat = m1 / (1.0 - beta1 ** step)
+    vhat = m2 / (1.0 - beta2 ** step)
+    return param - lr * mhat / (np.sqrt(vhat) + eps), m1, m2

@@ -82,3 +82,81 @@ def test_weights_generator_is_seeded_bf16(A):
     v = A.from_bf16_bits(W2)
     assert np.array_equal(A.bf16_round(v), v)
     assert np.array_equal(E, synth.assigner_weights(100, 2, 64, 7)[0])
+
+
+def _tiny_training_case(seed, R=6, dim=3, hidden=5, t=2, b=4, m=7):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = synth.random_profiles(seed, 9, m, 1, 4, 0.0)
+    rows = rng.integers(0, P.n, size=R)
+    par = {"E": rng.standard_normal((m, dim)), "W1": rng.standard_normal((hidden, dim)),
+           "b1": rng.standard_normal(hidden) * 0.3, "W2": rng.standard_normal((t * b, hidden)),
+           "b2": rng.standard_normal(t * b) * 0.3}
+    return P, rows, par, t, b, m
+
+
+def _loss(A, P, rows, par, t, b, m, hyper):
+    return A.train_forward_backward(P.indptr, P.indices, m, rows, par["E"], par["W1"], par["b1"],
+                                    par["W2"], par["b2"], t, b, rounding=False, **hyper)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+@pytest.mark.parametrize("hyper", [dict(w_neg=1.0, w_bal=1.0, w_ent=1.0),
+                                   dict(w_neg=0.7, w_bal=3.0, w_ent=0.2)])
+def test_training_gradients_match_finite_differences(A, seed, hyper):
+    """Every gradient of the training objective (E, W1, b1, W2, b2) against
+    central differences of the loss in float64, on a tiny batch of 3 pairs with
+    small layers and the roundings switched off.  A wrong pairing of the
+    non-neighbour (the roll direction), a dropped or mis-signed term of the
+    loss or of the softmax/entropy derivative, or a transposed product fails
+    here."""
+    P, rows, par, t, b, m = _tiny_training_case(seed)
+    loss, grads, inter = _loss(A, P, rows, par, t, b, m, hyper)
+    assert np.abs(inter["pre"]).min() > 1e-3                 # away from the ReLU kink
+    d = 1e-6
+    for name in ("E", "W1", "b1", "W2", "b2"):
+        x = par[name]
+        fd = np.zeros_like(x)
+        for idx in np.ndindex(x.shape):
+            old = x[idx]
+            x[idx] = old + d
+            lp = _loss(A, P, rows, par, t, b, m, hyper)[0]["total"]
+            x[idx] = old - d
+            lm = _loss(A, P, rows, par, t, b, m, hyper)[0]["total"]
+            x[idx] = old
+            fd[idx] = (lp - lm) / (2 * d)
+        got = grads["d" + name]
+        assert np.allclose(got, fd, rtol=1e-5, atol=1e-8), name
+
+
+def test_training_loss_closed_form_uniform(A):
+    """All-zero output layer: every head is uniform (p = 1/b), so s = n = 1/b,
+    q = 1/b, and the four parts are log b, -w_neg log(1 - 1/b), w_bal
+    log(1 + 1e-12) (zero but for the logarithm's guard) and w_ent log b; the softmax's gradient sums to zero over each head."""
+    P, rows, par, t, b, m = _tiny_training_case(21, b=8)
+    par["W2"][:] = 0.0
+    par["b2"][:] = 0.0
+    hyper = dict(w_neg=0.5, w_bal=2.0, w_ent=0.25)
+    loss, grads, inter = _loss(A, P, rows, par, t, b, m, hyper)
+    assert loss["pos"] == pytest.approx(np.log(b), rel=1e-12)
+    assert loss["neg"] == pytest.approx(-0.5 * np.log(1 - 1 / b), rel=1e-12)
+    assert loss["bal"] == pytest.approx(2.0 * np.log1p(1e-12), rel=1e-6)    # the 1e-12 guard
+    assert loss["ent"] == pytest.approx(0.25 * np.log(b), rel=1e-12)
+    dz = inter["dz"].reshape(len(rows), t, b)
+    assert np.abs(dz.sum(axis=-1)).max() < 1e-15
+
+
+def test_adam_step_matches_torch(A):
+    """Three Adam updates against torch.optim.Adam in float64 (same betas,
+    eps and learning rate, bias correction from step 1)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.Generator(np.random.PCG64(31))
+    x0 = rng.standard_normal(40)
+    grads = [rng.standard_normal(40) for _ in range(3)]
+    p = torch.tensor(x0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    x, m1, m2 = x0.copy(), np.zeros(40), np.zeros(40)
+    for step, g in enumerate(grads, start=1):
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        x, m1, m2 = A.adam_step(x, g, m1, m2, step, 3e-3)
+        assert np.allclose(x, p.detach().numpy(), rtol=0, atol=1e-15)
