@@ -95,12 +95,12 @@ typedef struct c2_params {
 typedef struct c2_tuning {
     uint32_t mfma_min_rows;   /* clusters with at least this many members use the
                                  MFMA path, smaller ones the bitmap path (default 2) */
-    uint32_t persistent_wgs;  /* MFMA path, batched form: persistent waves (one per block;
-                                 default 1024, one per SIMD) */
+    uint32_t persistent_wgs;  /* MFMA path, batched form: persistent waves (four per
+                                 256-thread block; default 2048, two per SIMD) */
     uint32_t split_rounds;    /* split rounds enqueued by the batched form */
     uint32_t group_tiles;     /* MFMA path: a row block whose cluster spans more than this many
                                  column tiles is split into up to 4 work items over disjoint
-                                 column ranges (default 4) */
+                                 column ranges (default 16) */
     uint32_t cluster_path;    /* 0: automatic; 1: grid rounds (any size); 2: one workgroup per
                                  configuration with every split round in LDS (n <= 8192 and
                                  bit_width(b) <= 20; otherwise the grid rounds are used) */
@@ -108,7 +108,8 @@ typedef struct c2_tuning {
     void *ev_knn_end;         /* the stream right before / after the pairwise local-KNN kernel */
     uint32_t tile32_max;      /* MFMA path tile shape per cluster: clusters of at most this many */
     uint32_t tile64_max;      /* members take 32 x 32 tiles (default 32), of at most tile64_max
-                                 64 x 64 tiles (default 64), larger ones 128 x 128 tiles */
+                                 64 x 64 tiles (default 64), larger ones 64-row x 128-column
+                                 tiles */
 } c2_tuning;
 
 /* Workspace queries: which call the size is for. */
@@ -360,6 +361,48 @@ c2_status c2_embag(const c2_profiles *P, const uint32_t *rows, uint32_t nrows, c
  * grad[r] / |P_u|.  Atomic fp32 adds: the summation order is not fixed. */
 c2_status c2_embag_backward(const c2_profiles *P, const uint32_t *rows, uint32_t nrows,
                             const float *grad, float *dE, void *stream);
+
+/* One training step of the assigner: loss and gradients of a batch of
+ * nrows = 2B profile rows (rows, device u32 [nrows]): rows 0..B-1 are users
+ * u_i, rows B..2B-1 exact neighbours v_i of theirs, and v_{i-1 mod B} is u_i's
+ * non-neighbour.  With p the per-head softmax of the logits z (the forward
+ * above: e and h rounded to bf16, z = h W2^T + b2 in fp32), s_i = <p(u_i),
+ * p(v_i)>, n_i = <p(u_i), p(v_{i-1})>, q = the batch mean of p and H the
+ * entropy, averaged over heads and pairs or rows:
+ *   L = -mean log max(s, 1e-12) - w_neg mean log(1 - clip(n, 0, 1 - 1e-6))
+ *       + w_bal mean_j sum_c q log(q b + 1e-12) + w_ent mean H
+ * (the library's own objective; the paper has no learned assigner).
+ * Outputs (device, caller-owned): loss fp32 [5] = total, pair, non-neighbour,
+ * balance and entropy terms; dE fp32 [m][C2_ASSIGN_DIM] (overwritten),
+ * dW1 fp32 [C2_ASSIGN_HIDDEN][C2_ASSIGN_DIM], db1 fp32 [C2_ASSIGN_HIDDEN],
+ * dW2 fp32 [t*b][C2_ASSIGN_HIDDEN], db2 fp32 [t*b]: the gradients of L with
+ * respect to the weights the forward read (the bf16 copies), the roundings
+ * passing gradients unchanged.  The products run on bf16 MFMA with fp32
+ * sums; the logits' gradient is rounded to bf16 as their operand.  b: a
+ * multiple of 64; nrows even and >= 2.  ws: at least
+ * c2_assign_train_workspace_bytes(nrows, t, b) bytes (device).  Asynchronous,
+ * capturable (no host synchronisation, no memset). */
+typedef struct c2_train_opts {
+    float w_neg, w_bal, w_ent;
+} c2_train_opts;
+
+size_t c2_assign_train_workspace_bytes(uint32_t nrows, uint32_t t, uint32_t b);
+
+c2_status c2_assign_train_grad(const c2_profiles *P, const uint32_t *rows, uint32_t nrows,
+                               const uint16_t *E, const uint16_t *W1, const float *b1,
+                               const uint16_t *W2, const float *b2, uint32_t t, uint32_t b,
+                               const c2_train_opts *opts, float *loss, float *dE, float *dW1,
+                               float *db1, float *dW2, float *db2, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/* Adam (Kingma and Ba, Algorithm 1) on count fp32 parameters in place:
+ * m1 = beta1 m1 + (1 - beta1) g, m2 = beta2 m2 + (1 - beta2) g^2,
+ * param -= lr (m1 / (1 - beta1^step)) / (sqrt(m2 / (1 - beta2^step)) + eps),
+ * step counted from 1.  param_bf16 (may be NULL) receives the updated values
+ * rounded to bf16, the copy the next forward reads.  All device. */
+c2_status c2_adam_step(float *param, const float *grad, float *m1, float *m2, uint64_t count,
+                       float lr, float beta1, float beta2, float eps, uint32_t step,
+                       uint16_t *param_bf16, void *stream);
 
 /* HIP-graph form of c2_build (C2_FORM_BATCHED) on fixed buffers.  Create
  * runs one plain clustering synchronously to learn how many split rounds the

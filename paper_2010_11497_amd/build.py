@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libc2.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["k_scan_sort.hip", "k_hash.hip", "k_cluster.hip", "k_cluster_wg.hip", "k_knn.hip",
-           "k_merge.hip", "k_fingerprint.hip", "k_assign.hip", "k_hyrec.hip",
+           "k_merge.hip", "k_fingerprint.hip", "k_assign.hip", "k_train.hip", "k_hyrec.hip",
            "c2_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

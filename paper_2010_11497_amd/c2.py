@@ -32,7 +32,8 @@ SYMBOLS = ["c2_last_error", "c2_workspace_bytes", "c2_validate", "c2_hash_items"
            "c2_cluster", "c2_cluster_keys", "c2_check_complete", "c2_local_knn",
            "c2_local_knn_alg2", "c2_merge", "c2_build", "c2_build_noalloc",
            "c2_brute_force", "c2_fingerprint", "c2_assign_hidden", "c2_assign_keys",
-           "c2_embag", "c2_embag_backward", "c2_graph_create", "c2_graph_launch",
+           "c2_embag", "c2_embag_backward", "c2_assign_train_workspace_bytes",
+           "c2_assign_train_grad", "c2_adam_step", "c2_graph_create", "c2_graph_launch",
            "c2_graph_destroy"]
 ASSIGN_DIM, ASSIGN_HIDDEN = 64, 256
 
@@ -56,6 +57,10 @@ class Params(ctypes.Structure):
 class Hyrec(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_uint32), ("max_iter", ctypes.c_uint32),
                 ("delta", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("w_neg", ctypes.c_float), ("w_bal", ctypes.c_float), ("w_ent", ctypes.c_float)]
 
 
 class Tuning(ctypes.Structure):
@@ -101,11 +106,17 @@ def load(path: str = LIB_PATH):
     L.c2_assign_keys.argtypes = [P, u32, P, P, u32, u32, P, ctypes.c_float, P, P, P]
     L.c2_embag.argtypes = [PP, P, u32, P, P, P]
     L.c2_embag_backward.argtypes = [PP, P, u32, P, P, P]
+    L.c2_assign_train_workspace_bytes.argtypes = [u32, u32, u32]
+    L.c2_assign_train_workspace_bytes.restype = sz
+    L.c2_assign_train_grad.argtypes = [PP, P, u32, P, P, P, P, P, u32, u32,
+                                       ctypes.POINTER(TrainOpts), P, P, P, P, P, P, P, sz, P]
+    f32 = ctypes.c_float
+    L.c2_adam_step.argtypes = [P, P, P, P, u64, f32, f32, f32, f32, u32, P, P]
     L.c2_graph_create.argtypes = [PP, P, PA, PT, P, P, P, P, sz, P, ctypes.POINTER(P)]
     L.c2_graph_launch.argtypes = [P, P]
     L.c2_graph_destroy.argtypes = [P]
     for name in SYMBOLS:
-        if name not in ("c2_last_error", "c2_workspace_bytes"):
+        if name not in ("c2_last_error", "c2_workspace_bytes", "c2_assign_train_workspace_bytes"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -304,6 +315,19 @@ def local_knn(P: DeviceProfiles, members, cl_off, cl_cfg_off, p: Params, form=FO
     return out
 
 
+def local_knn_workspace(P: DeviceProfiles, members, cl_off, cl_cfg_off, p: Params,
+                        tune: Optional[Tuning] = None) -> torch.Tensor:
+    """A c2_local_knn workspace whose store holds this partition's dictionary
+    rows: the default size, grown by what one plain run reports as missing."""
+    out = (_u32((P.n, p.t, p.k), P.device), _u32((P.n, p.t, p.k), P.device))
+    return _with_ws(lambda w: load().c2_local_knn(ctypes.byref(P.c), _ptr(members), _ptr(cl_off),
+                                                  _ptr(cl_cfg_off), ctypes.byref(p), FORM_PLAIN,
+                                                  ctypes.byref(tune) if tune else None,
+                                                  _ptr(out[0]), _ptr(out[1]), _ptr(w), w.numel(),
+                                                  _stream()),
+                    None, lambda: workspace(P, p, OP_LOCAL_KNN))
+
+
 def local_knn_alg2(P: DeviceProfiles, members, cl_off, cl_cfg_off, p: Params, rho=5,
                    max_iter=30, delta=0.001, seed=0, tune: Optional[Tuning] = None, ws=None,
                    out=None):
@@ -422,6 +446,49 @@ def embag_backward(P: DeviceProfiles, grad: torch.Tensor, dE: torch.Tensor,
     _check(load().c2_embag_backward(ctypes.byref(P.c), _ptr(rows), int(grad.shape[0]),
                                     _ptr(grad), _ptr(dE), _stream()))
     return dE
+
+
+def train_workspace(nrows: int, t: int, b: int, device="cuda") -> torch.Tensor:
+    nb = load().c2_assign_train_workspace_bytes(int(nrows), int(t), int(b))
+    if nb == 0:
+        raise C2Error(C2_E_ARG, load().c2_last_error().decode())
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def assign_train_grad(P: DeviceProfiles, rows: torch.Tensor, E, W1, b1, W2, b2, t: int, b: int,
+                      w_neg=1.0, w_bal=1.0, w_ent=1.0, ws=None, out=None):
+    """One training step's loss parts (fp32 [5]: total, pair, non-neighbour,
+    balance, entropy) and gradients (dE, dW1, db1, dW2, db2, fp32) for the
+    batch rows (int32 view of u32 [2B]: users, then their neighbours).  E, W1,
+    W2: the bf16 weights the forward reads; b1, b2 fp32."""
+    R = int(rows.numel())
+    dev = P.device
+    if out is None:
+        out = (torch.empty(5, dtype=torch.float32, device=dev),
+               torch.empty((P.m, ASSIGN_DIM), dtype=torch.float32, device=dev),
+               torch.empty((ASSIGN_HIDDEN, ASSIGN_DIM), dtype=torch.float32, device=dev),
+               torch.empty(ASSIGN_HIDDEN, dtype=torch.float32, device=dev),
+               torch.empty((t * b, ASSIGN_HIDDEN), dtype=torch.float32, device=dev),
+               torch.empty(t * b, dtype=torch.float32, device=dev))
+    ws = train_workspace(R, t, b, dev) if ws is None else ws
+    o = TrainOpts(float(w_neg), float(w_bal), float(w_ent))
+    loss, dE, dW1, db1, dW2, db2 = out
+    _check(load().c2_assign_train_grad(ctypes.byref(P.c), _ptr(rows), R, _ptr(E), _ptr(W1),
+                                       _ptr(b1), _ptr(W2), _ptr(b2), int(t), int(b),
+                                       ctypes.byref(o), _ptr(loss), _ptr(dE), _ptr(dW1),
+                                       _ptr(db1), _ptr(dW2), _ptr(db2), _ptr(ws), ws.numel(),
+                                       _stream()))
+    return out
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor,
+              lr: float, step: int, beta1=0.9, beta2=0.999, eps=1e-8,
+              param_bf16: Optional[torch.Tensor] = None) -> None:
+    """In-place Adam update of fp32 param (step counted from 1); param_bf16
+    receives the updated values rounded to bf16."""
+    _check(load().c2_adam_step(_ptr(param), _ptr(grad), _ptr(m1), _ptr(m2), param.numel(),
+                               float(lr), float(beta1), float(beta2), float(eps), int(step),
+                               _ptr(param_bf16), _stream()))
 
 
 def build_from_buckets(P: DeviceProfiles, bucket: torch.Tensor, p: Params,

@@ -1,5 +1,6 @@
 // C ABI of libc2.so: argument checks, workspace carving and the host-side
 // orchestration of the kernels.  Declarations and contracts: include/c2.h.
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -166,7 +167,6 @@ KnnPtrs knn_ptrs(char *base, size_t bytes, const KnnWs &w, uint32_t *status) {
     k.slots = u32(w.slots);
     k.sbase = u32(w.sbase);
     k.rb_done = u32(w.rb_done);
-    k.skeys = u64(w.skeys);
     k.htmp = u32(w.htmp);
     k.ctmp = u64(w.ctmp);
     k.ctr = u32(w.ctr);
@@ -402,9 +402,11 @@ size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params 
     case C2_OP_BRUTE_FORCE: {
         one.k = p ? p->k : 1;
         if (check_sizes(n, m, nnz, &one, true) != C2_OK) return 0;
-        // one cluster: its rows over the whole item universe at most
+        // one cluster: its rows over the whole item universe at most, after
+        // the scratch of its row blocks (up to 4 column groups each)
         return brute_head(n, one.k) + knn_ws_fixed(n, n, m, nullptr) +
-               (size_t)4 * (((size_t)n + 31) / 32 * 32) * full_row_words(m) + 4096;
+               (size_t)4 * (((size_t)n + 31) / 32 * 32) * full_row_words(m) +
+               (((size_t)n + 63) / 64) * 4 * 64 * one.k * 8 + 4096;
     }
     case C2_OP_LOCAL_KNN_ALG2:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
@@ -522,6 +524,51 @@ c2_status c2_embag_backward(const c2_profiles *P, const uint32_t *rows, uint32_t
     C2_TRY(launch_embag_backward(P->indptr, P->indices, P->nnz, P->n, P->m, rows, nrows, grad, dE,
                                  (hipStream_t)stream),
            "embedding bag backward");
+    return C2_OK;
+}
+
+size_t c2_assign_train_workspace_bytes(uint32_t nrows, uint32_t t, uint32_t b) {
+    if (nrows < 2 || nrows % 2 || t < 1 || t > 64 || b < 64 || b % 64 || b > (1u << 23)) {
+        fail(C2_E_ARG, "training batch: nrows = %u (even, >= 2), t = %u, b = %u", nrows, t, b);
+        return 0;
+    }
+    return train_ws_bytes(nrows, t, b);
+}
+
+c2_status c2_assign_train_grad(const c2_profiles *P, const uint32_t *rows, uint32_t nrows,
+                               const uint16_t *E, const uint16_t *W1, const float *b1,
+                               const uint16_t *W2, const float *b2, uint32_t t, uint32_t b,
+                               const c2_train_opts *opts, float *loss, float *dE, float *dW1,
+                               float *db1, float *dW2, float *db2, void *ws, size_t ws_bytes,
+                               void *stream) {
+    c2_status st;
+    if ((st = check_profiles(P)) != C2_OK) return st;
+    if ((st = check_sizes(P->n, P->m, P->nnz, nullptr, false)) != C2_OK) return st;
+    if (!rows || !E || !W1 || !b1 || !W2 || !b2 || !opts || !loss || !dE || !dW1 || !db1 ||
+        !dW2 || !db2)
+        return fail(C2_E_ARG, "NULL pointer");
+    const size_t need = c2_assign_train_workspace_bytes(nrows, t, b);
+    if (need == 0) return C2_E_ARG;
+    if ((uint64_t)nrows * t * b >= (1ull << 40)) return fail(C2_E_UNSUPPORTED, "batch too large");
+    if ((st = check_ws(ws, ws_bytes, need)) != C2_OK) return st;
+    C2_TRY(launch_train_grad(P->indptr, P->indices, P->nnz, P->n, P->m, rows, nrows, E, W1, b1,
+                             W2, b2, t, b, opts->w_neg, opts->w_bal, opts->w_ent, loss, dE, dW1,
+                             db1, dW2, db2, ws, (hipStream_t)stream),
+           "assign training step");
+    return C2_OK;
+}
+
+c2_status c2_adam_step(float *param, const float *grad, float *m1, float *m2, uint64_t count,
+                       float lr, float beta1, float beta2, float eps, uint32_t step,
+                       uint16_t *param_bf16, void *stream) {
+    if (!param || !grad || !m1 || !m2) return fail(C2_E_ARG, "NULL pointer");
+    if (step < 1) return fail(C2_E_ARG, "step counts from 1");
+    if (count == 0) return C2_OK;
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)step));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
+    C2_TRY(launch_adam(param, grad, m1, m2, count, lr, beta1, beta2, eps, bc1, bc2, param_bf16,
+                       (hipStream_t)stream),
+           "adam");
     return C2_OK;
 }
 

@@ -42,6 +42,19 @@ hipError_t launch_embag_backward(const int64_t *indptr, const uint32_t *indices,
                                  uint32_t n, uint32_t m, const uint32_t *rows, uint32_t nrows,
                                  const float *grad, float *dE, hipStream_t s);
 
+// ---- training of the assigner
+size_t train_ws_bytes(uint32_t nrows, uint32_t t, uint32_t b);
+hipError_t launch_train_grad(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                             uint32_t n, uint32_t m, const uint32_t *rows, uint32_t R,
+                             const uint16_t *E, const uint16_t *W1, const float *b1,
+                             const uint16_t *W2, const float *b2, uint32_t t, uint32_t b,
+                             float w_neg, float w_bal, float w_ent, float *loss, float *dE,
+                             float *dW1, float *db1, float *dW2, float *db2, void *ws,
+                             hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m1, float *m2, size_t n, float lr,
+                       float beta1, float beta2, float eps, float bc1, float bc2, uint16_t *p16,
+                       hipStream_t s);
+
 // ---- clustering
 struct ClusterDims {
     size_t NE;  // t*n slots
@@ -99,14 +112,13 @@ struct KnnArgs {
     uint32_t *part_id, *part_I;
 };
 struct KnnWs {  // byte offsets; the store takes the rest of the region
-    size_t rlen, cnt, items_m, items_b, slots, sbase, rb_done, skeys, htmp, ctmp, ctr, bmax, pc,
+    size_t rlen, cnt, items_m, items_b, slots, sbase, rb_done, htmp, ctmp, ctr, bmax, pc,
         ccls, cpos, cw, coff, ccur, dslot, dmap, store, total;
 };
 struct KnnPtrs {
     uint32_t *rlen;
     uint64_t *cnt, *items_m, *items_b;
     uint32_t *slots, *sbase, *rb_done;
-    uint64_t *skeys;
     uint32_t *htmp;
     uint64_t *ctmp;
     uint32_t *ctr, *bmax, *pc, *ccls, *cpos;

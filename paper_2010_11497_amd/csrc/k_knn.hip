@@ -50,7 +50,7 @@ constexpr uint32_t kRows = 64;       // rows of the largest MFMA tile (row membe
 constexpr uint32_t kCols = 128;      // columns of the largest MFMA tile
 constexpr uint32_t kDefaultMfmaMin = 2;
 constexpr uint32_t kDefaultTile32 = 32;   // clusters up to this size: 32-row tiles
-constexpr uint32_t kDefaultTile64 = 64;   // up to this size: 64-row tiles, else 128
+constexpr uint32_t kDefaultTile64 = 64;   // up to this size: 64 x 64 tiles, else 64 x 128
 constexpr uint32_t kGroupTiles = 16; // column tiles per work item before a row block is split
 constexpr uint32_t kMaxGroups = 4;   // column groups a row block is split into at most
 constexpr uint32_t kLensGrid = 2048;  // blocks of k_lens at most
@@ -710,7 +710,7 @@ C2_DEV float sigma_of(uint64_t root) {
 }
 
 struct MfmaScratch {
-    uint64_t *keys;         // [slot][kRows][kMaxK]
+    uint64_t *keys;         // [slot][kRows][k], at the start of the store
     uint32_t *rb_done;      // per (cluster, row block) of a split row block
     const uint32_t *sbase;  // first slot of each cluster
 };
@@ -1077,7 +1077,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
                 a.part_I[base + q] = 0;
             }
         } else {
-            uint64_t *out = sc.keys + ((size_t)(slot0 + g) * kRows + R) * kMaxK;
+            uint64_t *out = sc.keys + ((size_t)(slot0 + g) * kRows + R) * a.k;
 #pragma unroll
             for (uint32_t i = 0; i < kMaxK; ++i)
                 if (i < cnt) out[rk[i]] = ent[i];
@@ -1098,13 +1098,13 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
         const uint32_t R = 32 * bj + lr, p = rb * TRR + R;
         if (p >= s) continue;
         const uint32_t u = a.members[cv.o + p], Lu = ulen[u];
-        const uint64_t *in = sc.keys + ((size_t)slot0 * kRows + R) * kMaxK;
+        const uint64_t *in = sc.keys + ((size_t)slot0 * kRows + R) * a.k;
         uint32_t ptr[kMaxGroups];
         uint64_t head[kMaxGroups];
 #pragma unroll
         for (uint32_t q = 0; q < kMaxGroups; ++q) {
             ptr[q] = 0;
-            head[q] = q < ng ? in[(size_t)q * kRows * kMaxK] : 0;
+            head[q] = q < ng ? in[(size_t)q * kRows * a.k] : 0;
         }
         const size_t base = ((size_t)u * a.t + cv.j) * a.k;
         for (uint32_t r = 0; r < a.k; ++r) {
@@ -1118,7 +1118,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
                 if (q == best) {
                     v = head[q];
                     ++ptr[q];
-                    head[q] = (v != 0 && ptr[q] < a.k) ? in[(size_t)q * kRows * kMaxK + ptr[q]] : 0;
+                    head[q] = (v != 0 && ptr[q] < a.k) ? in[(size_t)q * kRows * a.k + ptr[q]] : 0;
                 }
             if (v == 0) {
                 a.part_id[base + r] = kPad;
@@ -1433,7 +1433,6 @@ size_t knn_ws_fixed(uint32_t n, uint32_t NE, uint32_t m, KnnWs *w) {
     x.sbase = take(4 * (size_t)NE);
     const size_t nslot = knn_max_slots(NE);
     x.rb_done = take(4 * nslot);
-    x.skeys = take(8 * nslot * kRows * kMaxK);
     x.items_b = take(8 * (size_t)NE);
     x.ctmp = take(8 * scan_tmp_elems(NE + 1));
     x.htmp = take(4 * scan_tmp_elems(NE + 1));
@@ -1453,15 +1452,20 @@ size_t knn_ws_fixed(uint32_t n, uint32_t NE, uint32_t m, KnnWs *w) {
     return off;
 }
 
-// Default room for the store: the dictionary rows of every cluster, where a
-// member's row over its cluster's dictionary takes about 4 words per profile
-// item on the workloads measured, plus the row padding (8 words at least per
-// row, 32-row blocks), capped by the rows over the whole item universe.
+// Default room for the store: the scratch of split row blocks, taken as one
+// slot of 64 rows x 32 keys (u64) per 64 slots of the partition (the slots a
+// partition needs when its clusters above 2048 members hold half the slots),
+// and the dictionary rows of every cluster, where a member's row over its
+// cluster's dictionary takes about 4 words per profile item on the workloads
+// measured, plus the row padding (8 words at least per row, 32-row blocks),
+// capped by the rows over the whole item universe.  A partition that needs
+// more is reported (c2_local_knn, header bytes 8..15).
 size_t knn_store_default_bytes(uint32_t n, uint32_t NE, uint32_t m, uint64_t nnz, uint32_t t) {
     const double tnnz = (double)nnz * t;
     double words = 4.0 * tnnz + 16.0 * NE + 8192.0;
     const double full = ((double)NE + 31.0 * NE / 2.0) * full_row_words(m);
     if (words > full) words = full;
+    words += (double)NE / 64.0 * kRows * kMaxK * 2.0;
     (void)n;
     return ((size_t)words > 1024 ? (size_t)words : 1024) * 4;  // 4 KiB at least
 }
@@ -1505,10 +1509,20 @@ static StageArgs stage_args(const KnnPtrs &w) {
     return st;
 }
 
+// The store begins with the scratch of the split row blocks (nslots slots of
+// kRows x k keys, u64): the cursor of the dictionary rows starts past it, so
+// that a scratch larger than the store fails every cluster's allocation.
+__global__ void k_store_init(unsigned long long *ccur, const uint32_t *nslots, uint32_t slot_words) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const unsigned long long w = (unsigned long long)(*nslots) * slot_words;
+        ccur[0] = (w + 63ull) & ~63ull;
+    }
+}
+
 // Staging of every cluster with >= 2 members, from the work lists the plan
 // wrote (the MFMA list, then the bitmap list; both start with each cluster's
-// first item).
-static hipError_t stage(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
+// first item).  nslots: the plan's count of scratch slots.
+static hipError_t stage(const KnnArgs &a, const KnnPtrs &w, const uint32_t *nslots, hipStream_t s) {
     const size_t lds = stage_lds(a.Wm);
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)k_dict, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1517,8 +1531,8 @@ static hipError_t stage(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
     if ((e = hipFuncSetAttribute((const void *)k_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds)) != hipSuccess)
         return e;
-    // allocation cursor (u64) and the cluster / item / map cursors
-    if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(w.ccur), 0, 2, s)) != hipSuccess) return e;
+    // allocation cursor (u64, past the scratch) and the cluster / item / map cursors
+    hipLaunchKernelGGL(k_store_init, dim3(1), dim3(64), 0, s, w.ccur, nslots, kRows * a.k * 2);
     if ((e = launch_fill_u32(w.ctr + 4, 0, 3, s)) != hipSuccess) return e;
     const StageArgs st = stage_args(w);
     hipLaunchKernelGGL(k_dict, dim3(kStageGrid), dim3(kStageThreads), lds, s, a, w.items_m, w.ctr, st);
@@ -1544,7 +1558,7 @@ static hipError_t launch_paths(const KnnArgs &a, const KnnPtrs &w, const KnnOpts
     sv.cw = w.cw;
     sv.coff = w.coff;
     MfmaScratch sc;
-    sc.keys = w.skeys;
+    sc.keys = reinterpret_cast<uint64_t *>(w.store);
     sc.rb_done = w.rb_done;
     sc.sbase = w.sbase;
     // the events bracket the MFMA kernel, which carries the large clusters
@@ -1573,7 +1587,7 @@ hipError_t knn_plain(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hipSt
                        w.items_b, w.sbase, w.rb_done, w.ctr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_fill_u32(w.status, 0, 1, s)) != hipSuccess) return e;
-    if ((e = stage(a, w, s)) != hipSuccess) return e;
+    if ((e = stage(a, w, w.slots + a.NE, s)) != hipSuccess) return e;
     uint32_t n[3] = {0, 0, 0};
     e = hipMemcpyAsync(n, w.ctr, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(n + 2, w.status, 4, hipMemcpyDeviceToHost, s);
@@ -1597,7 +1611,7 @@ hipError_t knn_batched(const KnnArgs &a, const KnnPtrs &w, const KnnOpts &o, hip
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_fill_u32(w.status, 0, 1, s)) != hipSuccess) return e;
     // the dictionaries take their clusters from that list, largest first
-    if ((e = stage(a, w, s)) != hipSuccess) return e;
+    if ((e = stage(a, w, w.pc + kSlotCtr, s)) != hipSuccess) return e;
     const uint32_t gm = o.persistent_wgs ? o.persistent_wgs : kDefaultWaves;
     return launch_paths(a, w, o, gm, kBitmapPersistent, true, s);
 }

@@ -10,18 +10,20 @@ FastRandomHash bucket (offset by b so the two key spaces stay apart), and
 groups larger than the cap are split by FastRandomHash (c2_cluster_keys).
 Local KNN and merge are unchanged, so the graph keeps the exact arithmetic.
 
-Training (on the GPU): positive pairs are exact KNN edges of a user subsample
-(c2_brute_force).  For pair (u, v) and head j with bucket distributions
-p_j(u) = softmax(z_u[j*b:(j+1)*b]) the loss is
+Training (on the GPU, every step in the library's kernels): positive pairs
+are exact KNN edges of a user subsample (c2_brute_force).  For pair (u, v)
+and head j with bucket distributions p_j(u) = softmax(z_u[j*b:(j+1)*b]) the
+loss is
     - log sum_c p_j(u,c) p_j(v,c)                 (collide with neighbours)
     - w_neg * log(1 - sum_c p_j(u,c) p_j(w,c))    (w: in-batch non-neighbour)
-    + w_bal * KL(mean_u p_j(u) || uniform)        (use all buckets)
+    + w_bal * sum_c q_j(c) log(q_j(c) b)          (use all buckets; q the batch mean)
     + w_ent * H(p_j(u))                           (be confident)
-averaged over heads and pairs.  The embedding bag runs through the library's
-HIP kernels (c2_embag, c2_embag_backward); the two dense layers and the
-softmax go through torch.  Weights are fp32 masters updated by Adam; the
-forward reads a bf16 copy of E, and inference uses bf16 copies of all
-matrices.
+averaged over heads and pairs (include/c2.h, c2_assign_train_grad).  The
+forward, loss and backward run as one call of the library (bf16 MFMA
+products, fp32 softmax statistics), and the update as c2_adam_step on fp32
+master weights, which also writes the bf16 copies the next forward and the
+inference read.  Batches are drawn on the host from a seeded generator and
+uploaded once.
 """
 
 from __future__ import annotations
@@ -47,25 +49,32 @@ class TrainStats:
     last_loss: float
 
 
-class Assigner:
-    def __init__(self, m: int, t: int, b: int, seed: int = 0, device="cuda"):
-        g = torch.Generator(device="cpu").manual_seed(seed)
-        self.m, self.t, self.b = m, t, b
-        self.E = (torch.randn(m, DIM, generator=g) * 0.5).to(device).requires_grad_()
-        self.W1 = (torch.randn(HIDDEN, DIM, generator=g) / DIM ** 0.5).to(device).requires_grad_()
-        self.b1 = torch.zeros(HIDDEN, device=device, requires_grad=True)
-        self.W2 = (torch.randn(t * b, HIDDEN, generator=g) / HIDDEN ** 0.5).to(device).requires_grad_()
-        self.b2 = torch.zeros(t * b, device=device, requires_grad=True)
+def _bf16_bits(x: np.ndarray) -> np.ndarray:
+    """float32 -> bf16 patterns, round to nearest even."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
 
-    def params(self):
-        return [self.E, self.W1, self.b1, self.W2, self.b2]
+
+class Assigner:
+    """fp32 master weights (E, W1, b1, W2, b2) and the bf16 copies of E, W1,
+    W2 that the kernels read, on the GPU."""
+
+    def __init__(self, m: int, t: int, b: int, seed: int = 0, device="cuda"):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        self.m, self.t, self.b = m, t, b
+        host = {"E": rng.standard_normal((m, DIM)) * 0.5,
+                "W1": rng.standard_normal((HIDDEN, DIM)) / DIM ** 0.5,
+                "b1": np.zeros(HIDDEN),
+                "W2": rng.standard_normal((t * b, HIDDEN)) / HIDDEN ** 0.5,
+                "b2": np.zeros(t * b)}
+        self.master = {k: torch.from_numpy(v.astype(np.float32)).to(device) for k, v in host.items()}
+        self.bf16 = {k: torch.from_numpy(_bf16_bits(host[k].astype(np.float32)).view(np.int16))
+                     .to(device).view(torch.bfloat16) for k in ("E", "W1", "W2")}
 
     def inference_weights(self):
         """(E, W1, b1, W2, b2) as the kernels take them: bf16 matrices, fp32 biases."""
-        with torch.no_grad():
-            return (self.E.detach().to(torch.bfloat16).contiguous(),
-                    self.W1.detach().to(torch.bfloat16).contiguous(), self.b1.detach().contiguous(),
-                    self.W2.detach().to(torch.bfloat16).contiguous(), self.b2.detach().contiguous())
+        return (self.bf16["E"], self.bf16["W1"], self.master["b1"], self.bf16["W2"],
+                self.master["b2"])
 
     def keys(self, P: c2.DeviceProfiles, frh_keys: Optional[torch.Tensor] = None,
              min_gap: float = 0.0, weights=None, with_gap=False):
@@ -103,57 +112,54 @@ def exact_pairs(P, n_sub: int, k: int, seed: int = 0):
 def train(A: Assigner, P: c2.DeviceProfiles, pairs: np.ndarray, steps: int = 400,
           batch: int = 1024, lr: float = 3e-3, w_neg: float = 1.0, w_bal: float = 3.0,
           w_ent: float = 1.0, seed: int = 0, log=None) -> TrainStats:
+    """Adam on the objective above, `steps` batches of `batch` pairs drawn with
+    replacement from `pairs` (host array [npairs][2] of user ids)."""
     dev = P.device
-    pairs_d = torch.from_numpy(pairs.astype(np.int32)).to(dev)
-    opt = torch.optim.Adam(A.params(), lr=lr)
-    gen = torch.Generator(device=dev).manual_seed(seed)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sel = rng.integers(0, pairs.shape[0], size=(steps, batch))
+    rows = np.concatenate([pairs[sel, 0], pairs[sel, 1]], axis=1).astype(np.uint32)
+    rows_d = torch.from_numpy(rows.view(np.int32)).to(dev)
     t, b = A.t, A.b
+    names = ("E", "W1", "b1", "W2", "b2")
+    ws = c2.train_workspace(2 * batch, t, b, dev)
+    loss = torch.empty(5, dtype=torch.float32, device=dev)
+    g = {k: torch.empty_like(A.master[k]) for k in names}
+    m1 = {k: torch.zeros_like(A.master[k]) for k in names}
+    m2 = {k: torch.zeros_like(A.master[k]) for k in names}
+    out = (loss, g["E"], g["W1"], g["b1"], g["W2"], g["b2"])
     first = last = float("nan")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(steps):
-        sel = torch.randint(0, pairs_d.shape[0], (batch,), device=dev, generator=gen)
-        rows = torch.cat([pairs_d[sel, 0], pairs_d[sel, 1]]).contiguous()
-        E16 = A.E.detach().to(torch.bfloat16).contiguous()
-        e = c2.embag(P, E16, rows).requires_grad_()
-        h = torch.relu(e @ A.W1.t() + A.b1)
-        z = (h @ A.W2.t() + A.b2).view(2 * batch, t, b)
-        p = torch.softmax(z, dim=-1)
-        ent = -(p * torch.log_softmax(z, dim=-1)).sum(-1).mean()
-        pu, pv = p[:batch], p[batch:]
-        pos = (pu * pv).sum(-1).clamp_min(1e-12)
-        neg = (pu * pv.roll(1, dims=0)).sum(-1).clamp(0.0, 1.0 - 1e-6)
-        q = p.mean(0)
-        bal = (q * torch.log(q * b + 1e-12)).sum(-1).mean()
-        loss = (-torch.log(pos).mean() - w_neg * torch.log1p(-neg).mean() + w_bal * bal
-                + w_ent * ent)
-        opt.zero_grad(set_to_none=True)
-        loss.backward()
-        dE = torch.zeros_like(A.E)
-        c2.embag_backward(P, e.grad.contiguous(), dE, rows)
-        A.E.grad = dE
-        opt.step()
+        E, W1, b1, W2, b2 = A.inference_weights()
+        c2.assign_train_grad(P, rows_d[step], E, W1, b1, W2, b2, t, b, w_neg, w_bal, w_ent,
+                             ws=ws, out=out)
+        for k in names:
+            c2.adam_step(A.master[k], g[k], m1[k], m2[k], lr, step + 1,
+                         param_bf16=A.bf16.get(k))
         if step == 0:
-            first = float(loss.detach())
+            first = float(loss[0])
         if log and (step % 100 == 0 or step == steps - 1):
-            log("train step %d loss %.4f (pos %.4f neg %.4f bal %.4f ent %.4f)"
-                % (step, float(loss.detach()), float(-torch.log(pos).mean().detach()),
-                   float(-torch.log1p(-neg).mean().detach()), float(bal.detach()),
-                   float(ent.detach())))
-    last = float(loss.detach())
+            v = loss.tolist()
+            log("train step %d loss %.4f (pos %.4f neg %.4f bal %.4f ent %.4f)" % (step, *v))
+    last = float(loss[0])
     torch.cuda.synchronize()
     return TrainStats(steps, time.perf_counter() - t0, int(pairs.shape[0]), first, last)
 
 
 def build(A: Assigner, P: c2.DeviceProfiles, tab: torch.Tensor, p: c2.Params,
           min_gap: float = 0.0, form=c2.FORM_PLAIN, tune: Optional[c2.Tuning] = None,
-          weights=None, check: bool = True, with_ws: bool = False):
+          weights=None, check: bool = True, with_ws: bool = False,
+          knn_ws: Optional[torch.Tensor] = None):
     """The learned-assignment build: keys (FastRandomHash fallback below
     min_gap), clustering from keys with FastRandomHash splits, local KNN,
     merge.  p.b is FastRandomHash's bucket count; the keys span 2*max(b, A.b).
     In the batched form nothing waits on the host, so the call can be captured
-    in a graph: pass check=False there and call c2.check_complete on the
-    clustering workspace (with_ws=True returns it) after each replay."""
+    in a graph: pass check=False and a local-KNN workspace large enough for the
+    partition (knn_ws, e.g. from c2.local_knn_workspace on an eager run), and
+    call c2.check_complete on both workspaces (with_ws=True returns them:
+    clustering, local KNN) after each replay.  With check=True the batched
+    form checks both, growing the local-KNN store once if it was too small."""
     bucket = c2.hash_items(tab, p.b, P.m)
     frh = c2.frh_keys(P, bucket) if min_gap > 0 else None
     keys = A.keys(P, frh, min_gap, weights)
@@ -162,6 +168,23 @@ def build(A: Assigner, P: c2.DeviceProfiles, tab: torch.Tensor, p: c2.Params,
     members, cl_off, cfg, ws = c2.cluster_keys(P, keys, bucket, pk, form, tune)
     if form == c2.FORM_BATCHED and check:
         c2.check_complete(ws)   # enough split rounds were enqueued (synchronous)
-    part = c2.local_knn(P, members, cl_off, cfg, pk, form, tune)
+    if form == c2.FORM_PLAIN:
+        # the plain form reports a small store synchronously (and the binding
+        # grows a workspace it allocated itself)
+        kws = knn_ws
+        part = c2.local_knn(P, members, cl_off, cfg, pk, form, tune, ws=kws)
+    else:
+        kws = c2.workspace(P, pk, c2.OP_LOCAL_KNN) if knn_ws is None else knn_ws
+        part = c2.local_knn(P, members, cl_off, cfg, pk, form, tune, ws=kws)
+        if check:
+            try:
+                c2.check_complete(kws)
+            except c2.C2Error as e:
+                if e.status != c2.C2_E_WORKSPACE or knn_ws is not None:
+                    raise
+                kws = torch.empty(kws.numel() + c2.store_need_bytes(kws), dtype=torch.uint8,
+                                  device=kws.device)
+                part = c2.local_knn(P, members, cl_off, cfg, pk, form, tune, ws=kws)
+                c2.check_complete(kws)
     out = c2.merge(P, part[0], part[1], pk)
-    return (out, ws) if with_ws else out
+    return (out, ws, kws) if with_ws else out

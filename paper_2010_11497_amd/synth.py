@@ -226,6 +226,28 @@ def assigner_weights(m: int, t: int, b: int, seed: int, dim: int = 64, hidden: i
     return E, W1, b1, W2, b2
 
 
+def assigner_exact_weights(m: int, t: int, b: int, seed: int, dim: int = 64,
+                           hidden: int = 256):
+    """Seeded assigner weights whose products and sums are all exact in bf16
+    and fp32: E holds integers 0..3, each W1 row adds two embedding
+    dimensions, each W2 row picks one hidden unit (a seeded choice of b
+    units per configuration, distinct when b <= hidden), biases are zero.
+    Same layout as assigner_weights."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    E = rng.integers(0, 4, size=(m, dim)).astype(np.float32)
+    W1 = np.zeros((hidden, dim), dtype=np.float32)
+    for r in range(hidden):
+        W1[r, rng.choice(dim, size=2, replace=False)] = 1.0
+    W2 = np.zeros((t * b, hidden), dtype=np.float32)
+    for j in range(t):
+        W2[j * b + np.arange(b), rng.choice(hidden, size=b, replace=b > hidden)] = 1.0
+
+    def bits(x):
+        return (x.view(np.uint32) >> 16).astype(np.uint16)
+    return (bits(E), bits(W1), np.zeros(hidden, dtype=np.float32), bits(W2),
+            np.zeros(t * b, dtype=np.float32))
+
+
 def hidden_inputs(n: int, seed: int, hidden: int = 256) -> np.ndarray:
     """Seeded stand-in for the hidden layer (uint16 bf16 patterns [n][hidden]):
     non-negative, about half exact zeros, as after a ReLU."""

@@ -29,7 +29,7 @@ def test_header_lists_entry_points():
     names = declared()
     from paper_2010_11497_amd import c2
     assert names == sorted(c2.SYMBOLS)
-    assert len(names) == 22
+    assert len(names) == 25
 
 
 def test_library_exports_every_symbol(lib):
@@ -91,3 +91,23 @@ def test_argument_errors_before_enqueue(lib):
     assert lib.c2_fingerprint(ctypes.byref(q), ctypes.c_void_p(1), 1024, ctypes.c_void_p(1),
                               ctypes.c_void_p(1), ctypes.byref(nnz), ctypes.c_void_p(1), 16,
                               None) == -3          # workspace too small
+
+
+def test_training_entry_points_host_checks(lib):
+    from paper_2010_11497_amd import c2
+    assert lib.c2_assign_train_workspace_bytes(3, 1, 64) == 0          # odd batch
+    assert b"nrows = 3" in lib.c2_last_error()
+    assert lib.c2_assign_train_workspace_bytes(2, 1, 96) == 0          # b not a multiple of 64
+    small = lib.c2_assign_train_workspace_bytes(2, 1, 64)
+    big = lib.c2_assign_train_workspace_bytes(4096, 16, 8192)
+    # the big batch holds its logits (fp32) and their gradient (bf16)
+    assert small > 0 and big > 4096 * 16 * 8192 * 6
+    one = ctypes.c_void_p(1)
+    assert lib.c2_adam_step(one, one, one, one, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None, None) == -1
+    assert lib.c2_adam_step(None, one, one, one, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == -1
+    assert lib.c2_adam_step(one, one, one, one, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == 0
+    P = c2.Profiles(10, 5, 20, 1, 1)
+    o = c2.TrainOpts(1.0, 1.0, 1.0)
+    assert lib.c2_assign_train_grad(ctypes.byref(P), one, 4, one, one, one, one, one, 1, 64,
+                                    ctypes.byref(o), one, one, one, one, one, one, one, 16,
+                                    None) == -3            # workspace too small

@@ -224,11 +224,70 @@ def test_learned_pipeline_end_to_end(A, orc):
         assert len({v for _, _, v in row}) == len(row) and u not in {v for _, _, v in row}
 
 
+@pytest.mark.parametrize("min_gap", [0.0, 0.0625])
+def test_learned_pipeline_exact_weights(A, orc, min_gap):
+    """The whole learned build on weights for which the kernels' bf16/fp32
+    arithmetic is exact (synth.assigner_exact_weights), so that every key is
+    decided: the hidden layer, the keys and gaps of all users equal the
+    oracle's, FastRandomHash fallback included (min_gap 0.0625 sends about
+    half the users there; min_gap 0 leaves the argmax ties to the lowest
+    bucket), and the partition and graph of the GPU pipeline (clustering from
+    keys with FastRandomHash splits, local KNN, merge; both forms) equal the
+    oracle's pipeline run on the oracle's own keys, bit for bit."""
+    w = synth.WORKLOADS["n2k_m1k"]
+    say("learned pipeline, exact weights, min_gap", min_gap)
+    P = synth.make_profiles(w)
+    t, b = w.t, 64
+    tab = synth.hash_tables(t, w.hash_seed)
+    E, W1, b1, W2, b2 = synth.assigner_exact_weights(P.m, t, b, 77)
+    dP = c2.DeviceProfiles.from_synth(P)
+    bucket = c2.hash_items(c2.tables_to_device(tab), b, P.m)
+    frh = c2.frh_keys(dP, bucket) if min_gap > 0 else None
+    h = c2.assign_hidden(dP, bf16_dev(E), bf16_dev(W1), torch.from_numpy(b1).cuda())
+    keys, gap = c2.assign_keys(h, bf16_dev(W2), torch.from_numpy(b2).cuda(), t, b, frh, min_gap,
+                               with_gap=True)
+    # the oracle's keys, from its own hidden layer and FastRandomHash keys
+    _, hw = A.hidden(P.indptr, P.indices, A.from_bf16_bits(E), A.from_bf16_bits(W1),
+                     b1.astype(np.float64))
+    wkey, wgap, _ = A.keys(hw, A.from_bf16_bits(W2), b2.astype(np.float64), t, b)
+    obucket = orc.hash_items(tab, b, P.m)
+    okeys = wkey
+    if min_gap > 0:
+        fall = wgap < np.float32(min_gap)
+        assert 0.2 < fall.mean() < 0.8
+        okeys = np.where(fall, b + orc.frh_keys(P.indptr, P.indices, P.n, P.m, obucket), wkey)
+    else:
+        assert (wgap == 0).mean() > 0.05          # ties decided by the lowest bucket
+    assert np.array_equal(A.from_bf16_bits(bf16_host(h)), hw)
+    if min_gap > 0:
+        assert np.array_equal(gap.cpu().numpy().astype(np.float64), wgap)
+    assert np.array_equal(c2.to_u32(keys).reshape(t, P.n), okeys.astype(np.uint32))
+    # the rest of the pipeline: the oracle on its keys, the GPU on its own
+    om, ooff, ocfg, _ = orc.cluster_keys(P.indptr, P.indices, P.n, P.m, okeys.astype(np.uint32),
+                                         obucket, w.cap)
+    pid, pI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, w.k, om, ooff, ocfg, THREADS)
+    want = orc.merge(P.indptr, P.n, t, w.k, pid, pI)
+    p = c2.params(t, 2 * b, w.cap, w.k)
+    for form in (c2.FORM_PLAIN, c2.FORM_BATCHED):
+        mem, off, cfg, ws = c2.cluster_keys(dP, keys, bucket, p, form, c2.tuning(split_rounds=64))
+        if form == c2.FORM_BATCHED:
+            c2.check_complete(ws)
+        gcfg = c2.to_u32(cfg)
+        assert np.array_equal(gcfg, ocfg)
+        assert np.array_equal(c2.to_u32(off)[: gcfg[-1] + 1], ooff)
+        assert np.array_equal(c2.to_u32(mem), om)
+        part = c2.local_knn(dP, mem, off, cfg, p, form)
+        got = c2.merge(dP, part[0], part[1], p)
+        for g, ww in zip(got, want):
+            assert np.array_equal(c2.to_u32(g), ww)
+
+
 def test_learned_build_graph_replays_equal_eager():
     """The batched learned build (keys, clustering from keys, local KNN,
     merge) captured once in a graph: several replays, with eager work and
     synchronisations between them, each checked for the split-round status
-    and against the eager batched result."""
+    and the local KNN's store and against the eager batched result; the
+    captured build takes the local-KNN workspace an eager run sized."""
     from paper_2010_11497_amd import learned
     say("learned graph replays")
     P = synth.random_profiles(123, 3000, 800, 5, 60, 1.0)
@@ -239,16 +298,19 @@ def test_learned_build_graph_replays_equal_eager():
     Asg = learned.Assigner(P.m, t, b, seed=5)
     W = Asg.inference_weights()
     tb = c2.tuning(split_rounds=16)
-    ref = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W)
+    ref, _, kws = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W,
+                                with_ws=True)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, capture_error_mode="thread_local"):
-        gout, gws = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W,
-                                  check=False, with_ws=True)
+        gout, gws, gkws = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W,
+                                        check=False, with_ws=True, knn_ws=kws)
+    assert gkws is kws
     for rep in range(4):
         g.replay()
         torch.cuda.synchronize()
         c2.check_complete(gws)
+        c2.check_complete(gkws)
         for a, b2 in zip(gout, ref):
             assert torch.equal(a, b2), rep
         # eager work between replays
