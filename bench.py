@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
-"""Benchmark: Cluster-and-Conquer KNN-graph builds on one MI355X.
+"""Benchmark: Cluster-and-Conquer KNN-graph builds on one MI355X at quality 0.95.
 
 A step is one whole build of the method on one batch of synthetic input with
 the profiles already resident in HBM: item hashing, FastRandomHash keys,
 clustering with recursive splitting, brute-force local KNN in every cluster,
-and the merge (Sections II-D to II-G).  The timed form is the batched build
-replayed as a HIP graph; the plain (host-driven) form is timed beside it.
+and the merge (Sections II-D to II-G).  The build runs at the setting of the
+hash-configuration count t and split threshold N that reaches quality 0.95
+against the exact graph (Eq. 2) fastest (the time/quality trade-off of
+Section VI, Figs. 6-7); the workload's own t and N are timed beside it.  The
+timed form is the batched build replayed as a HIP graph; the batched and plain
+eager forms and the learned-assignment build are timed beside it.
 
 value = Jaccard evaluations per second of whole-build time, where a Jaccard
 evaluation is one same-cluster pair (the paper's count of similarity
-computations, Section II-F).  The line also carries the quality of the graph
-against the exact graph (Eq. 2), the roofline of the dominant kernel (the
-pairwise local-KNN kernel, timed with HIP events on its own stream), and the
-CPU oracle timed on the host's cores.
+computations, Section II-F).  The line also carries the roofline of the
+dominant kernel (the pairwise local-KNN kernel, timed with HIP events that the
+library records on its own stream), and the CPU oracle timed on the host's
+cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 import argparse
 import hashlib
@@ -29,12 +33,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("Jaccard evals/s + KNN-graph build time at quality≥0.95, plain vs batched vs "
           "learned")
-DEFAULT_WORKLOAD = "n6k_m3.7k"
-VALU_PEAK = 256 * 4 * 16 * 2.4e9      # int32 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+DEFAULT_WORKLOAD = "n500k_m50k"
+QUALITY_BAR = 0.95
 MFMA_FP4_PEAK = 10.1e15               # dense fp4 (e2m1) MFMA flop/s
 KNN_KERNEL = "k_knn_mfma"
 MFMA_MIN_DEFAULT = 2                  # library default: clusters of >= 2 members take the MFMA path
-KNN_SOURCES = ["paper_2010_11497_amd/csrc/k_knn.hip", "paper_2010_11497_amd/csrc/c2_internal.h"]
+KNN_SOURCES = ["paper_2010_11497_amd/csrc/k_knn.hip", "paper_2010_11497_amd/csrc/c2_internal.h",
+               "paper_2010_11497_amd/csrc/c2_kernels.h"]
 
 
 def log(*a):
@@ -49,54 +54,87 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload):
-    """HBM bytes per launch of the local-KNN kernel from the committed PMC
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a device copy of known size),
-    only if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (KNN_KERNEL, workload))
+def profile_json(tag, kind):
+    """A committed PMC summary of the local-KNN kernel for this workload and
+    setting, only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s.json" % (KNN_KERNEL, tag, kind))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != source_hash():
-        return None
-    return d.get("bytes_per_launch")
+    return d if d.get("source_hash") == source_hash() else None
 
 
-def mfma_busy_from_profiles(workload):
-    """Hardware MFMA busy share of the local-KNN kernel (SQ_VALU_MFMA_BUSY_CYCLES
-    over the dispatch's cycles times the SIMD count) from the committed PMC
-    summary, only if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_mfma_busy.json" % (KNN_KERNEL, workload))
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        d = json.load(f)
-    return d.get("mfma_busy_frac") if d.get("source_hash") == source_hash() else None
+def setting_tag(w, t, cap):
+    return "%s_t%d_N%d" % (w.name, t, cap)
 
 
-def cpu_baseline(P, tab, w, E, budget_s):
-    """The oracle as it stands, on the host's cores, on whole builds of the same
-    workload repeated until about budget_s seconds have passed."""
+def cpu_baseline(P, tab, w, cap, E, budget_s):
+    """The oracle as it stands, on the host's cores, on a bounded sample of the
+    headline build: hashing and clustering in full, the local KNN on every
+    s-th cluster (s chosen so the sample takes about budget_s seconds), and
+    the merge on the first users' lists filled with t*k seeded candidates.  The
+    whole-build time is the full parts plus the sampled parts scaled by the
+    share of Jaccard evaluations (local KNN) and of users (merge) they hold."""
+    import numpy as np
     from oracle import oracle
     threads = min(16, os.cpu_count() or 1)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        oracle.build_graph(P.indptr, P.indices, P.n, P.m, tab, w.b, w.cap, w.k, threads)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or el / reps * (reps + 1) > 3 * budget_s:
-            break
+    t0 = time.perf_counter()
+    bucket = oracle.hash_items(tab, w.b, w.m)
+    t_hash = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    members, cl_off, cfg, _ = oracle.cluster(P.indptr, P.indices, P.n, P.m, bucket, cap)
+    t_cluster = time.perf_counter() - t0
+    t = bucket.shape[0]
+    off = cl_off.astype(np.int64)
+    sizes = np.diff(off)
+    E_orc = int((sizes * (sizes - 1) // 2).sum())
+
+    def knn_sample(stride):
+        idx = np.arange(0, len(sizes), stride, dtype=np.int64)
+        lens = sizes[idx]
+        sub_off = np.zeros(len(idx) + 1, dtype=np.int64)
+        sub_off[1:] = np.cumsum(lens)
+        within = np.arange(int(sub_off[-1])) - np.repeat(sub_off[:-1], lens)
+        sub_mem = members[np.repeat(off[idx], lens) + within]
+        sub_cfg = np.searchsorted(idx, cfg.astype(np.int64)).astype(np.uint32)
+        pairs = int((lens * (lens - 1) // 2).sum())
+        t1 = time.perf_counter()
+        oracle.local_knn(P.indptr, P.indices, P.n, P.m, t, w.k, sub_mem,
+                         sub_off.astype(np.uint32), sub_cfg, threads)
+        return pairs, time.perf_counter() - t1
+
+    # a small probe for the rate, then the sample sized to the budget
+    pairs, el = knn_sample(max(1, int(E_orc // 2e7)))
+    rate = pairs / max(el, 1e-6)
+    stride = max(1, int(math.ceil(E_orc / max(rate * budget_s * 0.7, 1.0))))
+    pairs, el = knn_sample(stride)
+    t_knn = el * E_orc / max(pairs, 1)
+    n_m = min(P.n, 20000)
+    rng = np.random.Generator(np.random.PCG64(7))
+    pid = rng.integers(0, P.n, size=(n_m, t, w.k), dtype=np.uint32)
+    pI = rng.integers(0, 8, size=(n_m, t, w.k), dtype=np.uint32)
+    t1 = time.perf_counter()
+    oracle.merge(P.indptr, n_m, t, w.k, pid, pI)
+    t_merge = (time.perf_counter() - t1) * P.n / n_m
+    total = t_hash + t_cluster + t_knn + t_merge
     model = None
     try:
         with open("/proc/cpuinfo") as f:
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": E * reps / el, "unit": "Jaccard evals/s", "cores": threads, "kind": "oracle",
+    return {"value": E / total, "unit": "Jaccard evals/s", "cores": threads, "kind": "oracle",
             "host_cpus": os.cpu_count(), "cpu_model": model,
-            "sample": "%d whole build(s) of %s (hash, cluster, local KNN on a %d-thread pool "
-                      "largest cluster first, merge): %.2f s each" % (reps, w.name, threads, el / reps)}
+            "build_s_estimate": total,
+            "parts_s": {"hash": t_hash, "cluster": t_cluster, "local_knn": t_knn,
+                        "merge": t_merge},
+            "sample": "%s at t=%d, N=%d: hashing and clustering in full (%.2f s), local KNN on "
+                      "every %d-th cluster (%d of %d Jaccard evaluations, %.2f s, on a %d-thread "
+                      "pool largest cluster first) scaled to all, merge of %d users' lists of "
+                      "t*k seeded candidates scaled to n" %
+                      (w.name, t, cap, t_hash + t_cluster, stride, pairs, E_orc, el, threads,
+                       n_m)}
 
 
 def upload_ms(P, torch, reps=5):
@@ -214,13 +252,13 @@ def time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf,
             q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), eI, eU)
             res["points"].append({"t": t, "N": cap, "build_ms_plain": ms, "quality": q})
             log("t=%2d N=%5d: plain build %8.3f ms, quality %.4f" % (t, cap, ms, q))
-    ok = [x for x in res["points"] if x["quality"] >= 0.95]
+    ok = [x for x in res["points"] if x["quality"] >= QUALITY_BAR]
     if ok:
         best = min(ok, key=lambda x: x["build_ms_plain"])
         dtab = c2.tables_to_device(synth.hash_tables(best["t"], w.hash_seed))
         p = c2.params(best["t"], w.b, best["N"], w.k)
         from paper_2010_11497_amd import autotune
-        tuned = autotune.load_table(w.name) if (best["t"], best["N"]) == (w.t, w.cap) else None
+        tuned = autotune.load_table(w.name, best["t"], best["N"])
         g = c2.Graph(dP, dtab, p, c2.tuning(**(tuned or {})))
         g.launch()
         torch.cuda.synchronize()
@@ -230,6 +268,7 @@ def time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf,
             g.launch()
         torch.cuda.synchronize()
         best = dict(best, build_ms_graph=(time.perf_counter() - t1) * 1e3 / reps)
+        g.check()
         g.close()
         res["fastest_at_0.95"] = best
         log("fastest setting with quality >= 0.95: %s" % best)
@@ -273,11 +312,12 @@ def hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np, bf, rho=5):
     return res
 
 
-def learned_graph(args, A, dP, tab, p, gap, tb, W, ref, c2, torch, learned):
+def learned_graph(args, A, dP, tab, p, gap, W, ref, kws, c2, torch, learned):
     """The batched learned build captured once as a graph, with the fewest
-    split rounds that complete, and replayed: the time per replay, and whether
-    every replay (checked after each, with the split-round status) equals the
-    eager batched result `ref`."""
+    split rounds that complete and the local-KNN workspace kws sized on an
+    eager run, and replayed: the time per replay, and whether every replay
+    (checked after each for the split rounds and the store) equals the eager
+    batched result `ref`."""
     try:
         # the fewest split rounds that complete on this data (synchronous
         # status check), as the FastRandomHash graph learns them from a plain run
@@ -285,7 +325,7 @@ def learned_graph(args, A, dP, tab, p, gap, tb, W, ref, c2, torch, learned):
         for r in (2, 4, 8, 16, 32):
             try:
                 learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, c2.tuning(split_rounds=r),
-                              weights=W)
+                              weights=W, knn_ws=kws)
                 rounds = r
                 break
             except c2.C2Error:
@@ -294,13 +334,14 @@ def learned_graph(args, A, dP, tab, p, gap, tb, W, ref, c2, torch, learned):
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, capture_error_mode="thread_local"):
-            gout, gws = learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W,
-                                      check=False, with_ws=True)
+            gout, gws, gkws = learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W,
+                                            check=False, with_ws=True, knn_ws=kws)
         equal = True
-        for _ in range(max(args.warmup, 2)):
+        for _ in range(args.warmup):
             g.replay()
             torch.cuda.synchronize()
             c2.check_complete(gws)
+            c2.check_complete(gkws)
             equal &= all(torch.equal(a, b) for a, b in zip(gout, ref))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -309,6 +350,7 @@ def learned_graph(args, A, dP, tab, p, gap, tb, W, ref, c2, torch, learned):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t1) * 1e3 / args.steps
         c2.check_complete(gws)
+        c2.check_complete(gkws)
         equal &= all(torch.equal(a, b) for a, b in zip(gout, ref))
         del g
         return {"build_ms_graph": ms, "graph_split_rounds": rounds,
@@ -317,16 +359,16 @@ def learned_graph(args, A, dP, tab, p, gap, tb, W, ref, c2, torch, learned):
         return {"build_ms_graph": None, "graph_error": str(e)[:200]}
 
 
-def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_ms, batched_ms):
+def learned_variant(args, w, P, dP, T, cap, c2, metrics, synth, torch, np, bf):
     """The learned cluster assigner: trained here on exact KNN edges of a
     100,000-user subsample, then the learned-assignment build (assignment,
-    clustering from keys with FastRandomHash splits, local KNN, merge) timed in
-    the plain and batched eager forms and scored against the exact graph.  Heads
-    and split threshold default to the workload's t and N."""
-    from paper_2010_11497_amd import learned, synth
+    clustering from keys with FastRandomHash splits, local KNN, merge) at T
+    heads and split threshold N, timed in the plain and batched eager forms
+    and as a graph replay, and scored against the exact graph.  min_gap 0
+    takes every learned bucket; min_gap 0.5 sends users whose top two logits
+    are closer than that to their FastRandomHash bucket."""
+    from paper_2010_11497_amd import learned
     b = 8192 if w.n >= 100000 else w.b
-    T = args.learned_t or w.t
-    cap = args.learned_cap or w.cap
     t0 = time.perf_counter()
     pairs = learned.exact_pairs(P, 100000, w.k, seed=1)
     A = learned.Assigner(P.m, T, b, seed=2)
@@ -334,25 +376,24 @@ def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_m
                        w_ent=1.0, lr=3e-3, log=log)
     train_s = time.perf_counter() - t0
     W = A.inference_weights()
-    tabT = c2.tables_to_device(synth.hash_tables(T, w.hash_seed)) if T != w.t else dtab
-    pT = c2.params(T, w.b, cap, w.k)
+    tab = c2.tables_to_device(synth.hash_tables(T, w.hash_seed))
+    p = c2.params(T, w.b, cap, w.k)
     res = {"buckets": b, "heads": T, "N": cap, "train_s": train_s, "train_steps": st.steps,
            "train_pairs": st.pairs, "loss": [st.first_loss, st.last_loss], "min_gap": {}}
     tb = c2.tuning(split_rounds=64)
     for gap in (0.0, 0.5):
         entry = {}
-        for form, tu, key in ((c2.FORM_PLAIN, None, "build_ms_plain"),
-                              (c2.FORM_BATCHED, tb, "build_ms_batched")):
-            out = None
-            for _ in range(args.warmup):
-                out = learned.build(A, dP, tabT, pT, gap, form, tu, weights=W)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(args.steps):
-                out = learned.build(A, dP, tabT, pT, gap, form, tu, weights=W)
-            torch.cuda.synchronize()
-            entry[key] = (time.perf_counter() - t1) * 1e3 / args.steps
-        entry.update(learned_graph(args, A, dP, tabT, pT, gap, tb, W, out, c2, torch, learned))
+        # the local-KNN workspace of the batched form, sized on one checked run
+        _, _, kws = learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W,
+                                  with_ws=True)
+        ms, _ = time_loop(lambda o: learned.build(A, dP, tab, p, gap, c2.FORM_PLAIN, None,
+                                                  weights=W), args.warmup, args.steps, torch)
+        entry["build_ms_plain"] = ms
+        ms, out = time_loop(lambda o: learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, tb,
+                                                    weights=W, knn_ws=kws),
+                            args.warmup, args.steps, torch)
+        entry["build_ms_batched"] = ms
+        entry.update(learned_graph(args, A, dP, tab, p, gap, W, out, kws, c2, torch, learned))
         q = None
         if bf is not None:
             q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
@@ -364,59 +405,155 @@ def learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np, bf, plain_m
                                                    entry["build_ms_batched"],
                                                    entry.get("build_ms_graph"),
                                                    entry.get("graph_equals_eager"), q))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        A.keys(dP, None, 0.0, W)
-    torch.cuda.synchronize()
-    res["assign_ms"] = (time.perf_counter() - t1) * 1e3 / args.steps
-    res["frh_build_ms"] = {"plain": plain_ms, "batched": batched_ms}
-    # FastRandomHash's time to the same quality bar: more hash configurations
-    # until the graph reaches quality 0.95 (plain form)
-    if bf is not None:
-        from paper_2010_11497_amd import synth
-        sweep = []
-        for t in (w.t, w.t + 2, w.t + 4, w.t + 8):
-            tab_t = c2.tables_to_device(synth.hash_tables(t, w.hash_seed))
-            p_t = c2.params(t, w.b, w.cap, w.k)
-            out = c2.build(dP, tab_t, p_t, c2.FORM_PLAIN)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(args.steps):
-                out = c2.build(dP, tab_t, p_t, c2.FORM_PLAIN)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t1) * 1e3 / args.steps
-            q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
-                                c2.to_u32(bf[2]))
-            sweep.append({"t": t, "build_ms_plain": ms, "quality": q})
-            log("FastRandomHash t=%d: plain build %.3f ms, quality %.4f" % (t, ms, q))
-            if q >= 0.95:
-                break
-        res["frh_t_sweep"] = sweep
+    res["assign_ms"], _ = time_loop(lambda o: A.keys(dP, None, 0.0, W), 0, args.steps, torch)
     log("assignment (hidden layer + keys) %.3f ms; training %.1f s" % (res["assign_ms"], train_s))
+    # the fastest learned build that reaches the bar, for the build_ms summary
+    ok = [(e.get("build_ms_graph") or e["build_ms_batched"], g, e)
+          for g, e in res["min_gap"].items() if e["quality"] is not None and
+          e["quality"] >= QUALITY_BAR]
+    if ok:
+        _, g, e = min(ok, key=lambda x: x[0])
+        res["at_bar"] = {"min_gap": float(g), "plain": e["build_ms_plain"],
+                         "batched": e["build_ms_batched"], "graph": e.get("build_ms_graph"),
+                         "quality": e["quality"]}
     return res
+
+
+def time_loop(fn, warmup, steps, torch):
+    """Mean wall time per call of fn(previous output) over `steps` calls after
+    `warmup` untimed ones, synchronised on both sides."""
+    out = None
+    for _ in range(warmup):
+        out = fn(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn(out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / max(steps, 1), out
+
+
+def frh_leg(args, w, dP, t, cap, c2, metrics, synth, torch, np, bf, events):
+    """The FastRandomHash build at t hash configurations and split threshold
+    N = cap: its partition's work counts, the graph replay (the timed form),
+    the batched and plain eager forms (all three must give the same graph),
+    the quality, and with events=True the local-KNN kernel's own time over
+    K batched builds (HIP events the library records on its stream right
+    before and after that kernel)."""
+    from paper_2010_11497_amd import autotune
+    tab = synth.hash_tables(t, w.hash_seed)
+    dtab = c2.tables_to_device(tab)
+    p = c2.params(t, w.b, cap, w.k)
+    tuned = autotune.load_table(w.name, t, cap) or {}
+    log("t=%d N=%d tuning: %s" % (t, cap, tuned if tuned else "built-in defaults"))
+
+    # partition statistics (the GPU clustering, counted on the device with torch)
+    bucket = c2.hash_items(dtab, w.b, w.m)
+    members, cl_off, cfg, _ = c2.cluster(dP, bucket, p, c2.FORM_PLAIN)
+    ncl = int(c2.to_u32(cfg)[-1])
+    work = metrics.cluster_work_torch(members, cl_off[: ncl + 1], c2.to_u32(cfg), dP.indptr,
+                                      dP.indices, w.m)
+    del members, cl_off, cfg, bucket
+    E = work["pairs"]
+    log("t=%d N=%d: clusters %d, Jaccard evals %d, max cluster %d"
+        % (t, cap, ncl, E, int(work["sizes"].max())))
+
+    g = c2.Graph(dP, dtab, p, c2.tuning(**tuned))
+    for _ in range(args.warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    g.check()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.launch()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    g.check()                  # every timed replay ran enough split rounds
+    out_graph = [c2.to_u32(x) for x in g.out]
+
+    def timed(form):
+        ws = torch.empty_like(g.ws)
+        tu = c2.tuning(**tuned)
+        ms, out = time_loop(lambda o: c2.build(dP, dtab, p, form, tu, ws=ws, out=o),
+                            args.warmup, args.steps, torch)
+        return ms, [c2.to_u32(x) for x in out]
+    batched_ms, out_b = timed(c2.FORM_BATCHED)
+    plain_ms, out_p = timed(c2.FORM_PLAIN)
+    same = all(np.array_equal(a, b) for a, b in zip(out_graph, out_b)) and \
+        all(np.array_equal(a, b) for a, b in zip(out_graph, out_p))
+    if not same:
+        raise SystemExit("forms disagree at t=%d N=%d: graph, batched and plain builds differ"
+                         % (t, cap))
+    log("t=%d N=%d: graph %.3f ms, batched %.3f ms, plain %.3f ms"
+        % (t, cap, graph_ms, batched_ms, plain_ms))
+
+    knn_ms = None
+    if events:
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ws = torch.empty_like(g.ws)
+        tu = c2.tuning(events=ev, **tuned)
+        out, knn = None, []
+        for _ in range(args.steps):
+            out = c2.build(dP, dtab, p, c2.FORM_BATCHED, tu, ws=ws, out=out)
+            ev[1].synchronize()
+            knn.append(ev[0].elapsed_time(ev[1]))
+        knn_ms = sum(knn) / len(knn)
+        log("local-KNN kernel: %.3f ms (events, mean of %d batched builds)" % (knn_ms, len(knn)))
+    g.close()
+    quality = None
+    if bf is not None:
+        quality = metrics.quality(out_graph[1], out_graph[2], c2.to_u32(bf[1]), c2.to_u32(bf[2]))
+        log("t=%d N=%d: quality %.4f" % (t, cap, quality))
+    return {"t": t, "N": cap, "tab": tab, "tuned": tuned, "work": work, "E": E, "clusters": ncl,
+            "graph_ms": graph_ms, "batched_ms": batched_ms, "plain_ms": plain_ms,
+            "knn_ms": knn_ms, "quality": quality}
+
+
+def roofline(leg, w):
+    """Achieved fp4-MFMA rate of the local-KNN kernel at the headline setting:
+    the dense 0/1 contraction's operations over the clusters that take the
+    MFMA path, per launch, over the kernel's mean event-timed duration."""
+    import numpy as np
+    work = leg["work"]
+    mfma_min = int(leg["tuned"].get("mfma_min_rows", MFMA_MIN_DEFAULT))
+    big = work["sizes"] >= mfma_min
+    ops = int((2 * work["sizes"][big].astype(np.int64) ** 2 * work["dict"][big]).sum())
+    achieved = ops / (leg["knn_ms"] * 1e-3)
+    tag = setting_tag(w, leg["t"], leg["N"])
+    traffic = profile_json(tag, "traffic")
+    busy = profile_json(tag, "mfma_busy")
+    return {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_FP4_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / MFMA_FP4_PEAK,
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "kernel": KNN_KERNEL, "setting": {"t": leg["t"], "N": leg["N"]},
+            "hw_mfma_busy_frac": busy["mfma_busy_frac"] if busy else None,
+            "ops_per_launch": ops, "kernel_ms": leg["knn_ms"],
+            "sparse_lower_bound_ops": int(work["sparse_pairs"]),
+            "ops_def": "sum over clusters with >= %d members of 2*s^2*D: the 0/1 product of the "
+                       "members' rows over the cluster's local dictionary (D = items held by >= "
+                       "2 members), computed on e2m1 (fp4) MFMA with fp32 accumulation, exact"
+                       % mfma_min}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle local-KNN work in the CPU baseline's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
-    ap.add_argument("--no-ablation", action="store_true",
-                    help="skip the MinHash-clustering (Table 4) and GoldFinger (Table 5) "
-                         "variants")
-    ap.add_argument("--learned", action="store_true",
-                    help="also train the learned cluster assigner on this workload and time the "
-                         "learned-assignment build beside the FastRandomHash forms")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the builds at the workload's own t and N when the headline "
+                         "setting differs from them")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training the learned cluster assigner and its builds")
     ap.add_argument("--learned-steps", type=int, default=1000)
-    ap.add_argument("--learned-t", type=int, default=0,
-                    help="heads (hash configurations) of the learned build (default: the workload's t)")
-    ap.add_argument("--learned-cap", type=int, default=0,
-                    help="split threshold N of the learned build (default: the workload's)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also run the MinHash-clustering (Table 4) and GoldFinger (Table 5) "
+                         "variants at the workload's own t and N")
     ap.add_argument("--sweep", action="store_true",
                     help="time-to-quality curve: plain builds over t and the split threshold N, "
                          "beside GPU brute force, and the fastest setting with quality >= 0.95")
@@ -437,83 +574,35 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2010_11497_amd import c2, metrics, synth
+    from paper_2010_11497_amd import autotune, c2, metrics, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = synth.WORKLOADS[args.workload]
     log("workload", w.name, "n=%d m=%d t=%d b=%d cap=%d k=%d" % (w.n, w.m, w.t, w.b, w.cap, w.k))
     P = synth.make_profiles(w)
-    tab = synth.hash_tables(w.t, w.hash_seed)
     dP = c2.DeviceProfiles.from_synth(P)
     h2d_ms = upload_ms(P, torch)
     log("CSR upload from pinned host memory: %.3f ms" % h2d_ms)
-    dtab = c2.tables_to_device(tab)
-    p = c2.params(w.t, w.b, w.cap, w.k)
     c2.validate(dP)
-
-    # partition statistics for the work counts (GPU clustering, read back)
-    bucket = c2.hash_items(dtab, w.b, w.m)
-    members, cl_off, cfg, _ = c2.cluster(dP, bucket, p, c2.FORM_PLAIN)
-    ncl = int(c2.to_u32(cfg)[-1])
-    work = metrics.cluster_work(c2.to_u32(members), c2.to_u32(cl_off)[: ncl + 1], P.indptr,
-                                P.indices, P.m)
-    E = work["pairs"]
-    log("clusters %d, Jaccard evals %d, max cluster %d" % (ncl, E, int(work["sizes"].max())))
-
-    # HIP-graph form of the batched build, with the autotuner's schedule if one
-    # was recorded for this workload
-    from paper_2010_11497_amd import autotune
-    tuned = autotune.load_table(w.name) or {}
-    log("tuning", tuned if tuned else "built-in defaults")
-    g = c2.Graph(dP, dtab, p, c2.tuning(**tuned))
-    for _ in range(args.warmup):
-        g.launch()
-    torch.cuda.synchronize()
-    g.check()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.launch()
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    log("graph build: %.3f ms/step" % graph_ms)
-    out_graph = [c2.to_u32(x) for x in g.out]
-
-    # batched (eager) and plain forms, same arithmetic
-    def timed(form):
-        ws = torch.empty_like(g.ws)
-        tu = c2.tuning(**tuned)
-        out = None
-        for _ in range(args.warmup):
-            out = c2.build(dP, dtab, p, form, tu, ws=ws, out=out)
+    bf = None
+    if not args.no_quality:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            out = c2.build(dP, dtab, p, form, tu, ws=ws, out=out)
+        bf = c2.brute_force(dP, w.k)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / args.steps, [c2.to_u32(x) for x in out]
-    batched_ms, out_b = timed(c2.FORM_BATCHED)
-    plain_ms, out_p = timed(c2.FORM_PLAIN)
+        log("exact graph (GPU brute force): %.1f ms" % ((time.perf_counter() - t0) * 1e3))
 
-    # dominant kernel: HIP events that the library records on its stream right
-    # before and after the pairwise local-KNN kernel, over K batched builds
-    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    ws = torch.empty_like(g.ws)
-    tu = c2.tuning(events=ev, **tuned)
-    out = None
-    knn = []
-    for _ in range(args.steps):
-        out = c2.build(dP, dtab, p, c2.FORM_BATCHED, tu, ws=ws, out=out)
-        ev[1].synchronize()
-        knn.append(ev[0].elapsed_time(ev[1]))
-    knn_ms = sum(knn) / len(knn)
-    log("local-KNN kernel: %.3f ms (events, avg of %d batched builds)" % (knn_ms, len(knn)))
-    log("batched eager: %.3f ms, plain: %.3f ms" % (batched_ms, plain_ms))
-    same = all(np.array_equal(a, b) for a, b in zip(out_graph, out_b)) and \
-        all(np.array_equal(a, b) for a, b in zip(out_graph, out_p))
-    if not same:
-        raise SystemExit("forms disagree: graph, batched and plain builds differ")
+    setting = autotune.quality_setting(w.name)
+    tq, Nq = setting["frh"]
+    head = frh_leg(args, w, dP, tq, Nq, c2, metrics, synth, torch, np, bf, events=True)
+    context = None
+    if (tq, Nq) != (w.t, w.cap) and not args.no_context:
+        c = frh_leg(args, w, dP, w.t, w.cap, c2, metrics, synth, torch, np, bf, events=False)
+        context = {"t": w.t, "N": w.cap, "quality": c["quality"], "jaccard_evals": c["E"],
+                   "build_ms": {"graph": c["graph_ms"], "batched": c["batched_ms"],
+                                "plain": c["plain_ms"]},
+                   "evals_per_s": c["E"] / (c["graph_ms"] * 1e-3)}
 
     if args.calibrate_copy_mb:
         src = torch.empty(args.calibrate_copy_mb << 20, dtype=torch.uint8, device="cuda")
@@ -522,69 +611,61 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: %d MiB x 3" % args.calibrate_copy_mb)
-
-    quality = None
-    if not args.no_quality:
-        bf = c2.brute_force(dP, w.k)
-        torch.cuda.synchronize()
-        quality = metrics.quality(out_graph[1], out_graph[2], c2.to_u32(bf[1]), c2.to_u32(bf[2]))
-        log("quality %.4f" % quality)
+        del src, dst
 
     learned_leg = None
-    if args.learned:
-        learned_leg = learned_variant(args, w, P, dP, dtab, p, c2, metrics, torch, np,
-                                      bf if quality is not None else None, plain_ms, batched_ms)
+    if not args.no_learned:
+        T, Nl = setting["learned"]
+        learned_leg = learned_variant(args, w, P, dP, T, Nl, c2, metrics, synth, torch, np, bf)
     sweep_leg = None
-    if args.sweep and quality is not None:
+    if args.sweep and bf is not None:
         sweep_leg = time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf,
                                     tuple(int(x) for x in args.sweep_t.split(",")),
                                     tuple(int(x) for x in args.sweep_n.split(",")))
     hyrec_leg = None
     if args.hyrec:
-        hyrec_leg = hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np,
-                                  bf if quality is not None else None)
+        dtab = c2.tables_to_device(synth.hash_tables(w.t, w.hash_seed))
+        hyrec_leg = hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np, bf)
     ablation = gold = None
-    if not args.no_ablation:
-        ablation = minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np,
-                                    bf if quality is not None else None)
-        gold = goldfinger_variant(args, w, P, dP, c2, metrics, synth, torch, np,
-                                  bf if quality is not None else None)
+    if args.ablation:
+        ablation = minhash_ablation(args, w, P, dP, c2, metrics, synth, torch, np, bf)
+        gold = goldfinger_variant(args, w, P, dP, c2, metrics, synth, torch, np, bf)
 
-    mfma_min = int(tuned.get("mfma_min_rows", MFMA_MIN_DEFAULT))
-    big = work["sizes"] >= mfma_min
-    ops = int((2 * work["sizes"][big].astype(np.int64) ** 2 * work["dict"][big]).sum())
-    achieved = ops / (knn_ms * 1e-3)
-    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_FP4_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / MFMA_FP4_PEAK,
-            "traffic": traffic_from_profiles(w.name), "kernel": KNN_KERNEL,
-            "hw_mfma_busy_frac": mfma_busy_from_profiles(w.name),
-            "ops_per_launch": ops,
-            "sparse_lower_bound_ops": int(work["sparse_pairs"]),
-            "ops_def": "sum over clusters with >= %d members of 2*s^2*D: the 0/1 product of the "
-                       "members' rows over the cluster's local dictionary (D = items held by >= "
-                       "2 members), computed on e2m1 (fp4) MFMA with fp32 accumulation, exact"
-                       % mfma_min}
-
+    E, graph_ms = head["E"], head["graph_ms"]
+    build_ms = {"graph": graph_ms, "batched": head["batched_ms"], "plain": head["plain_ms"]}
+    quality = {"frh": head["quality"]}
+    if learned_leg and learned_leg.get("at_bar"):
+        ab = learned_leg["at_bar"]
+        build_ms.update({"learned_graph": ab["graph"], "learned_batched": ab["batched"],
+                         "learned_plain": ab["plain"]})
+        quality["learned"] = ab["quality"]
     line = {
         "metric": METRIC, "value": E / (graph_ms * 1e-3), "unit": "Jaccard evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": graph_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp4",
         "data": "synthetic: seeded lognormal profile sizes, Zipf item popularity",
-        "config": {"workload": w.name, "n": w.n, "m": w.m, "nnz": P.nnz, "t": w.t, "b": w.b,
-                   "cap": w.cap, "k": w.k, "form": "batched build replayed as a HIP graph",
-                   "tuning": tuned or "defaults"},
-        "build_ms": {"graph": graph_ms, "batched": batched_ms, "plain": plain_ms},
-        "quality": quality, "jaccard_evals": E, "clusters": ncl,
+        "config": {"workload": w.name, "n": w.n, "m": w.m, "nnz": P.nnz, "t": tq, "N": Nq,
+                   "b": w.b, "k": w.k, "form": "batched build replayed as a HIP graph",
+                   "setting": "fastest (t, N) reaching quality >= %.2f in the time-to-quality "
+                              "sweep (the workload's own t=%d, N=%d reported under "
+                              "at_workload_t)" % (QUALITY_BAR, w.t, w.cap),
+                   "learned_setting": {"heads": setting["learned"][0],
+                                       "N": setting["learned"][1]},
+                   "tuning": head["tuned"] or "defaults"},
+        "build_ms": build_ms, "quality": quality,
+        "jaccard_evals": E, "clusters": head["clusters"],
         "evals_vs_brute_force": E / (P.n * (P.n - 1) / 2),
-        "minhash_ablation": ablation, "goldfinger": gold, "learned": learned_leg, "hyrec": hyrec_leg, "time_to_quality": sweep_leg,
+        "at_workload_t": context,
+        "learned": learned_leg, "time_to_quality": sweep_leg, "hyrec": hyrec_leg,
+        "minhash_ablation": ablation, "goldfinger": gold,
         "h2d_csr_ms": h2d_ms, "evals_per_s_incl_h2d": E / ((graph_ms + h2d_ms) * 1e-3),
-        "local_knn_ms": knn_ms, "local_knn_evals_per_s": E / (knn_ms * 1e-3),
-        "roofline": roof,
+        "local_knn_ms": head["knn_ms"], "local_knn_evals_per_s": E / (head["knn_ms"] * 1e-3),
+        "roofline": roofline(head, w),
     }
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(P, tab, w, E, args.cpu_budget)
+        cb = cpu_baseline(P, head["tab"], w, Nq, E, args.cpu_budget)
         line["cpu_baseline"] = cb
-        log("cpu oracle: %.3g evals/s on %d threads" % (cb["value"], cb["cores"]))
+        log("cpu oracle: %.3g evals/s on %d threads (%s)" % (cb["value"], cb["cores"], cb["sample"]))
     print(json.dumps(line), flush=True)
 
 

@@ -104,3 +104,58 @@ def edge_jaccard(indptr: np.ndarray, indices: np.ndarray, m: int, knn_id: np.nda
         I[e] = inter
         U[e] = lens[u[e]] + lens[v[e]] - inter
     return I.reshape(shape), U.reshape(shape)
+
+
+def cluster_work_torch(members, cl_off, cl_cfg_off, indptr, indices, m: int,
+                       max_entries: int = 1 << 26) -> dict:
+    """cluster_work on torch tensors (any device) for partitions too large for
+    its dense count table.  The (cluster, item) entries of one hash
+    configuration's clusters are taken in pieces of about max_entries, sorted
+    as keys cluster*m + item and counted by runs: a run of length f is an item
+    held by f members of that cluster."""
+    import torch
+    dev = members.device
+    off = cl_off.to(torch.int64)
+    s = off[1:] - off[:-1]
+    ip = indptr.to(torch.int64)
+    lens = ip[1:] - ip[:-1]
+    mem = members.to(torch.int64)[: int(off[-1])]
+    ix = indices.to(torch.int64)
+    cs = torch.cat([torch.zeros(1, dtype=torch.int64, device=dev), torch.cumsum(lens[mem], 0)])
+    ent = (cs[off[1:]] - cs[off[:-1]]).cpu().numpy()
+    cfg = [int(x) for x in cl_cfg_off]
+    bounds = []
+    for j in range(len(cfg) - 1):
+        e = ent[cfg[j]:cfg[j + 1]]
+        if len(e) == 0:
+            continue
+        piece = (np.cumsum(e) - 1) // max_entries
+        cut = np.nonzero(np.diff(piece))[0] + 1
+        edges = [0] + cut.tolist() + [len(e)]
+        bounds += [(cfg[j] + a, cfg[j] + b) for a, b in zip(edges[:-1], edges[1:])]
+    D = torch.zeros(len(s), dtype=torch.int64, device=dev)
+    sparse = 0
+    for c0, c1 in bounds:
+        users = mem[int(off[c0]):int(off[c1])]
+        reps = lens[users]
+        cl = torch.repeat_interleave(torch.arange(c0, c1, device=dev), s[c0:c1])
+        cl = torch.repeat_interleave(cl, reps)
+        starts = torch.repeat_interleave(ip[users], reps)
+        within = torch.arange(int(reps.sum()), device=dev) - torch.repeat_interleave(
+            torch.cumsum(reps, 0) - reps, reps)
+        keys, _ = torch.sort(cl * m + ix[starts + within])
+        run, f = torch.unique_consecutive(keys, return_counts=True)
+        D += torch.bincount(run[f >= 2] // m, minlength=len(s))
+        sparse += int((f * (f - 1) // 2).sum())
+    D[s < 2] = 0
+    s2 = s * s
+    return {
+        "clusters": int(len(s)),
+        "pairs": int((s * (s - 1) // 2).sum()),
+        "ordered": int(s2.sum()),
+        "bitmap_ops": int((2 * s2 * ((D + 31) // 32)).sum()),
+        "dense_ops": int((2 * s2 * D).sum()),
+        "sparse_pairs": sparse,
+        "sizes": s.cpu().numpy(),
+        "dict": D.cpu().numpy(),
+    }

@@ -7,6 +7,7 @@ is part of the contract (ascending hash values, sub-clusters before the users
 that stay), so partitions are compared as raw arrays, and also as sets so a
 failure says whether only the order differs.
 """
+import functools
 import json
 import os
 import sys
@@ -324,35 +325,66 @@ def test_workload_full_parity(orc, name):
         assert np.array_equal(u32(g)[rows], ww)
 
 
-def test_workload_sampled_parity_n70k(orc):
-    # 70,000 users: the whole partition against the oracle's, and the graph
-    # on sampled users against the definition (top-k over the users that
-    # share a final cluster), both from the graph form the benchmark times
+@functools.lru_cache(maxsize=2)
+def workload_profiles(name):
+    """The named workload's profiles, generated once per session (the 500,000
+    user workload takes tens of seconds to draw)."""
+    return synth.make_profiles(synth.WORKLOADS[name])
+
+
+def tuned_graph(dP, dtab, p, name, t, cap):
+    """The launch configuration the benchmark times: the batched build captured
+    as a graph with the autotuner's schedule for this workload and setting."""
     from paper_2010_11497_amd import autotune
-    name = "n70k_m10k"
-    w = synth.WORKLOADS[name]
-    say("workload sampled", name)
-    P = synth.make_profiles(w)
-    tab = synth.hash_tables(w.t, w.hash_seed)
-    dP, dtab = gpu_inputs(P, tab)
-    p = c2.params(w.t, w.b, w.cap, w.k)
-    bucket = orc.hash_items(tab, w.b, w.m)
-    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, w.cap)
-    gm, goff, gcfg, _ = c2.cluster(dP, c2.hash_items(dtab, w.b, w.m), p, c2.FORM_PLAIN)
+    return c2.Graph(dP, dtab, p, c2.tuning(**(autotune.load_table(name, t, cap) or {})))
+
+
+def gpu_partition(dP, bucket, p, form):
+    members, cl_off, cfg, ws = c2.cluster(dP, bucket, p, form, c2.tuning(split_rounds=64))
+    if form == c2.FORM_BATCHED:
+        c2.check_complete(ws)
+    return members, cl_off, cfg
+
+
+def assert_same_partition(got, want):
+    gm, goff, gcfg = got
+    om, ooff, ocfg = want
     gcfg = u32(gcfg)
     assert np.array_equal(gcfg, ocfg)
     assert np.array_equal(u32(goff)[: gcfg[-1] + 1], ooff)
     assert np.array_equal(u32(gm), om)
-    g = c2.Graph(dP, dtab, p, c2.tuning(**(autotune.load_table(name) or {})))
-    out = [u32(x) for x in g.launch()]
-    torch.cuda.synchronize()
-    g.check()
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("name", ["n70k_m10k", "n140k_m27k", "n500k_m50k"])
+def test_workload_whole_graph(orc, name):
+    """The three large workloads at their own t and N: the whole partition in
+    both forms and the whole graph (knn_id, knn_I, knn_U of every user) from the
+    tuned graph form on two replays and from the plain form, against the
+    oracle's complete build."""
+    w = synth.WORKLOADS[name]
+    say("workload whole graph", name)
+    P = workload_profiles(name)
+    tab = synth.hash_tables(w.t, w.hash_seed)
+    dP, dtab = gpu_inputs(P, tab)
+    p = c2.params(w.t, w.b, w.cap, w.k)
+    r = orc.build_graph(P.indptr, P.indices, P.n, P.m, tab, w.b, w.cap, w.k, THREADS)
+    say("oracle build done", name)
+    bucket = c2.hash_items(dtab, w.b, w.m)
+    for form in (c2.FORM_PLAIN, c2.FORM_BATCHED):
+        assert_same_partition(gpu_partition(dP, bucket, p, form),
+                              (r.members, r.cl_off, r.cl_cfg_off))
+    want = (r.knn_id, r.knn_I, r.knn_U)
+    g = tuned_graph(dP, dtab, p, name, w.t, w.cap)
+    for _ in range(2):
+        out = g.launch()
+        torch.cuda.synchronize()
+        g.check()
+        for a, ww in zip(out, want):
+            assert np.array_equal(u32(a), ww)
     g.close()
-    rows = np.random.Generator(np.random.PCG64(7)).choice(P.n, size=300, replace=False)
-    want = orc.candidate_topk(P.indptr, P.indices, P.n, P.m, w.t, w.k, om, ooff, ocfg,
-                              rows=rows, threads=THREADS)
-    for a, ww in zip(out, want):
-        assert np.array_equal(a[rows], ww)
+    for a, ww in zip(c2.build(dP, dtab, p, c2.FORM_PLAIN), want):
+        assert np.array_equal(u32(a), ww)
 
 
 def test_long_profiles_take_exact_fallback(orc):
@@ -463,7 +495,7 @@ def test_brute_force_sampled_large(orc, name):
     workloads: 200 seeded rows against the oracle's brute force over all n."""
     w = synth.WORKLOADS[name]
     say("brute force sampled", name)
-    P = synth.make_profiles(w)
+    P = workload_profiles(name)
     dP = c2.DeviceProfiles.from_synth(P)
     bf = c2.brute_force(dP, w.k)
     torch.cuda.synchronize()
@@ -515,40 +547,52 @@ def _blocks_partition(n, t, size, seed):
             np.asarray(cfg, np.uint32))
 
 
-def _store_words(P, om, ooff):
-    """Words of dictionary rows the partition needs: rows padded to 32 (or s
-    below 32), 8 words per 256 dictionary items (at least 8)."""
+def _store_words(P, om, ooff, k=10, group_tiles=16):
+    """Words of store the partition needs: first the scratch of split row
+    blocks (clusters of the 64 x 128 shape spanning more than group_tiles
+    column tiles: ceil(s/64) row blocks times min(4, ceil(tiles/group_tiles))
+    column groups, a slot of 64 rows x k u64 keys each; rounded up to 64
+    words), then the dictionary rows: rows padded to 32 (or s below 32), 8
+    words per 256 dictionary items (at least 8)."""
     ip = np.asarray(P.indptr)
-    need = 0
+    need, slots = 0, 0
     for c in range(len(ooff) - 1):
         mem = om[ooff[c]:ooff[c + 1]]
         if len(mem) < 2:
             continue
+        s = len(mem)
+        tiles = (s + 127) // 128
+        if s > 64 and tiles > group_tiles:
+            slots += (s + 63) // 64 * min(4, (tiles + group_tiles - 1) // group_tiles)
         items = np.concatenate([P.indices[ip[u]:ip[u + 1]] for u in mem])
         D = int((np.bincount(items, minlength=P.m) >= 2).sum())
-        rows = len(mem) if len(mem) < 32 else (len(mem) + 31) // 32 * 32
+        rows = s if s < 32 else (s + 31) // 32 * 32
         need += rows * 8 * max(1, (D + 255) // 256)
-    return need
+    return (slots * 64 * k * 2 + 63) // 64 * 64 + need
 
 
+@pytest.mark.parametrize("group_tiles", [0, 2])
 @pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
-def test_local_knn_store_sizes(orc, form):
+def test_local_knn_store_sizes(orc, form, group_tiles):
     """The store takes whatever workspace the caller passes beyond the fixed
-    part: exactly the partition's dictionary rows suffice and give the
-    oracle's lists; one 256-word row block less is reported (plain form:
-    C2_E_WORKSPACE from the call; batched form: from c2_check_complete)."""
+    part: exactly the partition's scratch and dictionary rows suffice and give
+    the oracle's lists; one 256-word row block less is reported (plain form:
+    C2_E_WORKSPACE from the call; batched form: from c2_check_complete).  With
+    group_tiles 2 the 400-member clusters split their row blocks in two column
+    groups, whose scratch takes the front of the store."""
     n, m, t, k, size = 3000, 16384, 2, 10, 400
     P = synth.random_profiles(77, n, m, 70, 95)
     om, ooff, ocfg = _blocks_partition(n, t, size, 78)
-    need = _store_words(P, om, ooff)
-    say("local_knn store sizes", form, need)
+    need = _store_words(P, om, ooff, k, group_tiles or 16)
+    tune = c2.tuning(group_tiles=group_tiles)
+    say("local_knn store sizes", form, group_tiles, need)
     dP = c2.DeviceProfiles.from_synth(P)
     dev = lambda a: torch.as_tensor(a.astype(np.uint32).view(np.int32)).cuda()
     p = c2.params(t, 64, size, k)
     fixed = c2.workspace_bytes(dP, p, c2.OP_LOCAL_KNN_MIN) - 4096
     wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
     ws = torch.empty(fixed + 4 * need, dtype=torch.uint8, device="cuda")
-    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, ws=ws)
+    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, tune, ws=ws)
     if form == c2.FORM_BATCHED:
         c2.check_complete(ws)
     assert np.array_equal(u32(pid), wid)
@@ -556,13 +600,42 @@ def test_local_knn_store_sizes(orc, form):
     assert c2.store_need_bytes(ws) == 4 * need
     small = torch.empty(fixed + 4 * (need - 256), dtype=torch.uint8, device="cuda")
     with pytest.raises(c2.C2Error) as e:
-        c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, ws=small)
+        c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, tune, ws=small)
         c2.check_complete(small)
     assert e.value.status == -3
     assert c2.store_need_bytes(small) == 4 * need
     # the binding grows a workspace it allocated itself and runs again
-    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, c2.FORM_PLAIN)
+    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, c2.FORM_PLAIN, tune)
     assert np.array_equal(u32(pid), wid)
+
+
+@pytest.mark.parametrize("form", [c2.FORM_PLAIN, c2.FORM_BATCHED])
+def test_local_knn_clusters_of_thousands(orc, form):
+    """Clusters of 8000, 6200 and 4100 members at the default schedule: their
+    row blocks split into 4, 4 and 3 column groups whose lists the last group
+    to finish merges from the scratch at the front of the store (the learned
+    assigner's N = 8000 reaches such clusters); against the oracle's lists."""
+    n, m, k = 18300, 4000, 30
+    P = synth.random_profiles(79, n, m, 5, 40, 1.0)
+    rng = np.random.Generator(np.random.PCG64(80))
+    perm = rng.permutation(n)
+    cuts = [0, 8000, 14200, 18300]
+    om = np.concatenate([np.sort(perm[a:b]) for a, b in zip(cuts[:-1], cuts[1:])]).astype(np.uint32)
+    ooff = np.asarray(cuts, np.uint32)
+    ocfg = np.asarray([0, 3], np.uint32)
+    say("local_knn clusters of thousands", form)
+    dP = c2.DeviceProfiles.from_synth(P)
+    dev = lambda a: torch.as_tensor(a.view(np.int32)).cuda()
+    p = c2.params(1, 64, 8000, k)
+    # sized by a plain run (the default store is smaller than these clusters need)
+    ws = c2.local_knn_workspace(dP, dev(om), dev(ooff), dev(ocfg), p)
+    assert ws.numel() > c2.workspace_bytes(dP, p, c2.OP_LOCAL_KNN)
+    pid, pI = c2.local_knn(dP, dev(om), dev(ooff), dev(ocfg), p, form, ws=ws)
+    if form == c2.FORM_BATCHED:
+        c2.check_complete(ws)
+    wid, wI = orc.local_knn(P.indptr, P.indices, P.n, P.m, 1, k, om, ooff, ocfg, THREADS)
+    assert np.array_equal(u32(pid), wid)
+    assert np.array_equal(u32(pI), wI)
 
 
 @pytest.mark.parametrize("m", [200000, 1 << 19])
@@ -616,29 +689,32 @@ def test_tile_shapes_agree_n6k():
             assert torch.equal(a, b2)
 
 
-@pytest.mark.parametrize("name", ["n140k_m27k", "n500k_m50k"])
-def test_workload_sampled_parity_large(orc, name):
-    """140,000 users over 27,000 items and 500,000 over 50,000 (rows of 848 and
-    1568 words: the dictionaries are on by default, and at 500,000 users the
-    compacted-row store is at its largest): the graph form with the tuned
-    schedule on sampled users against the definition (top-k over the users
-    sharing a final cluster)."""
-    from paper_2010_11497_amd import autotune
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("name,t,cap", [("n140k_m27k", 32, 4000), ("n500k_m50k", 32, 4000)])
+def test_workload_quality_setting(orc, name, t, cap):
+    """The large workloads at the setting the benchmark reports at quality 0.95
+    (32 hash configurations, N = 4000): the whole partition in both forms
+    against the oracle's, and the tuned graph form's graph on sampled users
+    against the definition (top-k over the users sharing a final cluster).
+    The oracle's whole graph would take several minutes here."""
     w = synth.WORKLOADS[name]
-    say("workload sampled", name)
-    P = synth.make_profiles(w)
-    tab = synth.hash_tables(w.t, w.hash_seed)
+    say("workload quality setting", name, t, cap)
+    P = workload_profiles(name)
+    tab = synth.hash_tables(t, w.hash_seed)
     dP, dtab = gpu_inputs(P, tab)
-    p = c2.params(w.t, w.b, w.cap, w.k)
-    bucket = orc.hash_items(tab, w.b, w.m)
-    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, w.cap)
-    g = c2.Graph(dP, dtab, p, c2.tuning(**(autotune.load_table(name) or {})))
+    p = c2.params(t, w.b, cap, w.k)
+    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, orc.hash_items(tab, w.b, w.m),
+                                    cap)
+    bucket = c2.hash_items(dtab, w.b, w.m)
+    for form in (c2.FORM_PLAIN, c2.FORM_BATCHED):
+        assert_same_partition(gpu_partition(dP, bucket, p, form), (om, ooff, ocfg))
+    g = tuned_graph(dP, dtab, p, name, t, cap)
     out = [u32(x) for x in g.launch()]
     torch.cuda.synchronize()
     g.check()
     g.close()
     rows = np.random.Generator(np.random.PCG64(8)).choice(P.n, size=200, replace=False)
-    want = orc.candidate_topk(P.indptr, P.indices, P.n, P.m, w.t, w.k, om, ooff, ocfg,
+    want = orc.candidate_topk(P.indptr, P.indices, P.n, P.m, t, w.k, om, ooff, ocfg,
                               rows=rows, threads=THREADS)
     for a, ww in zip(out, want):
         assert np.array_equal(a[rows], ww)

@@ -648,6 +648,26 @@ def test_cluster_work_sparse_pairs_identity(orc):
                                 (mem[off[c]:off[c + 1]] for c in range(len(off) - 1)))
 
 
+
+def test_cluster_work_torch_equals_dense_count(orc):
+    """The run-counting form (pieces of a few thousand entries, so that clusters
+    are cut into several pieces per configuration) gives the dense count
+    table's dictionary sizes and sums."""
+    import torch
+    from paper_2010_11497_amd import metrics
+    P = synth.random_profiles(62, 500, 120, 1, 30, 1.0)
+    bucket = orc.hash_items(synth.hash_tables(4, 63), 8, P.m)
+    mem, off, cfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, 60)
+    ref = metrics.cluster_work(mem, off, P.indptr, P.indices, P.m)
+    got = metrics.cluster_work_torch(torch.from_numpy(mem.astype(np.int64)),
+                                     torch.from_numpy(off.astype(np.int64)), cfg,
+                                     torch.from_numpy(P.indptr),
+                                     torch.from_numpy(P.indices.astype(np.int64)), P.m,
+                                     max_entries=700)
+    for key in ("clusters", "pairs", "ordered", "bitmap_ops", "dense_ops", "sparse_pairs"):
+        assert got[key] == ref[key], key
+    assert np.array_equal(got["sizes"], ref["sizes"]) and np.array_equal(got["dict"], ref["dict"])
+
 # ------------------------------------------------- Eq. 1 and Eq. 2 by hand --
 
 # A graph of 4 users with k = 3.  User 0 keeps an edge with I = 0, user 1 an
