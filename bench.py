@@ -104,11 +104,14 @@ def cpu_baseline(P, tab, w, cap, E, budget_s):
                          sub_off.astype(np.uint32), sub_cfg, threads)
         return pairs, time.perf_counter() - t1
 
-    # a small probe for the rate, then the sample sized to the budget
+    # a small probe for the rate, a sample of a third of the budget to
+    # measure it again (the probe's thread start-up weighs on it), then the
+    # sample sized to the budget
     pairs, el = knn_sample(max(1, int(E_orc // 2e7)))
-    rate = pairs / max(el, 1e-6)
-    stride = max(1, int(math.ceil(E_orc / max(rate * budget_s * 0.7, 1.0))))
-    pairs, el = knn_sample(stride)
+    for share in (1.0 / 3.0, 1.0):
+        rate = pairs / max(el, 1e-6)
+        stride = max(1, int(math.ceil(E_orc / max(rate * budget_s * share, 1.0))))
+        pairs, el = knn_sample(stride)
     t_knn = el * E_orc / max(pairs, 1)
     n_m = min(P.n, 20000)
     rng = np.random.Generator(np.random.PCG64(7))
@@ -470,6 +473,7 @@ def frh_leg(args, w, dP, t, cap, c2, metrics, synth, torch, np, bf, events):
     graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     g.check()                  # every timed replay ran enough split rounds
     out_graph = [c2.to_u32(x) for x in g.out]
+    ws_bytes, store_need = g.ws.numel(), c2.store_need_bytes(g.ws)
 
     def timed(form):
         ws = torch.empty_like(g.ws)
@@ -506,7 +510,8 @@ def frh_leg(args, w, dP, t, cap, c2, metrics, synth, torch, np, bf, events):
         log("t=%d N=%d: quality %.4f" % (t, cap, quality))
     return {"t": t, "N": cap, "tab": tab, "tuned": tuned, "work": work, "E": E, "clusters": ncl,
             "graph_ms": graph_ms, "batched_ms": batched_ms, "plain_ms": plain_ms,
-            "knn_ms": knn_ms, "quality": quality}
+            "knn_ms": knn_ms, "quality": quality,
+            "workspace": {"bytes": ws_bytes, "store_need_bytes": store_need}}
 
 
 def roofline(leg, w):
@@ -541,7 +546,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
-    ap.add_argument("--cpu-budget", type=float, default=12.0,
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle local-KNN work in the CPU baseline's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
@@ -653,7 +658,7 @@ def main():
                                        "N": setting["learned"][1]},
                    "tuning": head["tuned"] or "defaults"},
         "build_ms": build_ms, "quality": quality,
-        "jaccard_evals": E, "clusters": head["clusters"],
+        "jaccard_evals": E, "clusters": head["clusters"], "workspace": head["workspace"],
         "evals_vs_brute_force": E / (P.n * (P.n - 1) / 2),
         "at_workload_t": context,
         "learned": learned_leg, "time_to_quality": sweep_leg, "hyrec": hyrec_leg,

@@ -64,7 +64,7 @@ typedef int32_t c2_status;
 /* Limits of the library: n <= 2^31 - 1 users and t*n < 2^32, m <= 2^19 items
  * (two m-bit dictionary bitmaps per cluster live in the 160 KiB of LDS),
  * nnz < 2^40, every profile shorter than 2^20 items, 1 <= t <= 64,
- * 1 <= b <= 2^24, cap >= 1, 1 <= k <= 32. */
+ * 1 <= b <= 2^31, cap >= 1, 1 <= k <= 32. */
 
 /* Users and their profiles in CSR form (Section II-A: U, I and P_u).
  * Row u is indices[indptr[u] .. indptr[u+1]): strictly increasing item ids

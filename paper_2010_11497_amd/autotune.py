@@ -36,7 +36,7 @@ GRID = {
 # heads and N (each head count trained once).  Workloads not listed reach the
 # bar at their own t and N.
 QUALITY_SETTINGS = {
-    "n500k_m50k": {"frh": (32, 4000), "learned": (16, 8000)},
+    "n500k_m50k": {"frh": (32, 4000), "learned": (20, 6000)},
 }
 
 

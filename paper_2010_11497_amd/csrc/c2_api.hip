@@ -49,7 +49,7 @@ c2_status check_sizes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *p, 
     if (!need_p) return C2_OK;
     if (!p) return fail(C2_E_ARG, "params is NULL");
     if (p->t < 1 || p->t > 64) return fail(C2_E_ARG, "t = %u out of range [1, 64]", p->t);
-    if (p->b < 1 || p->b > (1u << 24)) return fail(C2_E_ARG, "b = %u out of range [1, 2^24]", p->b);
+    if (p->b < 1 || p->b > (1u << 31)) return fail(C2_E_ARG, "b = %u out of range [1, 2^31]", p->b);
     if (p->cap < 1) return fail(C2_E_ARG, "cap must be >= 1");
     if (p->k < 1 || p->k > kMaxK) return fail(C2_E_ARG, "k = %u out of range [1, %u]", p->k, kMaxK);
     if ((uint64_t)p->t * n >= 0xFFFFFFFFull) return fail(C2_E_UNSUPPORTED, "t*n >= 2^32");

@@ -1173,7 +1173,8 @@ void k_knn_mfma(KnnArgs a, StoreView sv, const uint32_t *ulen, MfmaScratch sc,
 
 // ---------------------------------------------------------------- planning
 
-// Tile shape code of a cluster of s members: 0 (32-row tiles), 1 (64) or 2 (128).
+// Tile shape code of a cluster of s members: 0 (32 x 32 tiles), 1 (64 x 64) or
+// 2 (64 rows x 128 columns).
 C2_DEV uint32_t tile_code(uint32_t s, uint32_t t32, uint32_t t64) {
     return s <= t32 ? 0u : s <= t64 ? 1u : 2u;
 }

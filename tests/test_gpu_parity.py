@@ -223,6 +223,31 @@ def test_build(orc, name, P, tab, b, cap, k, form, path):
         assert np.array_equal(u32(g), w)
 
 
+@pytest.mark.parametrize("b", [(1 << 31) - 1, 1 << 31, 3 << 29])
+def test_build_wide_bucket_range(orc, b):
+    """Bucket counts up to 2^31: hashing, the partition (the split's 64-bit
+    sort keys then hold a 32-bit value field) and the whole build in both
+    forms against the oracle."""
+    say("wide bucket range", b)
+    P = synth.random_profiles(81, 3000, 2000, 1, 40, 1.0)
+    t, cap, k = 4, 100, 10
+    tab = synth.hash_tables(t, 82)
+    dP, dtab = gpu_inputs(P, tab)
+    bucket = orc.hash_items(tab, b, P.m)
+    assert int(bucket.max()) >= 1 << 24                 # values past the former limit
+    assert np.array_equal(u32(c2.hash_items(dtab, b, P.m)), bucket)
+    p = c2.params(t, b, cap, k)
+    om, ooff, ocfg, _ = orc.cluster(P.indptr, P.indices, P.n, P.m, bucket, cap)
+    for form in (c2.FORM_PLAIN, c2.FORM_BATCHED):
+        assert_same_partition(gpu_partition(dP, c2.hash_items(dtab, b, P.m), p, form),
+                              (om, ooff, ocfg))
+    r = orc.build_graph(P.indptr, P.indices, P.n, P.m, tab, b, cap, k, THREADS)
+    for form in (c2.FORM_PLAIN, c2.FORM_BATCHED):
+        for g, want in zip(c2.build(dP, dtab, p, form, c2.tuning(split_rounds=64)),
+                           (r.knn_id, r.knn_I, r.knn_U)):
+            assert np.array_equal(u32(g), want)
+
+
 def test_brute_force(orc):
     for seed, (n, m, k) in enumerate([(300, 100, 5), (700, 3000, 32), (65, 20, 64 // 2), (2, 3, 4),
                                       (1000, 130, 17), (129, 64, 8)]):
