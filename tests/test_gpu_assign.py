@@ -282,28 +282,48 @@ def test_learned_pipeline_exact_weights(A, orc, min_gap):
             assert np.array_equal(c2.to_u32(g), ww)
 
 
-def test_learned_build_graph_replays_equal_eager():
+def test_learned_build_graph_replays_equal_eager(A, orc):
     """The batched learned build (keys, clustering from keys, local KNN,
     merge) captured once in a graph: several replays, with eager work and
-    synchronisations between them, each checked for the split-round status
-    and the local KNN's store and against the eager batched result; the
-    captured build takes the local-KNN workspace an eager run sized."""
+    synchronisations between them, each checked for the split rounds and the
+    local KNN's store, against the eager batched result and against the
+    oracle's pipeline on the oracle's own keys (weights whose forward is exact
+    in bf16/fp32, so every key is decided; about half the users take the
+    FastRandomHash fallback).  The captured build takes the local-KNN
+    workspace an eager run sized."""
     from paper_2010_11497_amd import learned
     say("learned graph replays")
     P = synth.random_profiles(123, 3000, 800, 5, 60, 1.0)
     dP = c2.DeviceProfiles.from_synth(P)
-    t, b, k = 4, 64, 10
-    tab = c2.tables_to_device(synth.hash_tables(t, 124))
-    p = c2.params(t, 32, 300, k)
+    t, b, k, bf, cap, gap = 4, 64, 10, 32, 300, 0.0625
+    htab = synth.hash_tables(t, 124)
+    tab = c2.tables_to_device(htab)
+    p = c2.params(t, bf, cap, k)
     Asg = learned.Assigner(P.m, t, b, seed=5)
-    W = Asg.inference_weights()
+    E, W1, b1, W2, b2 = synth.assigner_exact_weights(P.m, t, b, 125)
+    W = (bf16_dev(E), bf16_dev(W1), torch.from_numpy(b1).cuda(), bf16_dev(W2),
+         torch.from_numpy(b2).cuda())
+    # the oracle's graph from its own keys
+    _, hw = A.hidden(P.indptr, P.indices, A.from_bf16_bits(E), A.from_bf16_bits(W1),
+                     b1.astype(np.float64))
+    wkey, wgap, _ = A.keys(hw, A.from_bf16_bits(W2), b2.astype(np.float64), t, b)
+    fbucket = orc.hash_items(htab, bf, P.m)
+    fall = wgap < np.float32(gap)
+    assert 0.2 < fall.mean() < 0.8
+    okeys = np.where(fall, b + orc.frh_keys(P.indptr, P.indices, P.n, P.m, fbucket),
+                     wkey).astype(np.uint32)
+    om, ooff, ocfg, _ = orc.cluster_keys(P.indptr, P.indices, P.n, P.m, okeys, fbucket, cap)
+    pid, pI = orc.local_knn(P.indptr, P.indices, P.n, P.m, t, k, om, ooff, ocfg, THREADS)
+    want = orc.merge(P.indptr, P.n, t, k, pid, pI)
     tb = c2.tuning(split_rounds=16)
-    ref, _, kws = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W,
+    ref, _, kws = learned.build(Asg, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W,
                                 with_ws=True)
     torch.cuda.synchronize()
+    for a, ww in zip(ref, want):
+        assert np.array_equal(c2.to_u32(a), ww)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, capture_error_mode="thread_local"):
-        gout, gws, gkws = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W,
+        gout, gws, gkws = learned.build(Asg, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W,
                                         check=False, with_ws=True, knn_ws=kws)
     assert gkws is kws
     for rep in range(4):
@@ -311,11 +331,11 @@ def test_learned_build_graph_replays_equal_eager():
         torch.cuda.synchronize()
         c2.check_complete(gws)
         c2.check_complete(gkws)
-        for a, b2 in zip(gout, ref):
-            assert torch.equal(a, b2), rep
+        for a, b2_ in zip(gout, ref):
+            assert torch.equal(a, b2_), rep
         # eager work between replays
-        again = learned.build(Asg, dP, tab, p, 0.3, c2.FORM_BATCHED, tb, weights=W)
+        again = learned.build(Asg, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W)
         torch.cuda.synchronize()
-        for a, b2 in zip(again, ref):
-            assert torch.equal(a, b2)
+        for a, b2_ in zip(again, ref):
+            assert torch.equal(a, b2_)
     del g
