@@ -315,7 +315,7 @@ def hyrec_variant(args, w, P, dP, dtab, c2, metrics, torch, np, bf, rho=5):
     return res
 
 
-def learned_graph(args, A, dP, tab, p, gap, W, ref, kws, c2, torch, learned):
+def learned_graph(args, A, dP, tab, p, gap, W, ref, kws, c2, torch, learned, sched):
     """The batched learned build captured once as a graph, with the fewest
     split rounds that complete and the local-KNN workspace kws sized on an
     eager run, and replayed: the time per replay, and whether every replay
@@ -327,13 +327,13 @@ def learned_graph(args, A, dP, tab, p, gap, W, ref, kws, c2, torch, learned):
         rounds = 64
         for r in (2, 4, 8, 16, 32):
             try:
-                learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, c2.tuning(split_rounds=r),
-                              weights=W, knn_ws=kws)
+                learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED,
+                              c2.tuning(split_rounds=r, **sched), weights=W, knn_ws=kws)
                 rounds = r
                 break
             except c2.C2Error:
                 continue
-        tb = c2.tuning(split_rounds=rounds)
+        tb = c2.tuning(split_rounds=rounds, **sched)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, capture_error_mode="thread_local"):
@@ -362,14 +362,15 @@ def learned_graph(args, A, dP, tab, p, gap, W, ref, kws, c2, torch, learned):
         return {"build_ms_graph": None, "graph_error": str(e)[:200]}
 
 
-def learned_variant(args, w, P, dP, T, cap, c2, metrics, synth, torch, np, bf):
+def learned_variant(args, w, P, dP, T, cap, c2, metrics, synth, torch, np, bf, sched):
     """The learned cluster assigner: trained here on exact KNN edges of a
     100,000-user subsample, then the learned-assignment build (assignment,
     clustering from keys with FastRandomHash splits, local KNN, merge) at T
     heads and split threshold N, timed in the plain and batched eager forms
     and as a graph replay, and scored against the exact graph.  min_gap 0
     takes every learned bucket; min_gap 0.5 sends users whose top two logits
-    are closer than that to their FastRandomHash bucket."""
+    are closer than that to their FastRandomHash bucket.  The local KNN runs
+    with `sched`, the tuned schedule fields of the FastRandomHash build."""
     from paper_2010_11497_amd import learned
     b = 8192 if w.n >= 100000 else w.b
     t0 = time.perf_counter()
@@ -383,20 +384,22 @@ def learned_variant(args, w, P, dP, T, cap, c2, metrics, synth, torch, np, bf):
     p = c2.params(T, w.b, cap, w.k)
     res = {"buckets": b, "heads": T, "N": cap, "train_s": train_s, "train_steps": st.steps,
            "train_pairs": st.pairs, "loss": [st.first_loss, st.last_loss], "min_gap": {}}
-    tb = c2.tuning(split_rounds=64)
+    tb = c2.tuning(split_rounds=64, **sched)
+    tp = c2.tuning(**sched) if sched else None
     for gap in (0.0, 0.5):
         entry = {}
         # the local-KNN workspace of the batched form, sized on one checked run
         _, _, kws = learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, tb, weights=W,
                                   with_ws=True)
-        ms, _ = time_loop(lambda o: learned.build(A, dP, tab, p, gap, c2.FORM_PLAIN, None,
+        ms, _ = time_loop(lambda o: learned.build(A, dP, tab, p, gap, c2.FORM_PLAIN, tp,
                                                   weights=W), args.warmup, args.steps, torch)
         entry["build_ms_plain"] = ms
         ms, out = time_loop(lambda o: learned.build(A, dP, tab, p, gap, c2.FORM_BATCHED, tb,
                                                     weights=W, knn_ws=kws),
                             args.warmup, args.steps, torch)
         entry["build_ms_batched"] = ms
-        entry.update(learned_graph(args, A, dP, tab, p, gap, W, out, kws, c2, torch, learned))
+        entry.update(learned_graph(args, A, dP, tab, p, gap, W, out, kws, c2, torch, learned,
+                                   sched))
         q = None
         if bf is not None:
             q = metrics.quality(c2.to_u32(out[1]), c2.to_u32(out[2]), c2.to_u32(bf[1]),
@@ -621,7 +624,8 @@ def main():
     learned_leg = None
     if not args.no_learned:
         T, Nl = setting["learned"]
-        learned_leg = learned_variant(args, w, P, dP, T, Nl, c2, metrics, synth, torch, np, bf)
+        learned_leg = learned_variant(args, w, P, dP, T, Nl, c2, metrics, synth, torch, np, bf,
+                                      head["tuned"])
     sweep_leg = None
     if args.sweep and bf is not None:
         sweep_leg = time_to_quality(args, w, P, dP, c2, metrics, synth, torch, np, bf,
