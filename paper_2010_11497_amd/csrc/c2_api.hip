@@ -184,6 +184,7 @@ KnnPtrs knn_ptrs(char *base, size_t bytes, const KnnWs &w, uint32_t *status) {
                     : reinterpret_cast<unsigned long long *>(base + w.ccur);
     k.dslot = u32(w.dslot);
     k.dmap = u32(w.dmap);
+    k.rlist = u64(w.rlist);
     k.store = u32(w.store);
     k.store_words = bytes > w.store ? (bytes - w.store) / 4 : 0;
     k.status = status;

@@ -113,7 +113,7 @@ struct KnnArgs {
 };
 struct KnnWs {  // byte offsets; the store takes the rest of the region
     size_t rlen, cnt, items_m, items_b, slots, sbase, rb_done, htmp, ctmp, ctr, bmax, pc,
-        ccls, cpos, cw, coff, ccur, dslot, dmap, store, total;
+        ccls, cpos, cw, coff, ccur, dslot, dmap, rlist, store, total;
 };
 struct KnnPtrs {
     uint32_t *rlen;
@@ -126,6 +126,7 @@ struct KnnPtrs {
     uint64_t *coff;                // first word of each cluster's rows in the store
     unsigned long long *ccur;      // allocation cursor of the store
     uint32_t *dslot, *dmap;        // dictionary maps of the clusters larger than kBigS
+    uint64_t *rlist;               // row work of those clusters (cluster, first 32-row unit, units)
     uint32_t *store;               // the rows of every cluster over its dictionary
     uint64_t store_words;          // capacity of the store
     uint32_t *status;              // set to 1 when the store is too small (caller's header word)

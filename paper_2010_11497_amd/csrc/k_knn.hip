@@ -235,10 +235,13 @@ struct StageArgs {
     uint64_t *coff;
     unsigned long long *ccur;  // allocation cursor (words)
     uint32_t *cnext;           // cluster cursor of k_dict
-    uint32_t *rnext;           // item cursor of k_rows
+    uint32_t *rnext;           // entry cursor of k_rows
     uint32_t *dslot;           // map slot of each big cluster
     uint32_t *dmap;            // [slot][2 * Wm]: twice, then pre
     uint32_t *dcur;            // map slot cursor
+    uint64_t *rlist;           // row work of the big clusters: c << 32 | first unit << 8 | units
+    uint32_t *rcount;          // entries of rlist
+    uint32_t row_units;        // 32-row units per entry (2..8)
     uint32_t *status;          // bit 0 set when the store overflows
 };
 
@@ -246,7 +249,7 @@ struct StageArgs {
 // bitmap item, in work-list order, costliest first in the batched form):
 // dictionary bitmaps `once` and `twice` over the items (LDS), numbering, a
 // region of the store, then the rows (clusters of at most kBigS members) or
-// the published maps (larger ones).
+// the published maps and the cluster's entries in the row list (larger ones).
 __global__ __launch_bounds__(kStageThreads) void k_dict(KnnArgs a, const uint64_t *__restrict__ items,
                                                         const uint32_t *n_items, StageArgs st) {
     constexpr uint32_t NT = kStageThreads, G16 = 16, NG = NT / G16;
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(kStageThreads) void k_dict(KnnArgs a, const uint64_
     const uint32_t tid = threadIdx.x;
     __shared__ uint32_t wsum[NT / 64 + 1];
     __shared__ unsigned long long sh_off;
-    __shared__ uint32_t sh_ok, sh_c, sh_slot;
+    __shared__ uint32_t sh_ok, sh_c, sh_slot, sh_rbase;
     const uint32_t total_items = *n_items;
     for (;;) {
         __syncthreads();
@@ -334,18 +337,25 @@ __global__ __launch_bounds__(kStageThreads) void k_dict(KnnArgs a, const uint64_
                 dm[w] = twice[w];
                 dm[Wm + w] = pre[w];
             }
+            const uint32_t nblk = (s + 31) / 32, ne = (nblk + st.row_units - 1) / st.row_units;
+            if (tid == 0) sh_rbase = atomicAdd(st.rcount, ne);
+            __syncthreads();
+            for (uint32_t e = tid; e < ne; e += NT) {
+                const uint32_t u0 = e * st.row_units;
+                const uint32_t nu = nblk - u0 < st.row_units ? nblk - u0 : st.row_units;
+                st.rlist[sh_rbase + e] = ((uint64_t)c << 32) | ((uint64_t)u0 << 8) | nu;
+            }
             continue;
         }
         write_rows<NT>(a, cv, 0, (s + 31) / 32, G, st.bits + sh_off, twice, pre, win);
     }
 }
 
-// Rows of the clusters larger than kBigS members: every block takes MFMA
-// items (first column group only, one row block each) of such clusters,
-// loads the cluster's maps into LDS (kept while consecutive items share the
-// cluster) and writes the row block's rows.
-__global__ __launch_bounds__(kStageThreads) void k_rows(KnnArgs a, const uint64_t *__restrict__ items,
-                                                        const uint32_t *n_items, StageArgs st) {
+// Rows of the clusters larger than kBigS members: every block takes entries
+// of the row list (runs of 32-row units of one cluster, which k_dict appended
+// when it published the cluster's maps), loads the cluster's maps into LDS
+// (kept while consecutive entries share the cluster) and writes the rows.
+__global__ __launch_bounds__(kStageThreads) void k_rows(KnnArgs a, StageArgs st) {
     constexpr uint32_t NT = kStageThreads;
     extern __shared__ uint32_t lds[];
     const uint32_t Wm = a.Wm;
@@ -353,29 +363,24 @@ __global__ __launch_bounds__(kStageThreads) void k_rows(KnnArgs a, const uint64_
     const uint32_t tid = threadIdx.x;
     __shared__ uint64_t sh_code;
     uint32_t loaded = 0xFFFFFFFFu;
-    const uint32_t total_items = *n_items;
     for (;;) {
         __syncthreads();
         if (tid == 0) {
             const uint32_t i = atomicAdd(st.rnext, 1u);
-            sh_code = i < total_items ? items[i] : ~0ull;
+            sh_code = i < *st.rcount ? st.rlist[i] : ~0ull;
         }
         __syncthreads();
         const uint64_t code = sh_code;
         if (code == ~0ull) break;
-        if (((uint32_t)code >> 4 & 3u) != 0) continue;  // one item per row block
         const uint32_t c = (uint32_t)(code >> 32);
         const ClusterView cv = view(a, c);
-        if (cv.s <= kBigS || st.cw[c] == 0) continue;
         if (c != loaded) {
             const uint32_t *dm = st.dmap + (size_t)st.dslot[c] * 2 * Wm;
             for (uint32_t w = tid; w < 2 * Wm; w += NT) lds[w] = dm[w];
             loaded = c;
             __syncthreads();
         }
-        const uint32_t nb = shape_rows((uint32_t)code >> 6 & 3u) / 32, rb = (uint32_t)code >> 8;
-        const uint32_t u0 = rb * nb, nblk = (cv.s + 31) / 32;
-        const uint32_t u1 = u0 + nb < nblk ? u0 + nb : nblk;
+        const uint32_t u0 = (uint32_t)code >> 8, u1 = u0 + ((uint32_t)code & 0xFFu);
         write_rows<NT>(a, cv, u0, u1, st.cw[c] / 8, st.bits + st.coff[c], twice, pre, win);
     }
 }
@@ -1418,6 +1423,9 @@ size_t knn_max_slots(uint32_t NE) { return (size_t)NE / 8 + 8; }
 
 // Map slots: clusters of more than kBigS members.
 static size_t knn_max_maps(uint32_t NE) { return (size_t)NE / (kBigS + 1) + 1; }
+// Entries of the row list: at least two 32-row units each, so at most
+// ceil(units / 2) <= s / 64 + 2 per cluster.
+static size_t knn_max_row_entries(uint32_t NE) { return (size_t)NE / 64 + 2 * knn_max_maps(NE) + 16; }
 
 size_t knn_ws_fixed(uint32_t n, uint32_t NE, uint32_t m, KnnWs *w) {
     size_t off = 0;
@@ -1447,6 +1455,7 @@ size_t knn_ws_fixed(uint32_t n, uint32_t NE, uint32_t m, KnnWs *w) {
     x.ccur = take(16);
     x.dslot = take(4 * (size_t)NE);
     x.dmap = take((size_t)4 * 2 * dict_words(m) * knn_max_maps(NE));
+    x.rlist = take(8 * knn_max_row_entries(NE));
     x.store = off;
     x.total = off;
     if (w) *w = x;
@@ -1494,7 +1503,7 @@ static hipError_t lens(const KnnArgs &a, const KnnPtrs &w, hipStream_t s) {
 
 static size_t stage_lds(uint32_t Wm) { return ((size_t)win_offset(Wm) + 32 * kWinStride) * 4; }
 
-static StageArgs stage_args(const KnnPtrs &w) {
+static StageArgs stage_args(const KnnArgs &a, const KnnPtrs &w) {
     StageArgs st;
     st.bits = w.store;
     st.cap = w.store_words;
@@ -1506,6 +1515,12 @@ static StageArgs stage_args(const KnnPtrs &w) {
     st.dslot = w.dslot;
     st.dmap = w.dmap;
     st.dcur = w.ctr + 6;
+    st.rlist = w.rlist;
+    st.rcount = w.ctr + 9;
+    // entries of 8 units (256 rows) when the partition gives every staging
+    // block many of them, down to one 64-row block on small inputs
+    const uint32_t per_block = (uint32_t)((uint64_t)a.NE / 32 / kStageGrid / 8);
+    st.row_units = per_block >= 8 ? 8u : per_block >= 4 ? 4u : 2u;
     st.status = w.status;
     return st;
 }
@@ -1532,22 +1547,19 @@ static hipError_t stage(const KnnArgs &a, const KnnPtrs &w, const uint32_t *nslo
     if ((e = hipFuncSetAttribute((const void *)k_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds)) != hipSuccess)
         return e;
-    // allocation cursor (u64, past the scratch) and the cluster / item / map cursors
+    // allocation cursor (u64, past the scratch); the cursors of k_dict (both
+    // lists), of k_rows, of the map slots and the row list's count (ctr 4..9)
     hipLaunchKernelGGL(k_store_init, dim3(1), dim3(64), 0, s, w.ccur, nslots, kRows * a.k * 2);
-    if ((e = launch_fill_u32(w.ctr + 4, 0, 3, s)) != hipSuccess) return e;
-    const StageArgs st = stage_args(w);
+    if ((e = launch_fill_u32(w.ctr + 4, 0, 6, s)) != hipSuccess) return e;
+    const StageArgs st = stage_args(a, w);
     hipLaunchKernelGGL(k_dict, dim3(kStageGrid), dim3(kStageThreads), lds, s, a, w.items_m, w.ctr, st);
-    hipLaunchKernelGGL(k_rows, dim3(kStageGrid), dim3(kStageThreads), lds, s, a, w.items_m, w.ctr, st);
     // clusters on the bitmap path
     StageArgs sb = st;
     sb.cnext = w.ctr + 7;
-    if ((e = launch_fill_u32(w.ctr + 7, 0, 1, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_dict, dim3(kStageGrid / 4), dim3(kStageThreads), lds, s, a, w.items_b,
                        w.ctr + 1, sb);
-    sb.rnext = w.ctr + 8;
-    if ((e = launch_fill_u32(w.ctr + 8, 0, 1, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows, dim3(kStageGrid / 4), dim3(kStageThreads), lds, s, a, w.items_b,
-                       w.ctr + 1, sb);
+    // the rows of the big clusters of both lists
+    hipLaunchKernelGGL(k_rows, dim3(kStageGrid), dim3(kStageThreads), lds, s, a, st);
     return hipGetLastError();
 }
 
