@@ -242,11 +242,14 @@ struct StageArgs {
     uint64_t *rlist;           // row work of the big clusters: c << 32 | first unit << 8 | units
     uint32_t *rcount;          // entries of rlist
     uint32_t row_units;        // 32-row units per entry (2..8)
+    uint32_t claim;            // work-list items a k_dict block claims at a time (1..64)
     uint32_t *status;          // bit 0 set when the store overflows
 };
 
 // One block per cluster of >= 2 members (taken at the cluster's first MFMA or
-// bitmap item, in work-list order, costliest first in the batched form):
+// bitmap item, in work-list order, costliest first in the batched form; a
+// block claims st.claim consecutive items at a time and takes the clusters
+// whose first items they hold, one after the other):
 // dictionary bitmaps `once` and `twice` over the items (LDS), numbering, a
 // region of the store, then the rows (clusters of at most kBigS members) or
 // the published maps and the cluster's entries in the row list (larger ones).
@@ -259,95 +262,108 @@ __global__ __launch_bounds__(kStageThreads) void k_dict(KnnArgs a, const uint64_
     const uint32_t tid = threadIdx.x;
     __shared__ uint32_t wsum[NT / 64 + 1];
     __shared__ unsigned long long sh_off;
-    __shared__ uint32_t sh_ok, sh_c, sh_slot, sh_rbase;
+    __shared__ uint32_t sh_ok, sh_slot, sh_rbase, sh_n, sh_end;
+    __shared__ uint32_t sh_list[64];
     const uint32_t total_items = *n_items;
     for (;;) {
         __syncthreads();
-        if (tid == 0) {
-            const uint32_t i = atomicAdd(st.cnext, 1u);
-            sh_c = i >= total_items ? 0xFFFFFFFFu
-                   : first_item(items[i]) ? (uint32_t)(items[i] >> 32) : 0xFFFFFFFEu;
+        if (tid < 64) {  // wave 0 claims the items and lists their clusters
+            uint32_t base = 0;
+            if (tid == 0) base = atomicAdd(st.cnext, st.claim);
+            base = __shfl(base, 0);
+            const uint32_t i = base + tid;
+            uint64_t code = 0;
+            const bool f = tid < st.claim && i < total_items && first_item(code = items[i]);
+            const uint64_t bal = __ballot(f);
+            if (f) sh_list[__popcll(bal & ((1ull << tid) - 1))] = (uint32_t)(code >> 32);
+            if (tid == 0) {
+                sh_n = (uint32_t)__popcll(bal);
+                sh_end = base >= total_items;
+            }
         }
         __syncthreads();
-        const uint32_t c = sh_c;
-        if (c == 0xFFFFFFFFu) break;
-        if (c == 0xFFFFFFFEu) continue;
-        const ClusterView cv = view(a, c);
-        const uint32_t s = cv.s;
-        for (uint32_t w = tid; w < 2 * Wm; w += NT) lds[w] = 0;
-        __syncthreads();
-        // 1. dictionary: 16 lanes per member, 4 items per lane in flight; the
-        //    next member's row range and the id after it are loaded while the
-        //    current member's items are folded in
-        {
-            const uint32_t sub = tid & (G16 - 1), r0 = tid / G16;
-            uint64_t na = 0, ne = 0;
-            uint32_t nu = r0 < s ? a.members[cv.o + r0] : a.n;
-            if (nu < a.n) row_range(a.indptr, nu, a.nnz, na, ne);
-            nu = r0 + NG < s ? a.members[cv.o + r0 + NG] : a.n;
-            for (uint32_t r = r0; r < s; r += NG) {
-                const uint64_t p0 = na, p1 = ne;
-                na = ne = 0;
+        if (sh_end) break;
+        const uint32_t nlist = sh_n;
+        for (uint32_t ci = 0; ci < nlist; ++ci) {
+            if (ci) __syncthreads();  // the previous cluster is done with the LDS
+            const uint32_t c = sh_list[ci];
+            const ClusterView cv = view(a, c);
+            const uint32_t s = cv.s;
+            for (uint32_t w = tid; w < 2 * Wm; w += NT) lds[w] = 0;
+            __syncthreads();
+            // 1. dictionary: 16 lanes per member, 4 items per lane in flight; the
+            //    next member's row range and the id after it are loaded while the
+            //    current member's items are folded in
+            {
+                const uint32_t sub = tid & (G16 - 1), r0 = tid / G16;
+                uint64_t na = 0, ne = 0;
+                uint32_t nu = r0 < s ? a.members[cv.o + r0] : a.n;
                 if (nu < a.n) row_range(a.indptr, nu, a.nnz, na, ne);
-                nu = r + 2 * NG < s ? a.members[cv.o + r + 2 * NG] : a.n;
-                for (uint64_t p = p0 + sub; p < p1; p += 4 * G16) {
-                    uint32_t it[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        it[q] = p + q * G16 < p1 ? a.indices[p + q * G16] : 0xFFFFFFFFu;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (it[q] >= a.m) continue;
-                        const uint32_t bit = 1u << (it[q] & 31);
-                        if (atomicOr(&once[it[q] >> 5], bit) & bit) atomicOr(&twice[it[q] >> 5], bit);
+                nu = r0 + NG < s ? a.members[cv.o + r0 + NG] : a.n;
+                for (uint32_t r = r0; r < s; r += NG) {
+                    const uint64_t p0 = na, p1 = ne;
+                    na = ne = 0;
+                    if (nu < a.n) row_range(a.indptr, nu, a.nnz, na, ne);
+                    nu = r + 2 * NG < s ? a.members[cv.o + r + 2 * NG] : a.n;
+                    for (uint64_t p = p0 + sub; p < p1; p += 4 * G16) {
+                        uint32_t it[4];
+    #pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            it[q] = p + q * G16 < p1 ? a.indices[p + q * G16] : 0xFFFFFFFFu;
+    #pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            if (it[q] >= a.m) continue;
+                            const uint32_t bit = 1u << (it[q] & 31);
+                            if (atomicOr(&once[it[q] >> 5], bit) & bit) atomicOr(&twice[it[q] >> 5], bit);
+                        }
                     }
                 }
             }
-        }
-        __syncthreads();
-        // 2. rank of each word's first dictionary item (over `once`)
-        const uint32_t per = (Wm + NT - 1) / NT, w0 = tid * per;
-        uint32_t mine = 0;
-        for (uint32_t w = w0; w < w0 + per && w < Wm; ++w) mine += __popc(twice[w]);
-        uint32_t total;
-        uint32_t run = block_excl_scan<uint32_t, NT>(mine, wsum, &total);
-        for (uint32_t w = w0; w < w0 + per && w < Wm; ++w) {
-            const uint32_t c2 = __popc(twice[w]);
-            pre[w] = run;
-            run += c2;
-        }
-        const uint32_t G = total ? (total + 255u) / 256u : 1u;
-        if (tid == 0) {
-            const unsigned long long rows = s < 32 ? s : (unsigned long long)((s + 31) / 32) * 32;
-            const unsigned long long need = rows * 8 * G;
-            const unsigned long long off = atomicAdd(st.ccur, need);
-            sh_ok = off + need <= st.cap;
-            sh_off = off;
-            st.cw[c] = sh_ok ? 8 * G : 0u;
-            st.coff[c] = off;
-            if (!sh_ok) atomicOr(st.status, 1u);
-            sh_slot = sh_ok && s > kBigS ? atomicAdd(st.dcur, 1u) : 0xFFFFFFFFu;
-            if (sh_slot != 0xFFFFFFFFu) st.dslot[c] = sh_slot;
-        }
-        __syncthreads();
-        if (!sh_ok) continue;
-        if (sh_slot != 0xFFFFFFFFu) {
-            uint32_t *dm = st.dmap + (size_t)sh_slot * 2 * Wm;
-            for (uint32_t w = tid; w < Wm; w += NT) {
-                dm[w] = twice[w];
-                dm[Wm + w] = pre[w];
-            }
-            const uint32_t nblk = (s + 31) / 32, ne = (nblk + st.row_units - 1) / st.row_units;
-            if (tid == 0) sh_rbase = atomicAdd(st.rcount, ne);
             __syncthreads();
-            for (uint32_t e = tid; e < ne; e += NT) {
-                const uint32_t u0 = e * st.row_units;
-                const uint32_t nu = nblk - u0 < st.row_units ? nblk - u0 : st.row_units;
-                st.rlist[sh_rbase + e] = ((uint64_t)c << 32) | ((uint64_t)u0 << 8) | nu;
+            // 2. rank of each word's first dictionary item (over `once`)
+            const uint32_t per = (Wm + NT - 1) / NT, w0 = tid * per;
+            uint32_t mine = 0;
+            for (uint32_t w = w0; w < w0 + per && w < Wm; ++w) mine += __popc(twice[w]);
+            uint32_t total;
+            uint32_t run = block_excl_scan<uint32_t, NT>(mine, wsum, &total);
+            for (uint32_t w = w0; w < w0 + per && w < Wm; ++w) {
+                const uint32_t c2 = __popc(twice[w]);
+                pre[w] = run;
+                run += c2;
             }
-            continue;
+            const uint32_t G = total ? (total + 255u) / 256u : 1u;
+            if (tid == 0) {
+                const unsigned long long rows = s < 32 ? s : (unsigned long long)((s + 31) / 32) * 32;
+                const unsigned long long need = rows * 8 * G;
+                const unsigned long long off = atomicAdd(st.ccur, need);
+                sh_ok = off + need <= st.cap;
+                sh_off = off;
+                st.cw[c] = sh_ok ? 8 * G : 0u;
+                st.coff[c] = off;
+                if (!sh_ok) atomicOr(st.status, 1u);
+                sh_slot = sh_ok && s > kBigS ? atomicAdd(st.dcur, 1u) : 0xFFFFFFFFu;
+                if (sh_slot != 0xFFFFFFFFu) st.dslot[c] = sh_slot;
+            }
+            __syncthreads();
+            if (!sh_ok) continue;
+            if (sh_slot != 0xFFFFFFFFu) {
+                uint32_t *dm = st.dmap + (size_t)sh_slot * 2 * Wm;
+                for (uint32_t w = tid; w < Wm; w += NT) {
+                    dm[w] = twice[w];
+                    dm[Wm + w] = pre[w];
+                }
+                const uint32_t nblk = (s + 31) / 32, ne = (nblk + st.row_units - 1) / st.row_units;
+                if (tid == 0) sh_rbase = atomicAdd(st.rcount, ne);
+                __syncthreads();
+                for (uint32_t e = tid; e < ne; e += NT) {
+                    const uint32_t u0 = e * st.row_units;
+                    const uint32_t nu = nblk - u0 < st.row_units ? nblk - u0 : st.row_units;
+                    st.rlist[sh_rbase + e] = ((uint64_t)c << 32) | ((uint64_t)u0 << 8) | nu;
+                }
+                continue;
+            }
+            write_rows<NT>(a, cv, 0, (s + 31) / 32, G, st.bits + sh_off, twice, pre, win);
         }
-        write_rows<NT>(a, cv, 0, (s + 31) / 32, G, st.bits + sh_off, twice, pre, win);
     }
 }
 
@@ -1521,6 +1537,10 @@ static StageArgs stage_args(const KnnArgs &a, const KnnPtrs &w) {
     // block many of them, down to one 64-row block on small inputs
     const uint32_t per_block = (uint32_t)((uint64_t)a.NE / 32 / kStageGrid / 8);
     st.row_units = per_block >= 8 ? 8u : per_block >= 4 ? 4u : 2u;
+    // the same for k_dict's claims: one item at a time on small inputs, where
+    // one block per cluster keeps the largest clusters apart, up to 64
+    const uint32_t claim = (uint32_t)((uint64_t)a.NE / kStageGrid / 256);
+    st.claim = claim >= 64 ? 64u : claim >= 16 ? 16u : claim >= 4 ? 4u : 1u;
     st.status = w.status;
     return st;
 }
