@@ -74,9 +74,10 @@ size_t knn_min_bytes(uint32_t n, uint32_t NE, uint32_t m) {
     return knn_ws_fixed(n, NE, m, nullptr) + 4096;
 }
 
-ClusterDims cdims(uint32_t n, const c2_params *p) {
+ClusterDims cdims(uint32_t n, uint32_t m, const c2_params *p) {
     ClusterDims d;
     d.NE = (size_t)p->t * n;
+    d.TM = (size_t)p->t * m;
     size_t np = d.NE / ((size_t)p->cap + 1);
     d.NP = (np > p->t ? np : p->t) + 1;
     return d;
@@ -84,8 +85,8 @@ ClusterDims cdims(uint32_t n, const c2_params *p) {
 
 // Scratch of the clustering step: the grid rounds' state, or the workgroup
 // path's signatures and cluster starts, whichever is larger.
-size_t cluster_scratch_bytes(uint32_t n, const c2_params *p) {
-    const size_t g = cluster_ws_elems(cdims(n, p), nullptr);
+size_t cluster_scratch_bytes(uint32_t n, uint32_t m, const c2_params *p) {
+    const size_t g = cluster_ws_elems(cdims(n, m, p), nullptr);
     const size_t w = cluster_wg_ws_bytes(n, p->t);
     return g > w ? g : w;
 }
@@ -106,7 +107,7 @@ BuildLayout build_layout(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *
     L.part_id = take(4 * NE * p->k);
     L.part_I = take(4 * NE * p->k);
     L.scratch = off;
-    const size_t cw = cluster_scratch_bytes(n, p);
+    const size_t cw = cluster_scratch_bytes(n, m, p);
     L.knn_fixed = knn_ws_fixed(n, (uint32_t)NE, m, nullptr);
     const size_t kw = L.knn_fixed + knn_store_default_bytes(n, (uint32_t)NE, m, nnz, p->t);
     L.total = off + (cw > kw ? cw : kw);
@@ -117,7 +118,7 @@ BuildLayout build_layout(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *
 // clustering scratch or the local KNN's fixed part and a minimal store.
 size_t build_min_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params *p) {
     const BuildLayout L = build_layout(n, m, nnz, p);
-    const size_t cw = cluster_scratch_bytes(n, p), kw = L.knn_fixed + 4096;
+    const size_t cw = cluster_scratch_bytes(n, m, p), kw = L.knn_fixed + 4096;
     return L.scratch + (cw > kw ? cw : kw);
 }
 
@@ -149,6 +150,7 @@ ClusterPtrs cluster_ptrs(char *base, const ClusterWs &w, uint32_t *members, uint
     c.flg = u64(w.flg);
     c.ftmp = u64(w.ftmp);
     c.keys0 = u32(w.keys0);
+    c.bt = u32(w.bt);
     c.ctr = u32(w.ctr);
     c.status = status;
     return c;
@@ -232,7 +234,7 @@ c2_status run_cluster(const c2_profiles *P, const uint32_t *bucket, const c2_par
                       uint32_t *cl_cfg_off, char *scratch, uint32_t *status, hipStream_t s,
                       uint32_t *rounds_used, const uint32_t *keys_in = nullptr) {
     ClusterWs w;
-    const ClusterDims d = cdims(P->n, p);
+    const ClusterDims d = cdims(P->n, P->m, p);
     cluster_ws_elems(d, &w);
     const ClusterPtrs c = cluster_ptrs(scratch, w, members, status);
     ClusterArgs a;
@@ -392,7 +394,7 @@ size_t c2_workspace_bytes(uint32_t n, uint32_t m, uint64_t nnz, const c2_params 
         return kHeader;
     case C2_OP_CLUSTER:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
-        return kHeader + cluster_scratch_bytes(n, p);
+        return kHeader + cluster_scratch_bytes(n, m, p);
     case C2_OP_LOCAL_KNN:
         if (check_sizes(n, m, nnz, p, true) != C2_OK) return 0;
         return kHeader + knn_ws_fixed(n, p->t * n, m, nullptr) +
@@ -780,8 +782,8 @@ c2_status c2_merge(const c2_profiles *P, const uint32_t *part_id, const uint32_t
     if ((st = check_profiles(P)) != C2_OK) return st;
     if ((st = check_sizes(P->n, P->m, P->nnz, p, true)) != C2_OK) return st;
     if (!part_id || !part_I || !knn_id || !knn_I || !knn_U) return fail(C2_E_ARG, "NULL pointer");
-    C2_TRY(launch_merge(P->indptr, P->nnz, P->n, p->t, p->k, part_id, part_I, knn_id, knn_I, knn_U,
-                        (hipStream_t)stream),
+    C2_TRY(launch_merge(P->indptr, nullptr, P->nnz, P->n, p->t, p->k, part_id, part_I, knn_id,
+                        knn_I, knn_U, (hipStream_t)stream),
            "merge");
     return C2_OK;
 }
@@ -805,7 +807,12 @@ static c2_status build_impl(const c2_profiles *P, const uint64_t *tab, const c2_
     st = run_knn(P, members, cl_off, cl_cfg, p->t, p->k, form, tune, pid, pI, base + L.scratch,
                  ws_bytes - L.scratch, reinterpret_cast<uint32_t *>(base) + 1, s);
     if (st != C2_OK) return st;
-    C2_TRY(launch_merge(P->indptr, P->nnz, P->n, p->t, p->k, pid, pI, knn_id, knn_I, knn_U, s),
+    // the local KNN left the profile lengths at the start of its workspace
+    KnnWs kw;
+    knn_ws_fixed(P->n, p->t * P->n, P->m, &kw);
+    const uint32_t *rlen = reinterpret_cast<const uint32_t *>(base + L.scratch + kw.rlen);
+    C2_TRY(launch_merge(P->indptr, rlen, P->nnz, P->n, p->t, p->k, pid, pI, knn_id, knn_I, knn_U,
+                        s),
            "merge");
     return C2_OK;
 }
@@ -883,7 +890,8 @@ c2_status c2_brute_force(const c2_profiles *P, uint32_t k, uint32_t *knn_id, uin
     st = run_knn(P, members, cl_off, cl_cfg, 1, k, C2_FORM_BATCHED, nullptr, pid, pI, base + off,
                  ws_bytes - off, reinterpret_cast<uint32_t *>(base) + 1, s);
     if (st != C2_OK) return st;
-    C2_TRY(launch_merge(P->indptr, P->nnz, P->n, 1, k, pid, pI, knn_id, knn_I, knn_U, s), "merge");
+    C2_TRY(launch_merge(P->indptr, nullptr, P->nnz, P->n, 1, k, pid, pI, knn_id, knn_I, knn_U, s),
+           "merge");
     return C2_OK;
 }
 

@@ -10,6 +10,10 @@ constexpr uint32_t kMaxRounds = 4096;
 // ---- hashing / validation
 hipError_t launch_hash_items(const uint64_t *tab, uint32_t t, uint32_t b, uint32_t m,
                              uint32_t *bucket, hipStream_t s);
+// The same keys through an item-major copy of the table (bt: t * m u32 of scratch).
+hipError_t launch_frh_keys_rows(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
+                                uint32_t n, uint32_t m, const uint32_t *bucket, uint32_t t,
+                                uint32_t b, uint32_t *bt, uint32_t *keys, hipStream_t s);
 hipError_t launch_frh_keys(const int64_t *indptr, const uint32_t *indices, uint64_t nnz,
                            uint32_t n, uint32_t m, const uint32_t *bucket, uint32_t t, uint32_t b,
                            uint32_t *keys, hipStream_t s);
@@ -59,10 +63,11 @@ hipError_t launch_adam(float *p, const float *g, float *m1, float *m2, size_t n,
 struct ClusterDims {
     size_t NE;  // t*n slots
     size_t NP;  // most segments that can be split in one round
+    size_t TM;  // t*m: the item-major bucket table of the top-level keys
 };
 struct ClusterWs {  // byte offsets inside the clustering workspace
     size_t E_seg, S_state, S_eta1, S_len, mark, mtmp, A_uid, A_rank, P_start, P_len, P_state,
-        P_q0, key, key_alt, val, val_alt, hist, htmp, glb, glen, flg, ftmp, keys0, ctr, status,
+        P_q0, key, key_alt, val, val_alt, hist, htmp, glb, glen, flg, ftmp, keys0, bt, ctr, status,
         total;
 };
 struct ClusterPtrs {
@@ -72,7 +77,7 @@ struct ClusterPtrs {
     uint64_t *key, *key_alt;
     uint32_t *val, *val_alt, *hist, *htmp, *glb, *glen;
     uint64_t *flg, *ftmp;
-    uint32_t *keys0, *ctr, *status;
+    uint32_t *keys0, *bt, *ctr, *status;
 };
 struct ClusterArgs {
     const int64_t *indptr;
@@ -161,8 +166,9 @@ hipError_t launch_hyrec_out(const uint32_t *S, uint32_t s, uint32_t k, uint32_t 
                             uint32_t *part_I, hipStream_t st);
 
 // ---- merge
-hipError_t launch_merge(const int64_t *indptr, uint64_t nnz, uint32_t n, uint32_t t, uint32_t k,
-                        const uint32_t *part_id, const uint32_t *part_I, uint32_t *knn_id,
-                        uint32_t *knn_I, uint32_t *knn_U, hipStream_t s);
+// ulen: the profile lengths when the caller has them, else nullptr (read from indptr)
+hipError_t launch_merge(const int64_t *indptr, const uint32_t *ulen, uint64_t nnz, uint32_t n,
+                        uint32_t t, uint32_t k, const uint32_t *part_id, const uint32_t *part_I,
+                        uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U, hipStream_t s);
 
 }  // namespace c2

@@ -14,13 +14,45 @@ namespace c2 {
 
 constexpr int kMergeThreads = 64;
 
-// One wave of 64 lanes serves 32/G users (one if G = 64): all 64 lanes copy
+// DPP controls of the group maximum: quad_perm [1,0,3,2] and [2,3,0,1]
+// (partners at xor 1 and xor 2), then the half-row and row mirrors (which
+// pair each 4- and 8-lane block with the other one of its 8 and 16 lanes).
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+// max(b, b of the partner lane under DPP control CTRL), u64.
+template <int CTRL>
+C2_DEV uint64_t max_dpp(uint64_t b) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    return o > b ? o : b;
+}
+
+// Maximum of b over the G lanes of the group (all of them end with it).
+template <int G>
+C2_DEV uint64_t group_max(uint64_t b) {
+    if (G > 1) b = max_dpp<kDppXor1>(b);
+    if (G > 2) b = max_dpp<kDppXor2>(b);
+    if (G > 4) b = max_dpp<kDppHalfMirror>(b);
+    if (G > 8) b = max_dpp<kDppMirror>(b);
+#pragma unroll
+    for (int d = 16; d < G; d <<= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)b, d, G), hi = __shfl_xor((uint32_t)(b >> 32), d, G);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        b = o > b ? o : b;
+    }
+    return b;
+}
+
+// One wave of 64 lanes serves 64/G users (one if G = 64): all 64 lanes copy
 // the users' t lists (contiguous in part_*) into LDS with U computed,
-// coalesced, in one pass of loads; the selection loop then runs from LDS on
-// the first 32 lanes.  Half the users per wave (rather than 64/G) doubles
-// the waves in flight, which the latency-bound staging needs.
+// coalesced, in one pass of loads; the selection loop then runs from LDS.
+// The profile lengths come from ulen when the caller has them (one gather per
+// entry), else from indptr.
 template <int G>
 __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restrict__ indptr,
+                                                         const uint32_t *__restrict__ ulen,
                                                          uint64_t nnz, uint32_t n, uint32_t t,
                                                          uint32_t k,
                                                          const uint32_t *__restrict__ part_id,
@@ -28,21 +60,26 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
                                                          uint32_t *__restrict__ knn_id,
                                                          uint32_t *__restrict__ knn_I,
                                                          uint32_t *__restrict__ knn_U) {
-    constexpr int UPW = G <= kMergeThreads / 2 ? kMergeThreads / G / 2 : 1;  // users per wave
+    constexpr int UPW = G <= kMergeThreads ? kMergeThreads / G : 1;  // users per wave
     __shared__ uint32_t sv[UPW * G * kMaxK], sI[UPW * G * kMaxK], sU[UPW * G * kMaxK];
     const uint32_t lane = threadIdx.x;
     const uint64_t u0 = (uint64_t)blockIdx.x * UPW;
     // stage: entries of users u0 .. u0+UPW-1, list j, slot r at ((ul*G + j)*k + r).
     // The profile lengths of the block's users first; then, per lane, up to
-    // 16 entries with all their loads (entry, then the neighbour's row
-    // bounds) in flight before any is used.
-    __shared__ uint32_t ulen_s[UPW];
+    // 16 entries with all their loads (entry, then the neighbour's length)
+    // in flight before any is used.  wide[ul]: some U of the user is >= 2^16.
+    __shared__ uint32_t ulen_s[UPW], wide[UPW];
     const uint32_t nu = (uint32_t)(u0 + UPW <= n ? UPW : (u0 < n ? n - u0 : 0));
     if (lane < nu) {
-        uint64_t a0, a1;
-        row_range(indptr, (uint32_t)(u0 + lane), nnz, a0, a1);
-        ulen_s[lane] = (uint32_t)(a1 - a0);
+        if (ulen) {
+            ulen_s[lane] = ulen[u0 + lane];
+        } else {
+            uint64_t a0, a1;
+            row_range(indptr, (uint32_t)(u0 + lane), nnz, a0, a1);
+            ulen_s[lane] = (uint32_t)(a1 - a0);
+        }
     }
+    if (lane < UPW) wide[lane] = 0;
     __syncthreads();
     {
         const uint32_t tk = t * k;
@@ -56,12 +93,25 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
                 v[q] = e < total ? part_id[base + e] : kPad;
                 I[q] = e < total ? part_I[base + e] : 0;
             }
-            int64_t b0[16], b1[16];
+            uint32_t lv[16];
+            if (ulen) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const bool ok = v[q] < n;
-                b0[q] = ok ? indptr[v[q]] : 0;
-                b1[q] = ok ? indptr[v[q] + 1] : 0;
+                for (int q = 0; q < 16; ++q) lv[q] = v[q] < n ? ulen[v[q]] : 0u;
+            } else {
+                int64_t b0[16], b1[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const bool ok = v[q] < n;
+                    b0[q] = ok ? indptr[v[q]] : 0;
+                    b1[q] = ok ? indptr[v[q] + 1] : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    // the row bounds clamped as row_range does
+                    const int64_t lb = b0[q] < 0 ? 0 : b0[q];
+                    const int64_t hb = b1[q] < (int64_t)nnz ? b1[q] : (int64_t)nnz;
+                    lv[q] = v[q] < n && hb > lb ? (uint32_t)(hb - lb) : 0u;
+                }
             }
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -71,13 +121,11 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
                 const uint32_t ul = e / tk;
                 const uint32_t d = e + ul * (G - t) * k;
                 const bool ok = v[q] < n;
-                // the row bounds clamped as row_range does
-                const int64_t lb = b0[q] < 0 ? 0 : b0[q];
-                const int64_t hb = b1[q] < (int64_t)nnz ? b1[q] : (int64_t)nnz;
-                const uint32_t lv = ok && hb > lb ? (uint32_t)(hb - lb) : 0u;
+                const uint32_t U = ulen_s[ul] + lv[q] - I[q];
                 sv[d] = ok ? v[q] : kPad;
                 sI[d] = ok ? I[q] : 0;
-                sU[d] = ok ? ulen_s[ul] + lv - I[q] : 0;
+                sU[d] = ok ? U : 0;
+                if (ok && U >= 65536u) wide[ul] = 1;
             }
         }
     }
@@ -98,28 +146,56 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
     load();
     uint32_t out = 0;
     uint32_t *oid = knn_id + u * k, *oI = knn_I + u * k, *oU = knn_U + u * k;
-    while (out < k) {
-        // the group maximum of the heads (kPad: list exhausted)
-        bool ok = hv != kPad;
-        uint32_t bI = hI, bU = hU, bv = hv;
+    if (!wide[ul]) {
+        // Every U < 2^16: the 32-bit key orders the similarities exactly
+        // (distinct fractions get distinct keys, equal ones equal keys), so
+        // (key, then the smaller id) is one 64-bit maximum over the group.
+        // The lowest lane whose head is the maximum writes it.
+        auto head_key = [&]() -> uint64_t {
+            return hv == kPad ? 0ull : ((uint64_t)jkey(hI, hU) << 32) | (0xFFFFFFFFu - hv);
+        };
+        const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1) << (ul * G);
+        uint64_t my = head_key();
+        while (out < k) {
+            const uint64_t best = group_max<G>(my);
+            if (best == 0) break;  // every list exhausted
+            const uint64_t hit = __ballot(my == best) & gmask;
+            if (my == best && lane == (uint32_t)__ffsll((long long)hit) - 1) {
+                oid[out] = hv;
+                oI[out] = hI;
+                oU[out] = hU;
+            }
+            ++out;
+            if (my == best) {
+                ++ptr;
+                load();
+                my = head_key();
+            }
+        }
+    } else {
+        while (out < k) {
+            // the group maximum of the heads (kPad: list exhausted), exact order
+            bool ok = hv != kPad;
+            uint32_t bI = hI, bU = hU, bv = hv;
 #pragma unroll
-        for (int d = G / 2; d > 0; d >>= 1) {
-            const bool ook = __shfl_xor((int)ok, d, G) != 0;
-            const uint32_t oI2 = __shfl_xor(bI, d, G), oU2 = __shfl_xor(bU, d, G);
-            const uint32_t ov = __shfl_xor(bv, d, G);
-            const bool take = ook && (!ok || jbetter(oI2, oU2, ov, bI, bU, bv));
-            if (take) { ok = true; bI = oI2; bU = oU2; bv = ov; }
-        }
-        if (!ok) break;
-        if (j == 0) {
-            oid[out] = bv;
-            oI[out] = bI;
-            oU[out] = bU;
-        }
-        ++out;
-        if (hv == bv) {
-            ++ptr;
-            load();
+            for (int d = G / 2; d > 0; d >>= 1) {
+                const bool ook = __shfl_xor((int)ok, d, G) != 0;
+                const uint32_t oI2 = __shfl_xor(bI, d, G), oU2 = __shfl_xor(bU, d, G);
+                const uint32_t ov = __shfl_xor(bv, d, G);
+                const bool take = ook && (!ok || jbetter(oI2, oU2, ov, bI, bU, bv));
+                if (take) { ok = true; bI = oI2; bU = oU2; bv = ov; }
+            }
+            if (!ok) break;
+            if (j == 0) {
+                oid[out] = bv;
+                oI[out] = bI;
+                oU[out] = bU;
+            }
+            ++out;
+            if (hv == bv) {
+                ++ptr;
+                load();
+            }
         }
     }
     for (uint32_t r = out + j; r < k; r += G) {
@@ -129,17 +205,17 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
     }
 }
 
-hipError_t launch_merge(const int64_t *indptr, uint64_t nnz, uint32_t n, uint32_t t, uint32_t k,
-                        const uint32_t *part_id, const uint32_t *part_I, uint32_t *knn_id,
-                        uint32_t *knn_I, uint32_t *knn_U, hipStream_t s) {
+hipError_t launch_merge(const int64_t *indptr, const uint32_t *ulen, uint64_t nnz, uint32_t n,
+                        uint32_t t, uint32_t k, const uint32_t *part_id, const uint32_t *part_I,
+                        uint32_t *knn_id, uint32_t *knn_I, uint32_t *knn_U, hipStream_t s) {
     uint32_t G = 1;
     while (G < t) G <<= 1;
-    const uint32_t upw = G <= kMergeThreads / 2 ? kMergeThreads / G / 2 : 1;
+    const uint32_t upw = G <= kMergeThreads ? kMergeThreads / G : 1;
     const dim3 grid((uint32_t)div_up((uint64_t)n, upw));
 #define C2_MERGE(GG)                                                                           \
     case GG:                                                                                   \
-        hipLaunchKernelGGL(k_merge<GG>, grid, dim3(kMergeThreads), 0, s, indptr, nnz, n, t, k,  \
-                           part_id, part_I, knn_id, knn_I, knn_U);                           \
+        hipLaunchKernelGGL(k_merge<GG>, grid, dim3(kMergeThreads), 0, s, indptr, ulen, nnz, n, \
+                           t, k, part_id, part_I, knn_id, knn_I, knn_U);                       \
         break;
     switch (G) {
         C2_MERGE(1) C2_MERGE(2) C2_MERGE(4) C2_MERGE(8) C2_MERGE(16) C2_MERGE(32) C2_MERGE(64)

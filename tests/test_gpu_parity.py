@@ -435,6 +435,32 @@ def test_long_profiles_take_exact_fallback(orc):
         assert np.array_equal(u32(g), w)
 
 
+def test_merge_wide_unions(orc):
+    # unions of 2^16 items or more: the merge leaves the 32-bit key order for
+    # the exact comparison there (users with such a union among their
+    # candidates), both from indptr (c2_merge) and from the build's lengths
+    rng = np.random.Generator(np.random.PCG64(81))
+    m = 120000
+    sets = []
+    for u in range(48):
+        size = 40000 if u % 4 == 0 else int(rng.integers(5, 300))
+        sets.append(set(rng.choice(m, size=size, replace=False).tolist()))
+    P = synth.profiles_from_sets(sets, m)
+    k, t, b, cap = 6, 3, 2, 1000
+    tab = synth.hash_tables(t, 82)
+    r = orc.build_graph(P.indptr, P.indices, P.n, P.m, tab, b, cap, k, THREADS)
+    big = np.arange(P.n) % 4 == 0
+    assert (r.knn_U[big] >= 65536).any() and (r.knn_U[~big] < 65536).all()
+    dP, dtab = gpu_inputs(P, tab)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a).view(np.int32)).cuda()
+    got = c2.merge(dP, dev(r.part_id), dev(r.part_I), c2.params(t, b, cap, k))
+    for g, w in zip(got, (r.knn_id, r.knn_I, r.knn_U)):
+        assert np.array_equal(u32(g), w)
+    got = c2.build(dP, dtab, c2.params(t, b, cap, k), c2.FORM_BATCHED)
+    for g, w in zip(got, (r.knn_id, r.knn_I, r.knn_U)):
+        assert np.array_equal(u32(g), w)
+
+
 # ------------------------------------------------- MinHash clustering ----
 
 @pytest.mark.parametrize("path", list(CPATHS))
