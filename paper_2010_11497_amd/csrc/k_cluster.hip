@@ -249,6 +249,7 @@ size_t cluster_ws_elems(const ClusterDims &d, ClusterWs *w) {
     x.flg = take(8 * (NE + 1));
     x.ftmp = take(8 * scan_tmp_elems((uint32_t)NE));
     x.keys0 = take(4 * NE);
+    x.bt = take(4 * d.TM);
     x.ctr = take(4 * (kMaxRounds + 2));
     x.status = take(4 * 4);
     x.total = off;
@@ -295,7 +296,8 @@ hipError_t cluster_init(const ClusterArgs &a, const ClusterPtrs &c, hipStream_t 
                        dim3(256), 0, s, c.E_uid, c.E_seg, c.S_state, c.S_eta1, c.S_len, a.n, a.NE,
                        c.ctr, (uint32_t)(kMaxRounds + 2));
     if (a.keys_in) return hipGetLastError();
-    return launch_frh_keys(a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket, a.t, a.b, c.keys0, s);
+    return launch_frh_keys_rows(a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket, a.t, a.b, c.bt,
+                                c.keys0, s);
 }
 
 hipError_t cluster_finish(const ClusterArgs &a, const ClusterPtrs &c, uint32_t rounds,
