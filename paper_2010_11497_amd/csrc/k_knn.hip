@@ -798,8 +798,12 @@ struct SelCtx {
 
 // One selection round: the 16 candidates of accumulator block (BI, BJ) for the
 // lane's row member 32 * BJ + lr.  The fp32 filter runs on all lanes; the
-// candidates that pass are staged in LDS and inserted with the exact key,
-// the two lanes of the row taking turns (lower half first).
+// candidates that pass are staged in LDS and offered to the heap with the
+// exact key, which decides (a candidate that ties the root passes the filter
+// and is turned away there), the two lanes of the row taking turns (lower
+// half first).  The exact key is computed only in the insert loop, whose
+// iterations follow each lane's own candidates: a check of the 16 positions
+// in turn would run every position that any lane holds.
 template <int BJ, int BI>
 C2_DEV void select_round(const v16f &acc, uint32_t Lr, bool act, const SelCtx &cx, WaveLds &L) {
     const uint32_t R = 32 * BJ + cx.lr;
@@ -820,21 +824,6 @@ C2_DEV void select_round(const v16f &acc, uint32_t Lr, bool act, const SelCtx &c
         else pk[r >> 1] = I;
     }
     if (!__any(mask != 0u)) return;
-    // with a full heap, the exact key of every candidate that passed the fp32
-    // test is compared with the root (equal similarities pass that test)
-    if (full) {
-        const uint64_t root = L.hk[R];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if ((mask >> r) & 1u) {
-                const uint32_t I = (pk[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
-                const uint32_t col = acc_col(BI, r, cx.hh);
-                const uint32_t U = Lr + L.clen[col] - I, uid = L.cuid[col];
-                if ((((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid)) <= root) mask &= ~(1u << r);
-            }
-        }
-        if (!__any(mask != 0u)) return;
-    }
 #pragma unroll
     for (int q = 0; q < 8; ++q) L.scr[cx.lane * 8 + q] = pk[q];
     wave_sync();
@@ -891,7 +880,8 @@ C2_DEV void own_rows(v16f (&acc)[NC][2]) {
 }
 
 // One selection round on owned rows: the 16 candidates of column block BI,
-// lane half H, for the lane's own row member 32 * hh + lr.
+// lane half H, for the lane's own row member 32 * hh + lr (filter and
+// exact-key insert as in select_round).
 template <int H, int BI>
 C2_DEV void select_own(const v16f &acc, uint32_t Lr, bool act, const SelCtx &cx, WaveLds &L) {
     const uint32_t R = 32 * cx.hh + cx.lr;
@@ -913,18 +903,6 @@ C2_DEV void select_own(const v16f &acc, uint32_t Lr, bool act, const SelCtx &cx,
         else pk[r >> 1] = I;
     }
     if (!__any(mask != 0u)) return;
-    if (full) {  // exact keys of the candidates that passed the fp32 test
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if ((mask >> r) & 1u) {
-                const uint32_t I = (pk[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
-                const uint32_t col = acc_col(BI, r, H);
-                const uint32_t U = Lr + L.clen[col] - I, uid = L.cuid[col];
-                if ((((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid)) <= root) mask &= ~(1u << r);
-            }
-        }
-        if (!__any(mask != 0u)) return;
-    }
 #pragma unroll
     for (int q = 0; q < 8; ++q) L.scr[cx.lane * 8 + q] = pk[q];
     wave_sync();
