@@ -272,8 +272,9 @@ __global__ __launch_bounds__(kStageThreads) void k_dict(KnnArgs a, const uint64_
             if (tid == 0) base = atomicAdd(st.cnext, st.claim);
             base = __shfl(base, 0);
             const uint32_t i = base + tid;
-            uint64_t code = 0;
-            const bool f = tid < st.claim && i < total_items && first_item(code = items[i]);
+            const bool in = tid < st.claim && i < total_items;
+            const uint64_t code = in ? items[i] : 0ull;
+            const bool f = in && first_item(code);
             const uint64_t bal = __ballot(f);
             if (f) sh_list[__popcll(bal & ((1ull << tid) - 1))] = (uint32_t)(code >> 32);
             if (tid == 0) {
@@ -307,14 +308,15 @@ __global__ __launch_bounds__(kStageThreads) void k_dict(KnnArgs a, const uint64_
                     nu = r + 2 * NG < s ? a.members[cv.o + r + 2 * NG] : a.n;
                     for (uint64_t p = p0 + sub; p < p1; p += 4 * G16) {
                         uint32_t it[4];
-    #pragma unroll
+#pragma unroll
                         for (int q = 0; q < 4; ++q)
                             it[q] = p + q * G16 < p1 ? a.indices[p + q * G16] : 0xFFFFFFFFu;
-    #pragma unroll
+#pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             if (it[q] >= a.m) continue;
                             const uint32_t bit = 1u << (it[q] & 31);
-                            if (atomicOr(&once[it[q] >> 5], bit) & bit) atomicOr(&twice[it[q] >> 5], bit);
+                            if (atomicOr(&once[it[q] >> 5], bit) & bit)
+                                atomicOr(&twice[it[q] >> 5], bit);
                         }
                     }
                 }
