@@ -42,27 +42,67 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(const T *in, T *
     chunk_scan<T, kSingleThreads>(in, out, N, 0, (T)0, true, wsum);
 }
 
+// The chunk's total: the order of the sum does not matter, so the block reads
+// its chunk in consecutive runs of kScanThreads elements (coalesced, all loads
+// in flight before any is added).
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, T *part, uint32_t N) {
     __shared__ T wsum[kScanThreads / 64 + 1];
-    const uint32_t start = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
-    T sum = 0;
+    const uint32_t start = blockIdx.x * kScanChunk + threadIdx.x;
+    T v[kScanPer];
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
-        uint32_t idx = start + i;
-        if (idx < N) sum += in[idx];
+        const uint32_t idx = start + i * kScanThreads;
+        v[i] = idx < N ? in[idx] : (T)0;
     }
+    T sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) sum += v[i];
     T total;
     block_excl_scan<T, kScanThreads>(sum, wsum, &total);
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
+// chunk_scan of one kScanChunk chunk staged through LDS: loads and stores in
+// consecutive runs of kScanThreads elements (coalesced), each thread scanning
+// kScanPer consecutive elements from the staging array.
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const T *in, T *out, const T *part,
                                                             uint32_t N, uint32_t nb) {
     __shared__ T wsum[kScanThreads / 64 + 1];
-    chunk_scan<T, kScanThreads>(in, out, N, blockIdx.x * kScanChunk, part[blockIdx.x],
-                                blockIdx.x == nb - 1, wsum);
+    // element e of the chunk at e + e / kScanPer: a thread's kScanPer
+    // consecutive elements then fall in different banks
+    __shared__ T stage[kScanChunk + kScanChunk / kScanPer];
+    auto at = [](uint32_t e) { return e + e / kScanPer; };
+    const uint32_t base = blockIdx.x * kScanChunk, tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        const uint32_t idx = base + i * kScanThreads + tid;
+        stage[at(i * kScanThreads + tid)] = idx < N ? in[idx] : (T)0;
+    }
+    __syncthreads();
+    T loc[kScanPer];
+    T sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        loc[i] = stage[at(tid * kScanPer + i)];
+        sum += loc[i];
+    }
+    T total;
+    T pre = block_excl_scan<T, kScanThreads>(sum, wsum, &total) + part[blockIdx.x];
+    // (block_excl_scan's barriers order the reads above before these writes)
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        stage[at(tid * kScanPer + i)] = pre;
+        pre += loc[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        const uint32_t idx = base + i * kScanThreads + tid;
+        if (idx < N) out[idx] = stage[at(i * kScanThreads + tid)];
+    }
+    if (blockIdx.x == nb - 1 && tid == 0) out[N] = part[blockIdx.x] + total;
 }
 
 size_t scan_tmp_elems(uint32_t N) {
