@@ -56,6 +56,9 @@ __global__ __launch_bounds__(256) void k_clu_mark(const uint32_t *E_seg, const u
     mark[p] = (uint64_t)act | ((uint64_t)(act && s == p) << 32);
 }
 
+// LANES lanes per slot: kFillLanes for the split rounds, which scan the
+// profile; one at the top level (round 0), which only reads the given keys.
+template <int LANES>
 __global__ __launch_bounds__(256) void k_clu_fill(
     const int64_t *__restrict__ indptr, const uint32_t *__restrict__ indices, uint64_t nnz,
     uint32_t n, uint32_t m, const uint32_t *__restrict__ bucket, const uint32_t *__restrict__ keys0,
@@ -63,9 +66,10 @@ __global__ __launch_bounds__(256) void k_clu_fill(
     const uint32_t *S_eta1, const uint32_t *S_len, const uint64_t *mark, uint32_t NE,
     uint32_t *A_uid, uint32_t *A_rank, uint32_t *P_start, uint32_t *P_len, uint32_t *P_state,
     uint32_t *P_q0, uint64_t *key, uint32_t *val) {
-    const uint32_t p = (blockIdx.x * blockDim.x + threadIdx.x) / kFillLanes;
-    const uint32_t gl = threadIdx.x % kFillLanes;
-    if (p >= NE) return;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid / LANES >= NE) return;
+    const uint32_t p = (uint32_t)(gid / LANES);
+    const uint32_t gl = threadIdx.x % LANES;
     const uint32_t s = E_seg[p];
     const uint32_t st = S_state[s];
     if (st == kFinal) return;
@@ -76,8 +80,8 @@ __global__ __launch_bounds__(256) void k_clu_fill(
     if (st == kRoot) {
         e = keys0[(size_t)j * n + u];
     } else {
-        e = group_min_above<kFillLanes>(indptr, indices, nnz, bucket + (size_t)j * m, m, b, u,
-                                        S_eta1[s], gl);
+        e = group_min_above<LANES>(indptr, indices, nnz, bucket + (size_t)j * m, m, b, u,
+                                   S_eta1[s], gl);
     }
     if (gl == 0) {
         A_uid[q] = u;
@@ -267,11 +271,19 @@ hipError_t cluster_round(const ClusterArgs &a, const ClusterPtrs &c, uint32_t ro
     hipLaunchKernelGGL(k_clu_mark, grid_for(NE), dim3(256), 0, s, c.E_seg, c.S_state, c.mark, NE);
     hipError_t e = scan_u64(c.mark, c.mark, NE, c.mtmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_clu_fill, grid_for((uint64_t)NE * kFillLanes), dim3(256), 0, s,
-                       a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket,
-                       a.keys_in ? a.keys_in : c.keys0, a.b, a.bb,
-                       c.E_uid, c.E_seg, c.S_state, c.S_eta1, c.S_len, c.mark, NE, c.A_uid,
-                       c.A_rank, c.P_start, c.P_len, c.P_state, c.P_q0, c.key, c.val);
+    // (round 0: every slot is at the top level)
+    if (round == 0)
+        hipLaunchKernelGGL(k_clu_fill<1>, grid_for((uint64_t)NE), dim3(256), 0, s,
+                           a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket,
+                           a.keys_in ? a.keys_in : c.keys0, a.b, a.bb,
+                           c.E_uid, c.E_seg, c.S_state, c.S_eta1, c.S_len, c.mark, NE, c.A_uid,
+                           c.A_rank, c.P_start, c.P_len, c.P_state, c.P_q0, c.key, c.val);
+    else
+        hipLaunchKernelGGL(k_clu_fill<kFillLanes>, grid_for((uint64_t)NE * kFillLanes), dim3(256),
+                           0, s, a.indptr, a.indices, a.nnz, a.n, a.m, a.bucket,
+                           a.keys_in ? a.keys_in : c.keys0, a.b, a.bb,
+                           c.E_uid, c.E_seg, c.S_state, c.S_eta1, c.S_len, c.mark, NE, c.A_uid,
+                           c.A_rank, c.P_start, c.P_len, c.P_state, c.P_q0, c.key, c.val);
     const uint32_t *n_act = reinterpret_cast<const uint32_t *>(c.mark + NE);
     const uint32_t rank_bits = round == 0 ? bit_width(a.t - 1) : bit_width(a.NP - 1);
     bool in_alt = false;
