@@ -721,11 +721,18 @@ struct KeyHeap {
     }
 };
 
-// Necessary condition for a candidate to beat the root, in fp32 with a margin
-// that covers rounding: J > J_T implies I > sigma_T * (|P_u| + |P_v|).
-C2_DEV bool may_beat(uint32_t I, uint32_t S, float sigma) {
-    return (float)I >= sigma * (float)S * 0.999999f;
-}
+// Necessary condition for a candidate to beat the root: J > J_T implies
+// I > sigma_T * (|P_u| + |P_v|), sigma_T = J_T / (1 + J_T).  It is taken in
+// fp32 on the accumulator as I >= fma(s, |P_v|, s * |P_u|) with
+// s = sigma_T * (1 - 1e-6) fixed per row and round: the three roundings and
+// that of sigma_T stay far below the 1e-6 margin, so no candidate that can
+// beat the root is turned away.  An empty or filling heap has s = 0, and
+// every candidate passes.
+struct BeatTest {
+    float s, sL;
+    C2_DEV BeatTest(float sigma, uint32_t Lr) : s(sigma * 0.999999f), sL(s * (float)Lr) {}
+    C2_DEV bool operator()(float I, uint32_t Lv) const { return I >= __builtin_fmaf(s, (float)Lv, sL); }
+};
 
 C2_DEV float sigma_of(uint64_t root) {
     const float kt = (float)(uint32_t)(root >> 32);
@@ -812,15 +819,14 @@ C2_DEV void select_round(const v16f &acc, uint32_t Lr, bool act, const SelCtx &c
     const uint32_t self = cx.rowpos + 32 * BJ;
     const uint32_t cnt0 = L.hcnt[R];
     const bool full = cnt0 >= cx.k;
-    const float sigma = full ? sigma_of(L.hk[R]) : 0.0f;
+    const BeatTest beats(full ? sigma_of(L.hk[R]) : 0.0f, Lr);
     uint32_t mask = 0;
     uint32_t pk[8];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const uint32_t col = acc_col(BI, r, cx.hh);
         const uint32_t I = (uint32_t)acc[r];
-        const bool ok = act & (col < cx.ncol) & (col != self) &
-                        (!full || may_beat(I, Lr + L.clen[col], sigma));
+        const bool ok = act & (col < cx.ncol) & (col != self) & beats(acc[r], L.clen[col]);
         mask |= (ok ? 1u : 0u) << r;
         if (r & 1) pk[r >> 1] |= I << 16;
         else pk[r >> 1] = I;
@@ -891,15 +897,14 @@ C2_DEV void select_own(const v16f &acc, uint32_t Lr, bool act, const SelCtx &cx,
     const uint32_t cnt0 = L.hcnt[R];
     const bool full = cnt0 >= cx.k;
     const uint64_t root = full ? L.hk[R] : 0ull;
-    const float sigma = full ? sigma_of(root) : 0.0f;
+    const BeatTest beats(full ? sigma_of(root) : 0.0f, Lr);
     uint32_t mask = 0;
     uint32_t pk[8];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const uint32_t col = acc_col(BI, r, H);
         const uint32_t I = (uint32_t)acc[r];
-        const bool ok = act & (col < cx.ncol) & (col != self) &
-                        (!full || may_beat(I, Lr + L.clen[col], sigma));
+        const bool ok = act & (col < cx.ncol) & (col != self) & beats(acc[r], L.clen[col]);
         mask |= (ok ? 1u : 0u) << r;
         if (r & 1) pk[r >> 1] |= I << 16;
         else pk[r >> 1] = I;

@@ -8,7 +8,9 @@ in fp32 around the hardware reciprocal; tests/jkey_check.c restates the two
 functions in C and compares them with exact integer arithmetic over every
 (I, U) the kernel can see (profiles below 2^15 items), with the reciprocal
 correctly rounded and 1 or 2 ulps off.  The order argument itself is checked
-here with exact integers.
+here with exact integers.  tests/filter_check.c does the same for the fp32
+test that turns candidates away before any key is computed: it must pass
+every candidate whose exact key reaches a full heap's root.
 """
 import os
 import subprocess
@@ -53,3 +55,30 @@ def test_key_order_is_jaccard_order():
         assert key(a, b) < key(c, d), (a, b, c, d)
     for a, b, f in [(1, 2, 32767), (3, 7, 9362), (65534, 65534, 1), (0, 5, 13107)]:
         assert key(a, b) == key(a * f, b * f)
+
+
+@pytest.fixture(scope="module")
+def filter_checker(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("filter") / "filter_check")
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off",
+                           os.path.join(HERE, "filter_check.c"), "-o", exe, "-lm"])
+    return exe
+
+
+def test_filter_never_turns_away_a_candidate_that_enters(filter_checker):
+    """The kernel's fp32 test against a full heap's root, with its margin
+    (1 - 1e-6) and the quotient sigma up to 2 ulps off, passes the smallest
+    intersection whose exact key reaches the root's, for 640 root keys, every
+    profile-length sum S below 2^16 and five splits of S."""
+    r = subprocess.run([filter_checker, "0.999999", "2", "1"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "turned away 0" in r.stdout
+
+
+@pytest.mark.parametrize("margin", ["1.0", "0.9999999"])
+def test_filter_check_sees_a_short_margin(filter_checker, margin):
+    """Without the margin, or with one ten times shorter, rounding turns away
+    candidates that would enter: the check above has something to find."""
+    r = subprocess.run([filter_checker, margin, "0", "1"], capture_output=True, text=True)
+    assert r.returncode == 1, r.stdout + r.stderr
+    assert "turned away 0" not in r.stdout
