@@ -724,19 +724,35 @@ struct KeyHeap {
 // Necessary condition for a candidate to beat the root: J > J_T implies
 // I > sigma_T * (|P_u| + |P_v|), sigma_T = J_T / (1 + J_T).  It is taken in
 // fp32 on the accumulator as I >= fma(s, |P_v|, s * |P_u|) with
-// s = sigma_T * (1 - 1e-6) fixed per row and round: the three roundings and
-// that of sigma_T stay far below the 1e-6 margin, so no candidate that can
-// beat the root is turned away.  An empty or filling heap has s = 0, and
-// every candidate passes.
+// s = sigma_T * (1 - 1e-6) fixed per row and round: the roundings of the
+// products and of sigma_T (a reciprocal within 1 ulp) stay far below the
+// 1e-6 margin, so no candidate that can beat the root is turned away.  An
+// empty or filling heap has s = 0, and every real column passes.  The same
+// comparison drops what is not a candidate: a padded column has length +inf
+// (fma gives +inf, or NaN when s = 0) and a row past the cluster's end has
+// s = NaN; a comparison with NaN is false.
 struct BeatTest {
     float s, sL;
-    C2_DEV BeatTest(float sigma, uint32_t Lr) : s(sigma * 0.999999f), sL(s * (float)Lr) {}
-    C2_DEV bool operator()(float I, uint32_t Lv) const { return I >= __builtin_fmaf(s, (float)Lv, sL); }
+    C2_DEV BeatTest(float sigma, uint32_t Lr, bool act)
+        : s(act ? sigma * 0.999999f : __builtin_nanf("")), sL(s * (float)Lr) {}
+    C2_DEV bool operator()(float I, float Lv) const { return I >= __builtin_fmaf(s, Lv, sL); }
 };
 
-C2_DEV float sigma_of(uint64_t root) {
-    const float kt = (float)(uint32_t)(root >> 32);
-    return kt / (4294967295.0f + kt);
+// sigma of the root's key kt: kt / (2^32 - 1 + kt), at most sigma_T since kt
+// is J_T * (2^32 - 1) rounded down.
+C2_DEV float sigma_of(uint32_t key) {
+    const float kt = (float)key;
+    return kt * __builtin_amdgcn_rcpf(4294967295.0f + kt);
+}
+// The key half of heap R's root (the high word of the u64 entry).
+C2_DEV uint32_t root_key(const uint64_t *hk, uint32_t R) {
+    return reinterpret_cast<const uint32_t *>(hk)[2 * R + 1];
+}
+// The bit of the accumulator position that holds column `self` in a lane
+// whose first column is c0 (columns c0 + 8 * (r / 4) + r % 4), or 0.
+C2_DEV uint32_t self_bit(uint32_t self, uint32_t c0) {
+    const uint32_t d = self - c0;
+    return d < 32 && !(d & 4) ? 1u << (4 * (d >> 3) + (d & 3)) : 0u;
 }
 
 struct MfmaScratch {
@@ -748,7 +764,8 @@ struct MfmaScratch {
 struct __attribute__((aligned(16))) WaveLds {
     uint64_t hk[kMaxK * kRows];  // heaps, [slot][row]
     uint32_t hcnt[kRows];        // entries per heap
-    uint32_t cuid[kCols], clen[kCols];
+    uint32_t cuid[kCols];
+    float clen[kCols];           // profile lengths, +inf past the last column
     uint32_t scr[64 * 8];        // 16 counts (u16) per lane
 };
 
@@ -802,7 +819,7 @@ C2_DEV void mult_group(const uint4 (&xa)[NC], const uint4 (&xb)[NR], v16f (&acc)
 
 // Per-tile selection state shared by the rounds of one lane.
 struct SelCtx {
-    uint32_t k, lane, lr, hh, ncol, rowpos;
+    uint32_t k, lane, lr, hh, rowpos;
 };
 
 // One selection round: the 16 candidates of accumulator block (BI, BJ) for the
@@ -819,18 +836,20 @@ C2_DEV void select_round(const v16f &acc, uint32_t Lr, bool act, const SelCtx &c
     const uint32_t self = cx.rowpos + 32 * BJ;
     const uint32_t cnt0 = L.hcnt[R];
     const bool full = cnt0 >= cx.k;
-    const BeatTest beats(full ? sigma_of(L.hk[R]) : 0.0f, Lr);
+    const BeatTest beats(full ? sigma_of(root_key(L.hk, R)) : 0.0f, Lr, act);
+    const uint32_t sbit = self_bit(self, 32 * BI + 4 * cx.hh);
     uint32_t mask = 0;
     uint32_t pk[8];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const uint32_t col = acc_col(BI, r, cx.hh);
         const uint32_t I = (uint32_t)acc[r];
-        const bool ok = act & (col < cx.ncol) & (col != self) & beats(acc[r], L.clen[col]);
+        const bool ok = beats(acc[r], L.clen[col]);
         mask |= (ok ? 1u : 0u) << r;
         if (r & 1) pk[r >> 1] |= I << 16;
         else pk[r >> 1] = I;
     }
+    mask &= ~sbit;
     if (!__any(mask != 0u)) return;
 #pragma unroll
     for (int q = 0; q < 8; ++q) L.scr[cx.lane * 8 + q] = pk[q];
@@ -852,7 +871,7 @@ C2_DEV void select_round(const v16f &acc, uint32_t Lr, bool act, const SelCtx &c
                 m &= m - 1;
                 const uint32_t I = (L.scr[cx.lane * 8 + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
                 const uint32_t col = acc_col(BI, r, cx.hh);
-                const uint32_t U = Lr + L.clen[col] - I, uid = L.cuid[col];
+                const uint32_t U = Lr + (uint32_t)L.clen[col] - I, uid = L.cuid[col];
                 const uint64_t v = ((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid);
                 h.insert(v);
             }
@@ -897,18 +916,20 @@ C2_DEV void select_own(const v16f &acc, uint32_t Lr, bool act, const SelCtx &cx,
     const uint32_t cnt0 = L.hcnt[R];
     const bool full = cnt0 >= cx.k;
     const uint64_t root = full ? L.hk[R] : 0ull;
-    const BeatTest beats(full ? sigma_of(root) : 0.0f, Lr);
+    const BeatTest beats(full ? sigma_of(root_key(L.hk, R)) : 0.0f, Lr, act);
+    const uint32_t sbit = self_bit(self, 32 * BI + 4 * H);
     uint32_t mask = 0;
     uint32_t pk[8];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const uint32_t col = acc_col(BI, r, H);
         const uint32_t I = (uint32_t)acc[r];
-        const bool ok = act & (col < cx.ncol) & (col != self) & beats(acc[r], L.clen[col]);
+        const bool ok = beats(acc[r], L.clen[col]);
         mask |= (ok ? 1u : 0u) << r;
         if (r & 1) pk[r >> 1] |= I << 16;
         else pk[r >> 1] = I;
     }
+    mask &= ~sbit;
     if (!__any(mask != 0u)) return;
 #pragma unroll
     for (int q = 0; q < 8; ++q) L.scr[cx.lane * 8 + q] = pk[q];
@@ -926,7 +947,7 @@ C2_DEV void select_own(const v16f &acc, uint32_t Lr, bool act, const SelCtx &cx,
             m &= m - 1;
             const uint32_t I = (L.scr[cx.lane * 8 + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
             const uint32_t col = acc_col(BI, r, H);
-            const uint32_t U = Lr + L.clen[col] - I, uid = L.cuid[col];
+            const uint32_t U = Lr + (uint32_t)L.clen[col] - I, uid = L.cuid[col];
             h.insert(((uint64_t)jkey(I, U) << 32) | (0xFFFFFFFFu - uid));
         }
     }
@@ -1005,7 +1026,7 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
             const uint32_t p = cb * TRC + q;
             const uint32_t u = p < s ? a.members[cv.o + p] : kPad;
             L.cuid[q] = u;
-            L.clen[q] = p < s ? ulen[u] : 0u;
+            L.clen[q] = p < s ? (float)ulen[u] : __builtin_inff();
         }
         __amdgpu_buffer_rsrc_t rA[NC];
 #pragma unroll
@@ -1037,7 +1058,6 @@ C2_DEV void mfma_item(const KnnArgs &a, const StoreView &sv, const uint32_t *ule
         cx.lane = lane;
         cx.lr = lr;
         cx.hh = hh;
-        cx.ncol = s - cb * TRC < TRC ? s - cb * TRC : TRC;
         cx.rowpos = rb * TRR + lr - cb * TRC;  // column of the lane's row member in block bj = 0
         if constexpr (NR == 2) {
             own_rows<NC>(acc);

@@ -7,14 +7,18 @@
  * that holds exactly when I * (2^32 - 1 + kt) >= kt * S, i.e. for every I at
  * or above I* = ceil(kt * S / (2^32 - 1 + kt)).  The kernel turns a candidate
  * away when, in fp32,
- *     sigma = kt / (2^32 - 1 + kt),  s = sigma * MARGIN,  sL = s * |P_u|,
- *     I < fma(s, |P_v|, sL).
- * The filter is safe if I* always passes (the test does not depend on I
- * otherwise, so every larger I passes too).  This program restates the
- * kernel's arithmetic in C, with the quotient sigma correctly rounded or off
- * by up to `ulps` ulps, and checks I* against it for a set of root keys, every
- * STRIDE-th S up to 65534 (profiles below 2^15 items) and several splits of S
- * into |P_u| + |P_v| with both at least I*.
+ *     sigma = kt * rcp(2^32 - 1 + kt),  s = sigma * MARGIN,  sL = s * |P_u|,
+ *     I < fma(s, |P_v|, sL)
+ * (rcp: the hardware reciprocal, within 1 ulp).  The filter is safe if I*
+ * always passes (the test does not depend on I otherwise, so every larger I
+ * passes too).  This program restates the kernel's arithmetic in C, with the
+ * reciprocal correctly rounded or off by up to `ulps` ulps (and, as a second
+ * form, the quotient sigma itself so rounded or off), and checks I* against it
+ * for a set of root keys, every STRIDE-th S up to 65534 (profiles below 2^15
+ * items) and several splits of S into |P_u| + |P_v| with both at least I*.
+ * It also checks the two exclusions the kernel folds into the same test: a
+ * padded column has |P_v| = +inf and an inactive row s = NaN, and both fail
+ * the comparison whatever s and I are.
  *
  * Usage: filter_check MARGIN ULPS STRIDE  (the kernel's margin is 0.999999;
  * prints the number of candidates wrongly turned away, exits 1 on any). */
@@ -63,13 +67,23 @@ int main(int argc, char **argv)
         if (k > 0) roots[nr++] = k;
     }
     unsigned long long bad = 0, checked = 0;
+    /* the exclusions: +inf length (padded column), NaN slope (inactive row) */
+    {
+        const float I_max = 65535.0f, svals[3] = {0.0f, 1e-9f, 0.5f};
+        for (int q = 0; q < 3; ++q) {
+            bad += I_max >= fmaf(svals[q], INFINITY, svals[q] * 100.0f);
+            bad += I_max >= fmaf(NAN, 100.0f, NAN * 100.0f);
+        }
+    }
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : bad, checked)
     for (int ri = 0; ri < nr; ++ri) {
         const uint32_t kt = roots[ri];
         const uint64_t den = 0xFFFFFFFFull + kt;
+        for (int form = 0; form < 2; ++form)
         for (int d = -ulps; d <= ulps; ++d) {
             const float ktf = (float)kt;
-            const float sigma = off_ulps(ktf / (4294967295.0f + ktf), d);
+            const float den_f = 4294967295.0f + ktf;
+            const float sigma = form ? ktf * off_ulps(1.0f / den_f, d) : off_ulps(ktf / den_f, d);
             const float s = sigma * margin;
             for (uint32_t S = 1; S <= smax; S += (uint32_t)stride) {
                 const uint64_t Istar = ((uint64_t)kt * S + den - 1) / den;

@@ -67,9 +67,10 @@ def filter_checker(tmp_path_factory):
 
 def test_filter_never_turns_away_a_candidate_that_enters(filter_checker):
     """The kernel's fp32 test against a full heap's root, with its margin
-    (1 - 1e-6) and the quotient sigma up to 2 ulps off, passes the smallest
-    intersection whose exact key reaches the root's, for 640 root keys, every
-    profile-length sum S below 2^16 and five splits of S."""
+    (1 - 1e-6) and sigma from a reciprocal (or a quotient) up to 2 ulps off,
+    passes the smallest intersection whose exact key reaches the root's, for
+    640 root keys, every profile-length sum S below 2^16 and five splits of S;
+    a padded column (+inf length) and an inactive row (NaN slope) fail it."""
     r = subprocess.run([filter_checker, "0.999999", "2", "1"], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "turned away 0" in r.stdout
