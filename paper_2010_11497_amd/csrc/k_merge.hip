@@ -48,6 +48,9 @@ C2_DEV uint64_t group_max(uint64_t b) {
 // One wave of 64 lanes serves 64/G users (one if G = 64): all 64 lanes copy
 // the users' t lists (contiguous in part_*) into LDS with U computed,
 // coalesced, in one pass of loads; the selection loop then runs from LDS.
+// I and U share one word there (8 bytes per entry with the id, so that enough
+// waves fit on a CU to hide the loads); a user with some U >= 2^16, which
+// needs the exact comparison anyway, reads its heads from global memory.
 // The profile lengths come from ulen when the caller has them (one gather per
 // entry), else from indptr.
 template <int G>
@@ -61,7 +64,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
                                                          uint32_t *__restrict__ knn_I,
                                                          uint32_t *__restrict__ knn_U) {
     constexpr int UPW = G <= kMergeThreads ? kMergeThreads / G : 1;  // users per wave
-    __shared__ uint32_t sv[UPW * G * kMaxK], sI[UPW * G * kMaxK], sU[UPW * G * kMaxK];
+    // per entry: the id, and I | U << 16 (exact when U < 2^16; a user with a
+    // larger U is flagged wide and reads its lists from global memory instead)
+    __shared__ uint32_t sv[UPW * G * kMaxK], sIU[UPW * G * kMaxK];
     const uint32_t lane = threadIdx.x;
     const uint64_t u0 = (uint64_t)blockIdx.x * UPW;
     // stage: entries of users u0 .. u0+UPW-1, list j, slot r at ((ul*G + j)*k + r).
@@ -123,8 +128,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
                 const bool ok = v[q] < n;
                 const uint32_t U = ulen_s[ul] + lv[q] - I[q];
                 sv[d] = ok ? v[q] : kPad;
-                sI[d] = ok ? I[q] : 0;
-                sU[d] = ok ? U : 0;
+                sIU[d] = ok ? I[q] | U << 16 : 0u;
                 if (ok && U >= 65536u) wide[ul] = 1;
             }
         }
@@ -139,11 +143,11 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
         hv = kPad;
         if (j < t && ptr < k) {
             hv = sv[lb + ptr];
-            hI = sI[lb + ptr];
-            hU = sU[lb + ptr];
+            const uint32_t iu = sIU[lb + ptr];
+            hI = iu & 0xFFFFu;
+            hU = iu >> 16;
         }
     };
-    load();
     uint32_t out = 0;
     uint32_t *oid = knn_id + u * k, *oI = knn_I + u * k, *oU = knn_U + u * k;
     if (!wide[ul]) {
@@ -155,6 +159,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
             return hv == kPad ? 0ull : ((uint64_t)jkey(hI, hU) << 32) | (0xFFFFFFFFu - hv);
         };
         const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1) << (ul * G);
+        load();
         uint64_t my = head_key();
         while (out < k) {
             const uint64_t best = group_max<G>(my);
@@ -173,6 +178,30 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
             }
         }
     } else {
+        // the head of list j from global memory, U from the profile lengths as
+        // in the staging above
+        const size_t gb = ((size_t)u * t + j) * k;
+        auto load_wide = [&]() {
+            hv = kPad;
+            if (j < t && ptr < k) {
+                const uint32_t v = part_id[gb + ptr];
+                if (v < n) {
+                    uint32_t lv;
+                    if (ulen) {
+                        lv = ulen[v];
+                    } else {
+                        const int64_t b0 = indptr[v], b1 = indptr[v + 1];
+                        const int64_t lo = b0 < 0 ? 0 : b0;
+                        const int64_t hi = b1 < (int64_t)nnz ? b1 : (int64_t)nnz;
+                        lv = hi > lo ? (uint32_t)(hi - lo) : 0u;
+                    }
+                    hv = v;
+                    hI = part_I[gb + ptr];
+                    hU = ulen_s[ul] + lv - hI;
+                }
+            }
+        };
+        load_wide();
         while (out < k) {
             // the group maximum of the heads (kPad: list exhausted), exact order
             bool ok = hv != kPad;
@@ -194,7 +223,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const int64_t *__restri
             ++out;
             if (hv == bv) {
                 ++ptr;
-                load();
+                load_wide();
             }
         }
     }
